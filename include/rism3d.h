@@ -1,0 +1,206 @@
+/*
+ * rism3d.h -- C ABI of the MI355X (gfx950) 3D-RISM solver library.
+ *
+ * The library solves the 3D-RISM equations of arXiv 2403.01039 for one solute
+ * in a multi-site solvent on a uniform 3D grid:
+ *   - Eq 13  h_g(r) = sum_g' c_g' * chi_g'g            (3D-RISM equation)
+ *   - Eq 14-16 closures (HNC, KH) plus PSE-n (Kast & Kloss 2008)
+ *   - Eq 22  solute-solvent LJ + Coulomb potential
+ *   - Eq 29-30 analytic long-range split, half-integer k grid
+ *   - Eq 31-33 and steps 1-7 of "Numerical procedure"
+ *   - Eq 40  MDIIS acceleration, Eq 41 RMS stopping rule
+ *   - Eq 17-18 solvation free energy.
+ *
+ * Units: Angstrom, kcal/mol, elementary charge, Kelvin.
+ *
+ * Memory model.  Every large buffer is caller-owned device memory (for example
+ * a torch tensor): the solute atoms, the solvent susceptibility table, the
+ * workspace and the output grids.  Per-site solvent parameters (at most
+ * RISM3D_MAX_SITES) are small host arrays read during the call.  The library
+ * allocates no device memory.  Calls are ordered on the given HIP stream;
+ * rism3d_solve and rism3d_thermo synchronise that stream to return their
+ * small host-side results (iteration info, free energies).
+ *
+ * Errors.  Every entry point returns a rism3d_status; nothing throws across the
+ * ABI.  rism3d_last_error() returns a thread-local message for the last
+ * failing call on the calling thread.
+ *
+ * Grid layout.  All grids are site-major, x fastest: index
+ *   ((site * nz + iz) * ny + iy) * nx + ix.
+ * Grid point (ix, iy, iz) sits at r = center + ((ix - nx/2), (iy - ny/2),
+ * (iz - nz/2)) * spacing (integer division), so the box centre is a grid
+ * point and the box spans [center - (n/2) spacing, center + (n - n/2) spacing).
+ */
+#ifndef RISM3D_H
+#define RISM3D_H
+
+#include <stddef.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RISM3D_MAX_SITES 8
+#define RISM3D_MAX_DEPTH 16
+
+typedef enum {
+  RISM3D_OK = 0,
+  RISM3D_E_ARG = 1,          /* invalid argument (sizes, pointers, options) */
+  RISM3D_E_DEVICE = 2,       /* a HIP call failed */
+  RISM3D_E_NOCONV = 3,       /* max_iter reached; info and outputs hold the last iterate */
+  RISM3D_E_NONFINITE = 4,    /* the residual became NaN/Inf */
+  RISM3D_E_WORKSPACE = 5     /* workspace too small or not prepared by rism3d_potential */
+} rism3d_status;
+
+typedef enum { RISM3D_KH = 0, RISM3D_HNC = 1, RISM3D_PSE = 2 } rism3d_closure;
+
+/* The problem statement (Eq 22 for the solute, Eq 13 for the solvent).
+ *
+ * Solute atoms (device pointers, float64): xyz[n_atoms][3] (A), q (e),
+ * sigma (A), eps (kcal/mol).  Lorentz-Berthelot mixing with the solvent sites.
+ *
+ * Solvent sites (host pointers, float64, n_sites <= RISM3D_MAX_SITES):
+ * site_q (e), site_sigma (A), site_eps (kcal/mol), site_rho (number density of
+ * the species the site belongs to, A^-3).
+ *
+ * chi (device pointer, float64): chi[(a * n_sites + b) * n_k + m] =
+ * chi_ab(m * dk), the solvent susceptibility w_ab + rho_a h_ab from a 1D RISM
+ * solvent calculation, on a uniform k grid (dk in A^-1).  The table must reach
+ * past the largest |k| of the grid: (n_k - 1) * dk >= |k|_max.
+ *
+ * Grid: nx, ny, nz points (each 2..512, with prime factors 2, 3 and 5 only),
+ * spacing in A, center in A.
+ */
+typedef struct {
+  int n_atoms;
+  const double* xyz;
+  const double* q;
+  const double* sigma;
+  const double* eps;
+  int n_sites;
+  const double* site_q;
+  const double* site_sigma;
+  const double* site_eps;
+  const double* site_rho;
+  int n_k;
+  double dk;
+  const double* chi;
+  double temperature;
+  int nx, ny, nz;
+  double spacing;
+  double center[3];
+} rism3d_problem;
+
+/* Solver options (Eq 40-41 and the closure choice).
+ * closure, pse_order (PSE-n order n >= 1; PSE-1 is KH), tol (RMS residual
+ * threshold, Eq 41; the paper's default is 1e-6), max_iter, mdiis_depth
+ * (1..RISM3D_MAX_DEPTH), mdiis_eta (damping of the MDIIS step, (0, 1]),
+ * eta_dynamic (non-zero: eta = clamp(-0.2 ln RMS, 0.1, 1.0) each step),
+ * check_every (host polls the device convergence flag every this many
+ * iterations; 0 picks a default), anchor_every (every this many iterations the
+ * residual is evaluated exactly in FP64 and the FP32 iterations in between
+ * transform only the increment from that anchor; 0 picks a default). */
+typedef struct {
+  rism3d_closure closure;
+  int pse_order;
+  double tol;
+  int max_iter;
+  int mdiis_depth;
+  double mdiis_eta;
+  int eta_dynamic;
+  int check_every;
+  int anchor_every;
+} rism3d_opts;
+
+typedef struct {
+  int iterations;       /* evaluations of the 3D-RISM map (steps 2-5) */
+  double rms;           /* RMS residual of the returned iterate */
+  int restarts;         /* MDIIS restarts */
+  int warm_start_used;  /* 1 if a caller tau0 was used */
+} rism3d_info;
+
+typedef struct {
+  double sfe;                         /* kcal/mol, Eq 17 / Eq 18 / PSE-n */
+  double sfe_site[RISM3D_MAX_SITES];  /* per-site contributions */
+} rism3d_thermo_out;
+
+/* Bytes of device workspace needed for this problem and options. Returns 0 on
+ * invalid arguments (see rism3d_last_error). */
+size_t rism3d_workspace_bytes(const rism3d_problem* problem, const rism3d_opts* opts);
+
+/* Eq 22 and Eq 29-30: fills the workspace with, per solvent site g,
+ *   w_g(r) = min(beta u_g(r), 1e4) - f_g(r)   (float32 [n_sites][nz][ny][nx]),
+ *   phi_lr(r) = sum_a q_a (1 - exp(-|r - R_a|)) / |r - R_a|   (f_g = beta C q_g phi_lr),
+ * the analytic long-range spectrum of Eq 30 on the half-integer k grid, the
+ * interpolation tables of chi and the FFT twiddles.  d_ws must be 256-byte
+ * aligned and hold rism3d_workspace_bytes(problem, opts) bytes (the options
+ * fix the MDIIS history size).  Must precede rism3d_solve on the same
+ * workspace. */
+rism3d_status rism3d_potential(const rism3d_problem* problem, const rism3d_opts* opts,
+                               void* d_ws, size_t ws_bytes, hipStream_t stream);
+
+/* Steps 1-7 of "Numerical procedure" with MDIIS.  d_tau0 (device, float32
+ * [n_sites][nz][ny][nx], may be NULL) is the starting short-range indirect
+ * correlation tau = t - f; NULL starts from t = f (tau = 0) as the paper does.
+ * On return d_g (device, float32 [n_sites][nz][ny][nx], may be NULL) holds
+ * g_g(r) of the returned iterate, and info (host, may be NULL) the iteration
+ * count, final RMS and restart count.  Returns RISM3D_E_NOCONV when max_iter
+ * is reached (outputs then hold the last iterate), RISM3D_E_NONFINITE on a
+ * NaN/Inf residual. */
+rism3d_status rism3d_solve(const rism3d_problem* problem, const rism3d_opts* opts,
+                           const float* d_tau0, void* d_ws, size_t ws_bytes, float* d_g,
+                           rism3d_info* info, hipStream_t stream);
+
+/* Eq 17 (HNC), Eq 18 (KH) and the PSE-n form: the solvation free energy of the
+ * iterate rism3d_solve returned, as k_B T sum_g rho_g dV sum_r Phi_g(r) with
+ * h = g - 1 and c = g - 1 - t, accumulated in float64.  Writes out (host). */
+rism3d_status rism3d_thermo(const rism3d_problem* problem, const rism3d_opts* opts,
+                            const void* d_ws, size_t ws_bytes, rism3d_thermo_out* out,
+                            hipStream_t stream);
+
+/* Copies tau = t - f of the returned iterate (float32 [n_sites][nz][ny][nx]) into
+ * d_tau (device); usable as d_tau0 of a later solve (resume / warm start). */
+rism3d_status rism3d_get_tau(const rism3d_problem* problem, const rism3d_opts* opts,
+                             const void* d_ws, size_t ws_bytes, float* d_tau,
+                             hipStream_t stream);
+
+/* One evaluation of the discretised 3D-RISM map (steps 2-5, Eq 31-33) at a given
+ * tau = t - f (device, float32 [n_sites][nz][ny][nx]): writes the residual
+ * R = t' - t = h + 1 - g (device, float32, same layout) and returns its RMS in
+ * *rms (host, may be NULL).  Uses the workspace prepared by rism3d_potential and
+ * overwrites any solution held there. */
+rism3d_status rism3d_map(const rism3d_problem* problem, const rism3d_opts* opts, const float* d_tau,
+                         void* d_ws, size_t ws_bytes, float* d_residual, double* rms,
+                         hipStream_t stream);
+
+/* Copies the fields rism3d_potential computed: w (float32 [n_sites][nz][ny][nx],
+ * may be NULL) and phi_lr (float32 [nz][ny][nx], may be NULL), device to device. */
+rism3d_status rism3d_get_potential(const rism3d_problem* problem, const rism3d_opts* opts,
+                                   const void* d_ws, size_t ws_bytes, float* d_w, float* d_phi,
+                                   hipStream_t stream);
+
+/* The half-integer-shifted 3D transform of section "Numerical procedure" on
+ * `count` complex grids d_data[count][nz][ny][nx] (device, float2 pairs, in
+ * place):  forward != 0:  X_j = sum_a x_a exp(-2 pi i (j + 1/2) . a / n);
+ * otherwise the unnormalised inverse  x_a = sum_j X_j exp(+2 pi i (j + 1/2) . a / n).
+ * d_ws: device scratch of at least rism3d_transform_workspace_bytes bytes
+ * (twiddle tables), 256-byte aligned. */
+size_t rism3d_transform_workspace_bytes(int nx, int ny, int nz);
+rism3d_status rism3d_transform(int nx, int ny, int nz, int count, void* d_data, int forward,
+                               void* d_ws, size_t ws_bytes, hipStream_t stream);
+
+/* Thread-local message describing the last error on this thread ("" if none). */
+const char* rism3d_last_error(void);
+
+/* The unit constants the library uses: Coulomb factor C (kcal A / (mol e^2)),
+ * Boltzmann constant (kcal / (mol K)), the Eq 29-30 screening length (A), the
+ * distance clamp (A) and the cap on beta*u.  Host only; no device access. */
+void rism3d_constants(double* coulomb, double* kboltz, double* screen, double* d_min,
+                      double* beta_u_cap);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RISM3D_H */

@@ -1,0 +1,531 @@
+// Kernels of the self-consistent iteration (steps 2-7 of "Numerical
+// procedure") in the tau-form: tau = t - f, w = min(beta u, cap) - f, so that
+//   d = -beta u + t = -w + tau   (Eq 16)
+//   c_sr = g - 1 - t + f = g - 1 - tau   (Eq 31)
+//   R = t' - t = h + 1 - g   (Eq 33)
+// MDIIS is affine invariant (sum c_i = 1), so iterating tau instead of t is
+// the same iteration shifted by the constant field f.
+//
+// Precision.  An FP32 FFT of c_sr has round-off ~1e-7 |c_sr|, and c_sr reaches
+// tens to hundreds inside the solute core, which puts a noise floor near the
+// rms 1e-6 stopping threshold.  The map is therefore evaluated as a defect
+// correction: every few iterations an FP64 "anchor" evaluation computes
+// R_ref = R(tau_ref) exactly (double2 transforms); the iterations in between
+// transform only the FP32 increment
+//   dc = [g(d_ref + delta) - g(d_ref)] - delta,   delta = tau - tau_ref,
+// (the analytic long-range term cancels in the difference) and form
+//   R = R_ref + dh - dg.
+// The increment is small wherever the iteration has converged, so its FP32
+// round-off is a small fraction of the current residual.
+#pragma once
+
+#include "common.hpp"
+
+namespace rism {
+
+constexpr int kElemThreads = 256;
+constexpr int kRedBlocks = 1024;    // fixed block count of the FP64 reductions
+constexpr int kRedThreads = 256;
+
+// ---------------------------------------------------------------------------
+// State initialisation (a kernel rather than a memset so it can sit in a graph)
+// ---------------------------------------------------------------------------
+__global__ void k_init_state(IterState* st, float eta, int warm) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int i = 0; i < kMaxDepth; ++i) {
+    st->stored[i] = 0;
+    st->stamp[i] = 0;
+    st->coef[i] = 0.0f;
+    st->rms_slot[i] = 0.0;
+    for (int j = 0; j < kMaxDepth; ++j) st->gram[i][j] = 0.0;
+  }
+  st->stamp_counter = 0;
+  st->dest = 0;
+  st->newest = 0;
+  st->iter = 0;
+  st->done = 0;
+  st->converged = 0;
+  st->status = RISM3D_OK;
+  st->restarts = 0;
+  st->final_slot = 0;
+  st->eta = eta;
+  st->warm = warm;
+  st->last_rms = 0.0;
+  st->last_rr = 0.0;
+}
+
+__global__ void k_mark_prepared(IterState* st) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st->prepared = kPreparedMagic;
+    st->done = 1;
+    st->final_slot = -1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Step 6 + step 2 fused: MDIIS update, in difference form about the newest
+// stored pair b (which keeps sum c_i = 1 exact in FP32):
+//   tau = tau_b + sum_i c_i (tau_i - tau_b) + eta sum_i c_i R_i,
+// stored in the destination slot; then the closure.  ANCHOR: c_sr = g - 1 - tau
+// in FP64 (double2 grid).  Otherwise the FP32 increment dc = dg - delta about
+// the anchor, with dg kept for the residual.  Two sites share one complex grid
+// (site 2p real part, site 2p+1 imaginary part).
+// ---------------------------------------------------------------------------
+template <bool ANCHOR>
+__global__ __launch_bounds__(kElemThreads) void k_update_closure(
+    const IterState* __restrict__ st, const float* __restrict__ tau0, float* __restrict__ tau_hist,
+    const float* __restrict__ res_hist, const float* __restrict__ w,
+    const float* __restrict__ tau_ref, float* __restrict__ dg_out, void* __restrict__ spec,
+    size_t N, int nv, int npair, int M, int kind, int order) {
+  if (st->done) return;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)npair * N) return;
+  const int p = (int)(idx / N);
+  const size_t n = idx - (size_t)p * N;
+  const bool first = st->iter == 0;
+  const int dest = st->dest;
+  const int b = st->newest;
+  const float eta = st->eta;
+  double o64[2] = {0.0, 0.0};
+  float o32[2] = {0.0f, 0.0f};
+  for (int s = 0; s < 2; ++s) {
+    const int g = 2 * p + s;
+    if (g >= nv) break;
+    float tau = 0.0f;
+    if (first) {
+      if (tau0) tau = tau0[(size_t)g * N + n];
+    } else {
+      const float tb = tau_hist[((size_t)b * nv + g) * N + n];
+      float dt = 0.0f, dr = 0.0f;
+      for (int i = 0; i < M; ++i) {
+        const float c = st->coef[i];
+        if (c != 0.0f) {
+          const size_t o = ((size_t)i * nv + g) * N + n;
+          dt += c * (tau_hist[o] - tb);
+          dr += c * res_hist[o];
+        }
+      }
+      tau = tb + (dt + eta * dr);
+    }
+    tau_hist[((size_t)dest * nv + g) * N + n] = tau;
+    const size_t gn = (size_t)g * N + n;
+    if (ANCHOR) {
+      const double d = -(double)w[gn] + (double)tau;
+      o64[s] = closure_g(d, kind, order) - 1.0 - (double)tau;
+    } else {
+      const float tr = tau_ref[gn];
+      const float delta = tau - tr;
+      const float dg = closure_dg(-w[gn] + tr, delta, kind, order);
+      dg_out[gn] = dg;
+      o32[s] = dg - delta;
+    }
+  }
+  if (ANCHOR) static_cast<double2*>(spec)[idx] = make_double2(o64[0], o64[1]);
+  else static_cast<float2*>(spec)[idx] = make_float2(o32[0], o32[1]);
+}
+
+// ---------------------------------------------------------------------------
+// Steps 3-4 in k-space: unpack each site pair, c~ = c~sr - f~ (Eq 32), the
+// 3D-RISM contraction h~_g = sum_g' c~_g' chi_g'g(|k|) (Eq 13), repack.
+// With f~_g = q_g F:  h~_g = sum_g' c~sr_g' chi_g'g - F Q_g,  Q_g = sum_g' q_g' chi_g'g.
+// The increments (WITHF = false) carry no long-range term.
+// Thread L handles the mirror pair (L, N-1-L): k_(N-1-L) = -k_L.
+// ---------------------------------------------------------------------------
+__device__ inline float kappa_f(int j, int n, float dk) {
+  return (2 * j < n) ? (j + 0.5f) * dk : (j + 0.5f - n) * dk;
+}
+
+template <int NV, typename C, bool WITHF>
+__global__ __launch_bounds__(kElemThreads) void k_contract(
+    C* __restrict__ spec, int nx, int ny, int nz, float dkx, float dky, float dkz,
+    const C* __restrict__ F, const typename ScalarOf<C>::type* __restrict__ chi,
+    const typename ScalarOf<C>::type* __restrict__ qtab, float inv_dkt, int m_tab,
+    const int* __restrict__ done) {
+  using S = typename ScalarOf<C>::type;
+  if (*done) return;
+  constexpr int NP = (NV + 1) / 2;
+  const size_t N = (size_t)nx * ny * nz;
+  const size_t half = (N + 1) / 2;
+  const size_t L = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (L >= half) return;
+  const size_t Lb = N - 1 - L;
+  const int jx = (int)(L % nx);
+  const int jy = (int)((L / nx) % ny);
+  const int jz = (int)(L / ((size_t)nx * ny));
+  const float kx = kappa_f(jx, nx, dkx), ky = kappa_f(jy, ny, dky), kz = kappa_f(jz, nz, dkz);
+  const float kmag = sqrtf(kx * kx + ky * ky + kz * kz);
+  const float x = kmag * inv_dkt;
+  int m;
+  S fr;
+  if (x >= (float)(m_tab - 1)) {
+    m = m_tab - 2;
+    fr = S(1);
+  } else {
+    m = (int)x;
+    fr = (S)(x - (float)m);
+  }
+  C X[NV];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const C z = spec[(size_t)p * N + L];
+    const C zb = spec[(size_t)p * N + Lb];
+    // A = (z + conj zb)/2,  B = (z - conj zb)/(2i)
+    X[2 * p] = make_c(S(0.5) * (z.x + zb.x), S(0.5) * (z.y - zb.y));
+    if (2 * p + 1 < NV) X[2 * p + 1] = make_c(S(0.5) * (z.y + zb.y), S(-0.5) * (z.x - zb.x));
+  }
+  C Fk = make_c(S(0), S(0));
+  if (WITHF) Fk = F[L];
+  const S* c0 = chi + (size_t)m * NV * NV;
+  const S* c1 = c0 + NV * NV;
+  C H[NV];
+#pragma unroll
+  for (int g = 0; g < NV; ++g) {
+    C acc = make_c(S(0), S(0));
+    if (WITHF) {
+      const S* q0 = qtab + (size_t)m * NV;
+      const S Q = q0[g] + fr * (q0[NV + g] - q0[g]);
+      acc = make_c(-Fk.x * Q, -Fk.y * Q);
+    }
+#pragma unroll
+    for (int gp = 0; gp < NV; ++gp) {
+      const S c = c0[gp * NV + g] + fr * (c1[gp * NV + g] - c0[gp * NV + g]);
+      acc.x += X[gp].x * c;
+      acc.y += X[gp].y * c;
+    }
+    H[g] = acc;
+  }
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const C a = H[2 * p];
+    const C bb = (2 * p + 1 < NV) ? H[2 * p + 1] : make_c(S(0), S(0));
+    // W(L) = A + iB;  W(Lb) = conj(A) + i conj(B)
+    spec[(size_t)p * N + L] = make_c(a.x - bb.y, a.y + bb.x);
+    spec[(size_t)p * N + Lb] = make_c(a.x + bb.y, -a.y + bb.x);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Step 5 and the MDIIS inner products.  ANCHOR: R = h + 1 - g (Eq 33) in FP64
+// from the double2 grid, which also becomes the new anchor (tau_ref, R_ref).
+// Otherwise R = R_ref + dh - dg.  R is stored in the destination slot and
+// <R, R_i> for every other stored slot and <R, R> are accumulated in FP64;
+// per-block partial sums are written in block order (reduced by k_control).
+// ---------------------------------------------------------------------------
+__device__ inline double block_sum(double v, double* lds) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) lds[wv] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += lds[i];
+  }
+  return s;
+}
+
+template <bool ANCHOR>
+__global__ __launch_bounds__(kRedThreads) void k_residual(
+    const IterState* __restrict__ st, const void* __restrict__ spec, const float* __restrict__ w,
+    const float* __restrict__ tau_hist, float* __restrict__ res_hist, float* __restrict__ tau_ref,
+    float* __restrict__ r_ref, const float* __restrict__ dg, size_t N, int nv, int npair, int M,
+    int kind, int order, double* __restrict__ partials) {
+  if (st->done) return;
+  __shared__ double red[kRedThreads / 64];
+  const int dest = st->dest;
+  unsigned mask = 0;
+  for (int i = 0; i < M; ++i)
+    if (st->stored[i] && i != dest) mask |= 1u << i;
+  double acc[kMaxDepth + 1];
+#pragma unroll
+  for (int i = 0; i <= kMaxDepth; ++i) acc[i] = 0.0;
+  const size_t total = (size_t)npair * N;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int p = (int)(idx / N);
+    const size_t n = idx - (size_t)p * N;
+    double2 h64 = make_double2(0.0, 0.0);
+    float2 h32 = make_float2(0.0f, 0.0f);
+    if (ANCHOR) h64 = static_cast<const double2*>(spec)[idx];
+    else h32 = static_cast<const float2*>(spec)[idx];
+    for (int s = 0; s < 2; ++s) {
+      const int g = 2 * p + s;
+      if (g >= nv) break;
+      const size_t gn = (size_t)g * N + n;
+      const size_t od = (size_t)dest * nv * N + gn;
+      float R;
+      if (ANCHOR) {
+        const float tau = tau_hist[od];
+        const double gg = closure_g(-(double)w[gn] + (double)tau, kind, order);
+        R = (float)((s ? h64.y : h64.x) + 1.0 - gg);
+        tau_ref[gn] = tau;
+        r_ref[gn] = R;
+      } else {
+        R = r_ref[gn] + ((s ? h32.y : h32.x) - dg[gn]);
+      }
+      res_hist[od] = R;
+      acc[kMaxDepth] += (double)R * (double)R;
+#pragma unroll
+      for (int i = 0; i < kMaxDepth; ++i) {
+        if (mask & (1u << i)) acc[i] += (double)R * (double)res_hist[(size_t)i * nv * N + gn];
+      }
+    }
+  }
+  for (int i = 0; i < M; ++i) {
+    const double s = block_sum(acc[i], red);
+    if (threadIdx.x == 0) partials[(size_t)blockIdx.x * (M + 1) + i] = s;
+  }
+  const double s = block_sum(acc[kMaxDepth], red);
+  if (threadIdx.x == 0) partials[(size_t)blockIdx.x * (M + 1) + M] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Step 6-7 control (one workgroup): reduce the partials in fixed order, RMS
+// (Eq 41 as a true root-mean-square), convergence / failure flags, the ring of
+// MDIIS pairs, the FP64 bordered Gram solve (Lagrange multiplier for
+// sum c_i = 1) with partial pivoting, restarts, the next coefficients.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kRedThreads) void k_control(
+    IterState* __restrict__ st, const double* __restrict__ partials, int nblocks, int M,
+    double inv_count, double tol, int max_iter, float eta_static, int eta_dynamic) {
+  if (st->done) return;
+  __shared__ double red[kRedThreads / 64];
+  __shared__ double sums[kMaxDepth + 1];
+  for (int q = 0; q <= M; ++q) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) v += partials[(size_t)b * (M + 1) + q];
+    const double s = block_sum(v, red);
+    if (threadIdx.x == 0) sums[q] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+
+  const int dest = st->dest;
+  const double rr = sums[M];
+  const double rms = sqrt(rr * inv_count);
+  st->iter += 1;
+  st->last_rms = rms;
+  st->last_rr = rr;
+  if (!(rr == rr) || rr > 1.0e300) {
+    st->status = RISM3D_E_NONFINITE;
+    st->final_slot = dest;
+    st->done = 1;
+    return;
+  }
+  if (rms < tol) {
+    st->converged = 1;
+    st->final_slot = dest;
+    st->done = 1;
+    return;
+  }
+  if (st->iter >= max_iter) {
+    st->status = RISM3D_E_NOCONV;
+    st->final_slot = dest;
+    st->done = 1;
+    return;
+  }
+  // The destination slot's old pair (the oldest, when the ring was full) has
+  // been overwritten by the new iterate: drop it.
+  st->stored[dest] = 0;
+  int best = -1;
+  double best_rms = 0.0;
+  for (int i = 0; i < M; ++i) {
+    if (st->stored[i] && (best < 0 || st->rms_slot[i] < best_rms)) {
+      best = i;
+      best_rms = st->rms_slot[i];
+    }
+  }
+  if (best >= 0 && rms > 10.0 * best_rms) {
+    for (int i = 0; i < M; ++i) st->stored[i] = (i == best);
+    st->newest = best;
+    st->restarts += 1;
+  } else {
+    st->stored[dest] = 1;
+    st->newest = dest;
+    st->rms_slot[dest] = rms;
+    st->stamp[dest] = ++st->stamp_counter;
+    for (int i = 0; i < M; ++i) {
+      if (st->stored[i] && i != dest) {
+        st->gram[dest][i] = sums[i];
+        st->gram[i][dest] = sums[i];
+      }
+    }
+    st->gram[dest][dest] = rr;
+  }
+  // Stored slots, oldest first.
+  int slot[kMaxDepth];
+  int m = 0;
+  for (int i = 0; i < M; ++i)
+    if (st->stored[i]) slot[m++] = i;
+  for (int a = 1; a < m; ++a) {
+    const int v = slot[a];
+    int b = a - 1;
+    while (b >= 0 && st->stamp[slot[b]] > st->stamp[v]) {
+      slot[b + 1] = slot[b];
+      --b;
+    }
+    slot[b + 1] = v;
+  }
+  double c[kMaxDepth];
+  bool ok = true;
+  if (m == 1) {
+    c[0] = 1.0;
+  } else {
+    double A[kMaxDepth + 1][kMaxDepth + 1];
+    double rhs[kMaxDepth + 1];
+    double scale = 0.0;
+    for (int i = 0; i < m; ++i) scale = fmax(scale, st->gram[slot[i]][slot[i]]);
+    const int n = m + 1;
+    for (int i = 0; i < m; ++i) {
+      for (int j = 0; j < m; ++j) A[i][j] = st->gram[slot[i]][slot[j]] / scale;
+      A[i][m] = -1.0;
+      A[m][i] = -1.0;
+      rhs[i] = 0.0;
+    }
+    A[m][m] = 0.0;
+    rhs[m] = -1.0;
+    double min_piv = 1.0e300;
+    for (int col = 0; col < n && ok; ++col) {
+      int piv = col;
+      for (int r = col + 1; r < n; ++r)
+        if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
+      if (piv != col) {
+        for (int j = 0; j < n; ++j) {
+          const double t = A[col][j];
+          A[col][j] = A[piv][j];
+          A[piv][j] = t;
+        }
+        const double t = rhs[col];
+        rhs[col] = rhs[piv];
+        rhs[piv] = t;
+      }
+      const double pv = A[col][col];
+      min_piv = fmin(min_piv, fabs(pv));
+      if (fabs(pv) < 1.0e-300) {
+        ok = false;
+        break;
+      }
+      for (int r = col + 1; r < n; ++r) {
+        const double f = A[r][col] / pv;
+        for (int j = col; j < n; ++j) A[r][j] -= f * A[col][j];
+        rhs[r] -= f * rhs[col];
+      }
+    }
+    if (ok && min_piv >= 1.0e-12) {
+      double sol[kMaxDepth + 1];
+      for (int r = n - 1; r >= 0; --r) {
+        double s = rhs[r];
+        for (int j = r + 1; j < n; ++j) s -= A[r][j] * sol[j];
+        sol[r] = s / A[r][r];
+      }
+      for (int i = 0; i < m; ++i) c[i] = sol[i];
+    } else {
+      ok = false;
+    }
+    if (!ok) {   // ill-conditioned subspace: restart from the best stored pair
+      int b = slot[0];
+      for (int i = 1; i < m; ++i)
+        if (st->rms_slot[slot[i]] < st->rms_slot[b]) b = slot[i];
+      for (int i = 0; i < M; ++i) st->stored[i] = (i == b);
+      st->newest = b;
+      slot[0] = b;
+      m = 1;
+      c[0] = 1.0;
+      st->restarts += 1;
+    }
+  }
+  for (int i = 0; i < M; ++i) st->coef[i] = 0.0f;
+  for (int i = 0; i < m; ++i) st->coef[slot[i]] = (float)c[i];
+  float eta = eta_static;
+  if (eta_dynamic) eta = (float)fmin(fmax(-0.2 * log(rms), 0.1), 1.0);
+  st->eta = eta;
+  // Next destination: a free slot while the ring is not full, else the oldest.
+  int next = -1;
+  if (m < M) {
+    for (int i = 0; i < M; ++i)
+      if (!st->stored[i]) {
+        next = i;
+        break;
+      }
+  } else {
+    next = slot[0];
+  }
+  st->dest = next;
+}
+
+// ---------------------------------------------------------------------------
+// Outputs: g of the accepted iterate, and tau itself.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kElemThreads) void k_output(
+    const IterState* __restrict__ st, const float* __restrict__ tau_hist,
+    const float* __restrict__ w, size_t N, int nv, int kind, int order, float* __restrict__ g_out,
+    float* __restrict__ tau_out) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)nv * N) return;
+  const int slot = st->final_slot;
+  if (slot < 0) return;
+  const float tau = tau_hist[(size_t)slot * nv * N + idx];
+  if (g_out) g_out[idx] = (float)closure_g(-(double)w[idx] + (double)tau, kind, order);
+  if (tau_out) tau_out[idx] = tau;
+}
+
+// ---------------------------------------------------------------------------
+// Eq 17 / 18 / PSE-n free-energy density, summed per site in FP64.
+//   h = g - 1,  c = g - 1 - t = g - 1 - tau - f,  d = -w + tau
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kRedThreads) void k_sfe_partial(
+    const IterState* __restrict__ st, const float* __restrict__ tau_hist,
+    const float* __restrict__ w, const float* __restrict__ phi_lr, size_t N, int nv, int kind,
+    int order, SiteConsts sc, double* __restrict__ partials) {
+  __shared__ double red[kRedThreads / 64];
+  const int slot = st->final_slot;
+  if (slot < 0) return;
+  double inv_fact = 1.0;
+  for (int i = 2; i <= order + 1; ++i) inv_fact /= (double)i;
+  for (int g = 0; g < nv; ++g) {
+    double acc = 0.0;
+    const float* tau = tau_hist + ((size_t)slot * nv + g) * N;
+    const float* wg = w + (size_t)g * N;
+    for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
+         n += (size_t)gridDim.x * blockDim.x) {
+      const double t = tau[n];
+      const double d = -(double)wg[n] + t;
+      const double gg = closure_g(d, kind, order);
+      const double h = gg - 1.0;
+      const double c = h - t - (double)sc.coul[g] * (double)phi_lr[n];
+      double phi = -c - 0.5 * h * c;
+      if (kind == RISM3D_HNC) phi += 0.5 * h * h;
+      else if (kind == RISM3D_KH) phi += (h < 0.0) ? 0.5 * h * h : 0.0;
+      else phi += 0.5 * h * h - ((h > 0.0) ? pow(d, (double)(order + 1)) * inv_fact : 0.0);
+      acc += phi;
+    }
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[(size_t)blockIdx.x * nv + g] = s;
+  }
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_sfe_reduce(const double* __restrict__ partials,
+                                                            int nblocks, int nv, double scale,
+                                                            SiteConsts sc, double* __restrict__ out) {
+  __shared__ double red[kRedThreads / 64];
+  double total = 0.0;
+  for (int g = 0; g < nv; ++g) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) v += partials[(size_t)b * nv + g];
+    const double s = block_sum(v, red);
+    if (threadIdx.x == 0) {
+      out[g] = s * sc.rho[g] * scale;
+      total += out[g];
+    }
+  }
+  if (threadIdx.x == 0) out[kMaxSites] = total;
+}
+
+// Copy of one history slot (the residual of a single map evaluation).
+__global__ void k_copy_floats(const float* __restrict__ src, float* __restrict__ dst, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+}  // namespace rism

@@ -1,0 +1,615 @@
+// C-ABI entry points of the gfx950 3D-RISM library (see include/rism3d.h).
+//
+// Host orchestration only: argument checks, the workspace layout, kernel
+// launches on the caller's stream and the once-per-chunk convergence poll.
+// Every step of the computation runs in the kernels of setup.hpp, fft.hpp and
+// iterate.hpp.
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "common.hpp"
+#include "fft.hpp"
+#include "iterate.hpp"
+#include "setup.hpp"
+
+using namespace rism;
+
+namespace {
+
+thread_local std::string g_error;
+
+rism3d_status fail(rism3d_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return fail(RISM3D_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));          \
+  } while (0)
+
+#define LAUNCH_CHECK()                                                                      \
+  do {                                                                                      \
+    hipError_t e_ = hipGetLastError();                                                      \
+    if (e_ != hipSuccess)                                                                   \
+      return fail(RISM3D_E_DEVICE, "kernel launch failed (%s:%d): %s", __FILE__, __LINE__, \
+                  hipGetErrorString(e_));                                                   \
+  } while (0)
+
+size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+bool plan_axis(int n, AxisPlan* p) {
+  if (n < 2 || n > kFftMaxN) return false;
+  p->n = n;
+  p->npass = 0;
+  int m = n;
+  const int radices[5] = {8, 4, 2, 3, 5};
+  for (int r : radices) {
+    while (m % r == 0) {
+      if (p->npass >= kMaxRadixPasses) return false;
+      p->radix[p->npass++] = r;
+      m /= r;
+    }
+  }
+  return m == 1;
+}
+
+double axis_kmax(int n, double dk) {
+  double km = 0.0;
+  for (int j = 0; j < n; ++j) {
+    const double k = (2 * j < n) ? (j + 0.5) * dk : (j + 0.5 - n) * dk;
+    km = fmax(km, fabs(k));
+  }
+  return km;
+}
+
+struct Layout {
+  int nx, ny, nz, nv, npair, M, n_atoms, m_tab;
+  size_t N, half;
+  double dkx, dky, dkz, beta, dv;
+  AxisPlan px, py, pz;
+  size_t off_state, off_w, off_phi, off_F, off_tau, off_res, off_tref, off_rref, off_dg, off_spec,
+      off_part, off_atoms, off_lj, off_ph, off_chi32, off_chi64, off_q64, off_tw32[3], off_tw64[3],
+      off_out, total;
+};
+
+constexpr int kDefaultCheckEvery = 8;
+constexpr int kDefaultAnchorEvery = 16;
+
+rism3d_status make_layout(const rism3d_problem* pr, const rism3d_opts* op, Layout* L) {
+  if (!pr || !op) return fail(RISM3D_E_ARG, "null problem or options");
+  if (pr->n_atoms < 0) return fail(RISM3D_E_ARG, "n_atoms < 0");
+  if (pr->n_atoms > 0 && (!pr->xyz || !pr->q || !pr->sigma || !pr->eps))
+    return fail(RISM3D_E_ARG, "null solute atom array");
+  if (pr->n_sites < 1 || pr->n_sites > kMaxSites)
+    return fail(RISM3D_E_ARG, "n_sites must be in 1..%d", kMaxSites);
+  if (!pr->site_q || !pr->site_sigma || !pr->site_eps || !pr->site_rho)
+    return fail(RISM3D_E_ARG, "null solvent site array");
+  for (int g = 0; g < pr->n_sites; ++g) {
+    if (!(pr->site_rho[g] > 0.0) || !(pr->site_sigma[g] >= 0.0) || !(pr->site_eps[g] >= 0.0))
+      return fail(RISM3D_E_ARG, "invalid parameters for solvent site %d", g);
+  }
+  if (pr->n_k < 2 || !(pr->dk > 0.0) || !pr->chi)
+    return fail(RISM3D_E_ARG, "invalid susceptibility table (n_k, dk, chi)");
+  if (!(pr->temperature > 0.0)) return fail(RISM3D_E_ARG, "temperature must be > 0");
+  if (!(pr->spacing > 0.0)) return fail(RISM3D_E_ARG, "spacing must be > 0");
+  if (!plan_axis(pr->nx, &L->px) || !plan_axis(pr->ny, &L->py) || !plan_axis(pr->nz, &L->pz))
+    return fail(RISM3D_E_ARG,
+                "grid %dx%dx%d unsupported: each axis must be 2..%d with prime factors 2, 3, 5",
+                pr->nx, pr->ny, pr->nz, kFftMaxN);
+  if (op->closure != RISM3D_KH && op->closure != RISM3D_HNC && op->closure != RISM3D_PSE)
+    return fail(RISM3D_E_ARG, "unknown closure %d", (int)op->closure);
+  if (op->closure == RISM3D_PSE && (op->pse_order < 1 || op->pse_order > 16))
+    return fail(RISM3D_E_ARG, "pse_order must be in 1..16");
+  if (!(op->tol > 0.0)) return fail(RISM3D_E_ARG, "tol must be > 0");
+  if (op->max_iter < 1) return fail(RISM3D_E_ARG, "max_iter must be >= 1");
+  if (op->mdiis_depth < 1 || op->mdiis_depth > kMaxDepth)
+    return fail(RISM3D_E_ARG, "mdiis_depth must be in 1..%d", kMaxDepth);
+  if (!(op->mdiis_eta > 0.0) || op->mdiis_eta > 2.0)
+    return fail(RISM3D_E_ARG, "mdiis_eta must be in (0, 2]");
+  if (op->check_every < 0 || op->anchor_every < 0)
+    return fail(RISM3D_E_ARG, "check_every and anchor_every must be >= 0");
+
+  L->nx = pr->nx;
+  L->ny = pr->ny;
+  L->nz = pr->nz;
+  L->nv = pr->n_sites;
+  L->npair = (pr->n_sites + 1) / 2;
+  L->M = op->mdiis_depth;
+  L->n_atoms = pr->n_atoms;
+  L->N = (size_t)pr->nx * pr->ny * pr->nz;
+  L->half = (L->N + 1) / 2;
+  const double two_pi = 6.283185307179586476925286766559;
+  L->dkx = two_pi / (pr->nx * pr->spacing);
+  L->dky = two_pi / (pr->ny * pr->spacing);
+  L->dkz = two_pi / (pr->nz * pr->spacing);
+  L->beta = 1.0 / (kBoltzmann * pr->temperature);
+  L->dv = pr->spacing * pr->spacing * pr->spacing;
+  const double kx = axis_kmax(pr->nx, L->dkx), ky = axis_kmax(pr->ny, L->dky),
+               kz = axis_kmax(pr->nz, L->dkz);
+  const double kmax = sqrt(kx * kx + ky * ky + kz * kz);
+  const double mmax = kmax / pr->dk;
+  if (mmax > (double)(pr->n_k - 1))
+    return fail(RISM3D_E_ARG, "susceptibility table ends at k=%g but the grid reaches |k|=%g",
+                (pr->n_k - 1) * pr->dk, kmax);
+  L->m_tab = (int)fmin((double)pr->n_k, floor(mmax) + 3.0);
+  if (L->m_tab < 2) L->m_tab = 2;
+
+  const size_t nv = L->nv, N = L->N, M = L->M;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  L->off_state = take(sizeof(IterState));
+  L->off_w = take(nv * N * sizeof(float));
+  L->off_phi = take(N * sizeof(float));
+  L->off_F = take(L->half * sizeof(double2));
+  L->off_tau = take(M * nv * N * sizeof(float));
+  L->off_res = take(M * nv * N * sizeof(float));
+  L->off_tref = take(nv * N * sizeof(float));
+  L->off_rref = take(nv * N * sizeof(float));
+  L->off_dg = take(nv * N * sizeof(float));
+  L->off_spec = take((size_t)L->npair * N * sizeof(double2));   // float2 in the bulk iterations
+  const size_t part_q = (size_t)((M + 1) > nv ? (M + 1) : nv);
+  L->off_part = take((size_t)kRedBlocks * part_q * sizeof(double));
+  const size_t na = pr->n_atoms > 0 ? (size_t)pr->n_atoms : 1;
+  L->off_atoms = take(na * sizeof(double4));
+  L->off_lj = take(na * nv * sizeof(double2));
+  L->off_ph = take(na * (size_t)(pr->nx + pr->ny + pr->nz) * sizeof(double2));
+  L->off_chi32 = take((size_t)L->m_tab * nv * nv * sizeof(float));
+  L->off_chi64 = take((size_t)L->m_tab * nv * nv * sizeof(double));
+  L->off_q64 = take((size_t)L->m_tab * nv * sizeof(double));
+  const int dims[3] = {pr->nx, pr->ny, pr->nz};
+  for (int a = 0; a < 3; ++a) {
+    L->off_tw32[a] = take(2 * (size_t)dims[a] * sizeof(float2));
+    L->off_tw64[a] = take(2 * (size_t)dims[a] * sizeof(double2));
+  }
+  L->off_out = take((kMaxSites + 1) * sizeof(double));
+  L->total = off;
+  return RISM3D_OK;
+}
+
+rism3d_status check_ws(const Layout& L, const void* ws, size_t bytes) {
+  if (!ws) return fail(RISM3D_E_WORKSPACE, "null workspace");
+  if (((uintptr_t)ws) & 255) return fail(RISM3D_E_WORKSPACE, "workspace must be 256-byte aligned");
+  if (bytes < L.total)
+    return fail(RISM3D_E_WORKSPACE, "workspace holds %zu bytes, %zu needed", bytes, L.total);
+  return RISM3D_OK;
+}
+
+template <typename T>
+T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+template <typename T>
+const T* at(const void* ws, size_t off) {
+  return reinterpret_cast<const T*>(static_cast<const char*>(ws) + off);
+}
+
+SiteConsts site_consts(const rism3d_problem* pr, double beta) {
+  SiteConsts sc;
+  memset(&sc, 0, sizeof(sc));
+  sc.nv = pr->n_sites;
+  for (int g = 0; g < pr->n_sites; ++g) {
+    sc.coul[g] = (float)(beta * kCoulomb * pr->site_q[g]);
+    sc.coul64[g] = beta * kCoulomb * pr->site_q[g];
+    sc.q64[g] = pr->site_q[g];
+    sc.rho[g] = pr->site_rho[g];
+  }
+  return sc;
+}
+
+unsigned blocks_for(size_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
+
+template <int NV>
+void launch_potential_nv(const Layout& L, void* ws, double dr, const SiteConsts& sc,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_potential<NV>, dim3(blocks_for(L.N, kPotThreads)), dim3(kPotThreads), 0, s,
+                     at<double4>(ws, L.off_atoms), at<double2>(ws, L.off_lj), L.n_atoms, L.nx, L.ny,
+                     L.nz, dr, sc, at<float>(ws, L.off_w), at<float>(ws, L.off_phi));
+}
+
+void launch_potential(const Layout& L, void* ws, double dr, const SiteConsts& sc, hipStream_t s) {
+  switch (L.nv) {
+    case 1: launch_potential_nv<1>(L, ws, dr, sc, s); break;
+    case 2: launch_potential_nv<2>(L, ws, dr, sc, s); break;
+    case 3: launch_potential_nv<3>(L, ws, dr, sc, s); break;
+    case 4: launch_potential_nv<4>(L, ws, dr, sc, s); break;
+    case 5: launch_potential_nv<5>(L, ws, dr, sc, s); break;
+    case 6: launch_potential_nv<6>(L, ws, dr, sc, s); break;
+    case 7: launch_potential_nv<7>(L, ws, dr, sc, s); break;
+    default: launch_potential_nv<8>(L, ws, dr, sc, s); break;
+  }
+}
+
+template <int NV>
+void launch_contract_nv(const Layout& L, void* ws, bool anchor, float inv_dkt, const int* done,
+                        hipStream_t s) {
+  const dim3 grid(blocks_for(L.half, kElemThreads)), block(kElemThreads);
+  if (anchor)
+    hipLaunchKernelGGL((k_contract<NV, double2, true>), grid, block, 0, s,
+                       at<double2>(ws, L.off_spec), L.nx, L.ny, L.nz, (float)L.dkx, (float)L.dky,
+                       (float)L.dkz, at<double2>(ws, L.off_F), at<double>(ws, L.off_chi64),
+                       at<double>(ws, L.off_q64), inv_dkt, L.m_tab, done);
+  else
+    hipLaunchKernelGGL((k_contract<NV, float2, false>), grid, block, 0, s,
+                       at<float2>(ws, L.off_spec), L.nx, L.ny, L.nz, (float)L.dkx, (float)L.dky,
+                       (float)L.dkz, (const float2*)nullptr, at<float>(ws, L.off_chi32),
+                       (const float*)nullptr, inv_dkt, L.m_tab, done);
+}
+
+void launch_contract(const Layout& L, void* ws, bool anchor, float inv_dkt, const int* done,
+                     hipStream_t s) {
+  switch (L.nv) {
+    case 1: launch_contract_nv<1>(L, ws, anchor, inv_dkt, done, s); break;
+    case 2: launch_contract_nv<2>(L, ws, anchor, inv_dkt, done, s); break;
+    case 3: launch_contract_nv<3>(L, ws, anchor, inv_dkt, done, s); break;
+    case 4: launch_contract_nv<4>(L, ws, anchor, inv_dkt, done, s); break;
+    case 5: launch_contract_nv<5>(L, ws, anchor, inv_dkt, done, s); break;
+    case 6: launch_contract_nv<6>(L, ws, anchor, inv_dkt, done, s); break;
+    case 7: launch_contract_nv<7>(L, ws, anchor, inv_dkt, done, s); break;
+    default: launch_contract_nv<8>(L, ws, anchor, inv_dkt, done, s); break;
+  }
+}
+
+// Forward (forward != 0) or inverse 3D transform of all packed pairs, one
+// kernel per axis; C = float2 (bulk) or double2 (anchor).
+template <typename C>
+void launch_fft3_on(const Layout& L, C* spec, const C* const tw[3], int forward, const int* done,
+                    hipStream_t s) {
+  const int axes_fwd[3] = {0, 1, 2};
+  const int axes_inv[3] = {2, 1, 0};
+  for (int k = 0; k < 3; ++k) {
+    const int axis = forward ? axes_fwd[k] : axes_inv[k];
+    const AxisPlan& p = axis == 0 ? L.px : (axis == 1 ? L.py : L.pz);
+    const int lines = fft_lines_per_block<C>(axis, p.n, L.nx);
+    unsigned grid;
+    if (axis == 0) {
+      const size_t rows = (size_t)L.npair * L.nz * L.ny;
+      grid = (unsigned)((rows + lines - 1) / lines);
+    } else {
+      const int tiles_x = (L.nx + lines - 1) / lines;
+      const int outer = axis == 1 ? L.npair * L.nz : L.npair * L.ny;
+      grid = (unsigned)outer * tiles_x;
+    }
+    hipLaunchKernelGGL(k_fft_axis<C>, dim3(grid), dim3(kFftThreads), 0, s, spec, L.nx, L.ny,
+                       L.nz, L.npair, axis, p, tw[axis], forward, lines, done);
+  }
+}
+
+template <typename C>
+void launch_fft3(const Layout& L, void* ws, int forward, const int* done, hipStream_t s);
+
+template <>
+void launch_fft3<float2>(const Layout& L, void* ws, int forward, const int* done, hipStream_t s) {
+  const float2* tw[3] = {at<float2>(ws, L.off_tw32[0]), at<float2>(ws, L.off_tw32[1]),
+                         at<float2>(ws, L.off_tw32[2])};
+  launch_fft3_on(L, at<float2>(ws, L.off_spec), tw, forward, done, s);
+}
+
+template <>
+void launch_fft3<double2>(const Layout& L, void* ws, int forward, const int* done, hipStream_t s) {
+  const double2* tw[3] = {at<double2>(ws, L.off_tw64[0]), at<double2>(ws, L.off_tw64[1]),
+                          at<double2>(ws, L.off_tw64[2])};
+  launch_fft3_on(L, at<double2>(ws, L.off_spec), tw, forward, done, s);
+}
+
+// One evaluation of the 3D-RISM map plus the MDIIS bookkeeping: update +
+// closure, forward FFT, contraction, inverse FFT, residual + Gram row, control.
+// anchor: FP64 evaluation that re-bases the FP32 increments.
+void launch_iteration(const Layout& L, void* ws, const rism3d_opts* op, const float* tau0,
+                      float inv_dkt, bool anchor, hipStream_t s) {
+  IterState* st = at<IterState>(ws, L.off_state);
+  const int* done = &st->done;
+  const int kind = (int)op->closure;
+  const int order = op->closure == RISM3D_PSE ? op->pse_order : 1;
+  const dim3 eg(blocks_for((size_t)L.npair * L.N, kElemThreads)), eb(kElemThreads);
+  if (anchor)
+    hipLaunchKernelGGL(k_update_closure<true>, eg, eb, 0, s, st, tau0, at<float>(ws, L.off_tau),
+                       at<float>(ws, L.off_res), at<float>(ws, L.off_w),
+                       at<float>(ws, L.off_tref), at<float>(ws, L.off_dg),
+                       at<void>(ws, L.off_spec), L.N, L.nv, L.npair, L.M, kind, order);
+  else
+    hipLaunchKernelGGL(k_update_closure<false>, eg, eb, 0, s, st, tau0, at<float>(ws, L.off_tau),
+                       at<float>(ws, L.off_res), at<float>(ws, L.off_w),
+                       at<float>(ws, L.off_tref), at<float>(ws, L.off_dg),
+                       at<void>(ws, L.off_spec), L.N, L.nv, L.npair, L.M, kind, order);
+  if (anchor) launch_fft3<double2>(L, ws, 1, done, s);
+  else launch_fft3<float2>(L, ws, 1, done, s);
+  launch_contract(L, ws, anchor, inv_dkt, done, s);
+  if (anchor) launch_fft3<double2>(L, ws, 0, done, s);
+  else launch_fft3<float2>(L, ws, 0, done, s);
+  const size_t work = (size_t)L.npair * L.N;
+  unsigned nblk = blocks_for(work, kRedThreads);
+  if (nblk > (unsigned)kRedBlocks) nblk = kRedBlocks;
+  if (anchor)
+    hipLaunchKernelGGL(k_residual<true>, dim3(nblk), dim3(kRedThreads), 0, s, st,
+                       at<void>(ws, L.off_spec), at<float>(ws, L.off_w), at<float>(ws, L.off_tau),
+                       at<float>(ws, L.off_res), at<float>(ws, L.off_tref),
+                       at<float>(ws, L.off_rref), at<float>(ws, L.off_dg), L.N, L.nv, L.npair,
+                       L.M, kind, order, at<double>(ws, L.off_part));
+  else
+    hipLaunchKernelGGL(k_residual<false>, dim3(nblk), dim3(kRedThreads), 0, s, st,
+                       at<void>(ws, L.off_spec), at<float>(ws, L.off_w), at<float>(ws, L.off_tau),
+                       at<float>(ws, L.off_res), at<float>(ws, L.off_tref),
+                       at<float>(ws, L.off_rref), at<float>(ws, L.off_dg), L.N, L.nv, L.npair,
+                       L.M, kind, order, at<double>(ws, L.off_part));
+  const double inv_count = 1.0 / ((double)L.N * (double)L.nv);
+  hipLaunchKernelGGL(k_control, dim3(1), dim3(kRedThreads), 0, s, st, at<double>(ws, L.off_part),
+                     (int)nblk, L.M, inv_count, op->tol, op->max_iter, (float)op->mdiis_eta,
+                     op->eta_dynamic);
+}
+
+int order_of(const rism3d_opts* op) { return op->closure == RISM3D_PSE ? op->pse_order : 1; }
+
+}  // namespace
+
+extern "C" {
+
+size_t rism3d_workspace_bytes(const rism3d_problem* problem, const rism3d_opts* opts) {
+  Layout L;
+  if (make_layout(problem, opts, &L) != RISM3D_OK) return 0;
+  return L.total;
+}
+
+rism3d_status rism3d_potential(const rism3d_problem* pr, const rism3d_opts* op, void* ws,
+                               size_t ws_bytes, hipStream_t s) {
+  Layout L;
+  rism3d_status st = make_layout(pr, op, &L);
+  if (st != RISM3D_OK) return st;
+  if ((st = check_ws(L, ws, ws_bytes)) != RISM3D_OK) return st;
+  const double r0x = pr->center[0] - (pr->nx / 2) * pr->spacing;
+  const double r0y = pr->center[1] - (pr->ny / 2) * pr->spacing;
+  const double r0z = pr->center[2] - (pr->nz / 2) * pr->spacing;
+  const SiteConsts sc = site_consts(pr, L.beta);
+  SiteLJ sl;
+  memset(&sl, 0, sizeof(sl));
+  for (int g = 0; g < pr->n_sites; ++g) {
+    sl.sigma[g] = pr->site_sigma[g];
+    sl.eps[g] = pr->site_eps[g];
+  }
+  if (L.n_atoms > 0) {
+    hipLaunchKernelGGL(k_prep_atoms, dim3(blocks_for(L.n_atoms, 256)), dim3(256), 0, s, pr->xyz,
+                       pr->q, pr->sigma, pr->eps, L.n_atoms, r0x, r0y, r0z, L.beta, L.nv, sl,
+                       at<double4>(ws, L.off_atoms), at<double2>(ws, L.off_lj));
+    LAUNCH_CHECK();
+    const int nsum = L.nx + L.ny + L.nz;
+    hipLaunchKernelGGL(k_phase_tables, dim3(blocks_for((size_t)L.n_atoms * nsum, 256)), dim3(256),
+                       0, s, pr->xyz, L.n_atoms, L.nx, L.ny, L.nz, r0x, r0y, r0z, L.dkx, L.dky,
+                       L.dkz, at<double2>(ws, L.off_ph));
+    LAUNCH_CHECK();
+  }
+  launch_potential(L, ws, pr->spacing, sc, s);
+  LAUNCH_CHECK();
+  const double pref = 4.0 * M_PI * L.beta * kCoulomb / (kScreen * kScreen) / L.dv;
+  hipLaunchKernelGGL(k_ftilde, dim3(blocks_for(L.half, 256)), dim3(256), 0, s,
+                     at<double2>(ws, L.off_ph), at<double4>(ws, L.off_atoms), L.n_atoms, L.nx, L.ny,
+                     L.nz, L.dkx, L.dky, L.dkz, pref, at<double2>(ws, L.off_F));
+  LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_chi_tables, dim3(blocks_for((size_t)L.m_tab * L.nv, 256)), dim3(256), 0, s,
+                     pr->chi, L.nv, pr->n_k, L.m_tab, 1.0 / (double)L.N, sc,
+                     at<float>(ws, L.off_chi32), at<double>(ws, L.off_chi64),
+                     at<double>(ws, L.off_q64));
+  LAUNCH_CHECK();
+  const int dims[3] = {L.nx, L.ny, L.nz};
+  for (int a = 0; a < 3; ++a)
+    hipLaunchKernelGGL(k_twiddles, dim3(blocks_for(2 * dims[a], 256)), dim3(256), 0, s, dims[a],
+                       at<float2>(ws, L.off_tw32[a]), at<double2>(ws, L.off_tw64[a]));
+  hipLaunchKernelGGL(k_mark_prepared, dim3(1), dim3(1), 0, s, at<IterState>(ws, L.off_state));
+  LAUNCH_CHECK();
+  return RISM3D_OK;
+}
+
+rism3d_status rism3d_solve(const rism3d_problem* pr, const rism3d_opts* op, const float* tau0,
+                           void* ws, size_t ws_bytes, float* g_out, rism3d_info* info,
+                           hipStream_t s) {
+  Layout L;
+  rism3d_status st = make_layout(pr, op, &L);
+  if (st != RISM3D_OK) return st;
+  if ((st = check_ws(L, ws, ws_bytes)) != RISM3D_OK) return st;
+  IterState* dst = at<IterState>(ws, L.off_state);
+  IterState host;
+  HIP_TRY(hipMemcpyAsync(&host, dst, sizeof(IterState), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (host.prepared != kPreparedMagic)
+    return fail(RISM3D_E_WORKSPACE, "workspace not prepared: call rism3d_potential first");
+  hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1), 0, s, dst, (float)op->mdiis_eta,
+                     tau0 ? 1 : 0);
+  LAUNCH_CHECK();
+  const float inv_dkt = (float)(1.0 / pr->dk);
+  const int chunk = op->check_every > 0 ? op->check_every : kDefaultCheckEvery;
+  const int every = op->anchor_every > 0 ? op->anchor_every : kDefaultAnchorEvery;
+  int launched = 0;
+  for (;;) {
+    const int todo = (op->max_iter - launched) < chunk ? (op->max_iter - launched) : chunk;
+    for (int k = 0; k < todo; ++k)
+      launch_iteration(L, ws, op, tau0, inv_dkt, ((launched + k) % every) == 0, s);
+    LAUNCH_CHECK();
+    launched += todo;
+    HIP_TRY(hipMemcpyAsync(&host, dst, sizeof(IterState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (host.done || launched >= op->max_iter) break;
+  }
+  if (g_out) {
+    hipLaunchKernelGGL(k_output, dim3(blocks_for((size_t)L.nv * L.N, kElemThreads)),
+                       dim3(kElemThreads), 0, s, dst, at<float>(ws, L.off_tau),
+                       at<float>(ws, L.off_w), L.N, L.nv, (int)op->closure, order_of(op), g_out,
+                       (float*)nullptr);
+    LAUNCH_CHECK();
+  }
+  if (info) {
+    info->iterations = host.iter;
+    info->rms = host.last_rms;
+    info->restarts = host.restarts;
+    info->warm_start_used = host.warm;
+  }
+  if (!host.done) return fail(RISM3D_E_NOCONV, "no convergence in %d iterations", host.iter);
+  if (host.status == RISM3D_E_NONFINITE)
+    return fail(RISM3D_E_NONFINITE, "non-finite residual at iteration %d", host.iter);
+  if (host.status == RISM3D_E_NOCONV)
+    return fail(RISM3D_E_NOCONV, "rms %g above tol %g after %d iterations", host.last_rms,
+                op->tol, host.iter);
+  g_error.clear();
+  return RISM3D_OK;
+}
+
+rism3d_status rism3d_thermo(const rism3d_problem* pr, const rism3d_opts* op, const void* ws_c,
+                            size_t ws_bytes, rism3d_thermo_out* out, hipStream_t s) {
+  Layout L;
+  rism3d_status st = make_layout(pr, op, &L);
+  if (st != RISM3D_OK) return st;
+  if ((st = check_ws(L, ws_c, ws_bytes)) != RISM3D_OK) return st;
+  if (!out) return fail(RISM3D_E_ARG, "null output");
+  void* ws = const_cast<void*>(ws_c);
+  IterState* dst = at<IterState>(ws, L.off_state);
+  IterState host;
+  HIP_TRY(hipMemcpyAsync(&host, dst, sizeof(IterState), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (host.prepared != kPreparedMagic || host.final_slot < 0)
+    return fail(RISM3D_E_WORKSPACE, "no solution in the workspace: call rism3d_solve first");
+  const SiteConsts sc = site_consts(pr, L.beta);
+  unsigned nblk = blocks_for(L.N, kRedThreads);
+  if (nblk > (unsigned)kRedBlocks) nblk = kRedBlocks;
+  hipLaunchKernelGGL(k_sfe_partial, dim3(nblk), dim3(kRedThreads), 0, s, dst,
+                     at<float>(ws, L.off_tau), at<float>(ws, L.off_w), at<float>(ws, L.off_phi),
+                     L.N, L.nv, (int)op->closure, order_of(op), sc, at<double>(ws, L.off_part));
+  const double scale = L.dv / L.beta;   // k_B T dV
+  hipLaunchKernelGGL(k_sfe_reduce, dim3(1), dim3(kRedThreads), 0, s, at<double>(ws, L.off_part),
+                     (int)nblk, L.nv, scale, sc, at<double>(ws, L.off_out));
+  LAUNCH_CHECK();
+  double res[kMaxSites + 1];
+  HIP_TRY(hipMemcpyAsync(res, at<double>(ws, L.off_out), sizeof(res), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  memset(out, 0, sizeof(*out));
+  out->sfe = res[kMaxSites];
+  for (int g = 0; g < L.nv; ++g) out->sfe_site[g] = res[g];
+  g_error.clear();
+  return RISM3D_OK;
+}
+
+rism3d_status rism3d_get_tau(const rism3d_problem* pr, const rism3d_opts* op, const void* ws_c,
+                             size_t ws_bytes, float* d_tau, hipStream_t s) {
+  Layout L;
+  rism3d_status st = make_layout(pr, op, &L);
+  if (st != RISM3D_OK) return st;
+  if ((st = check_ws(L, ws_c, ws_bytes)) != RISM3D_OK) return st;
+  if (!d_tau) return fail(RISM3D_E_ARG, "null output");
+  void* ws = const_cast<void*>(ws_c);
+  hipLaunchKernelGGL(k_output, dim3(blocks_for((size_t)L.nv * L.N, kElemThreads)),
+                     dim3(kElemThreads), 0, s, at<IterState>(ws, L.off_state),
+                     at<float>(ws, L.off_tau), at<float>(ws, L.off_w), L.N, L.nv,
+                     (int)op->closure, order_of(op), (float*)nullptr, d_tau);
+  LAUNCH_CHECK();
+  return RISM3D_OK;
+}
+
+rism3d_status rism3d_map(const rism3d_problem* pr, const rism3d_opts* op, const float* d_tau,
+                         void* ws, size_t ws_bytes, float* d_res, double* rms, hipStream_t s) {
+  Layout L;
+  rism3d_status st = make_layout(pr, op, &L);
+  if (st != RISM3D_OK) return st;
+  if ((st = check_ws(L, ws, ws_bytes)) != RISM3D_OK) return st;
+  if (!d_tau || !d_res) return fail(RISM3D_E_ARG, "null tau or residual");
+  IterState* dst = at<IterState>(ws, L.off_state);
+  IterState host;
+  HIP_TRY(hipMemcpyAsync(&host, dst, sizeof(IterState), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (host.prepared != kPreparedMagic)
+    return fail(RISM3D_E_WORKSPACE, "workspace not prepared: call rism3d_potential first");
+  rism3d_opts one = *op;
+  one.max_iter = 1;
+  one.tol = 0.0;   // never "converged": the single evaluation always runs to the end
+  hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1), 0, s, dst, (float)op->mdiis_eta, 1);
+  launch_iteration(L, ws, &one, d_tau, (float)(1.0 / pr->dk), true, s);
+  const size_t n = (size_t)L.nv * L.N;
+  hipLaunchKernelGGL(k_copy_floats, dim3(blocks_for(n, kElemThreads)), dim3(kElemThreads), 0, s,
+                     at<float>(ws, L.off_res), d_res, n);   // slot 0 holds R
+  LAUNCH_CHECK();
+  HIP_TRY(hipMemcpyAsync(&host, dst, sizeof(IterState), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (rms) *rms = host.last_rms;
+  g_error.clear();
+  return RISM3D_OK;
+}
+
+rism3d_status rism3d_get_potential(const rism3d_problem* pr, const rism3d_opts* op,
+                                   const void* ws_c, size_t ws_bytes, float* d_w, float* d_phi,
+                                   hipStream_t s) {
+  Layout L;
+  rism3d_status st = make_layout(pr, op, &L);
+  if (st != RISM3D_OK) return st;
+  if ((st = check_ws(L, ws_c, ws_bytes)) != RISM3D_OK) return st;
+  if (d_w)
+    HIP_TRY(hipMemcpyAsync(d_w, at<float>(ws_c, L.off_w), (size_t)L.nv * L.N * sizeof(float),
+                           hipMemcpyDeviceToDevice, s));
+  if (d_phi)
+    HIP_TRY(hipMemcpyAsync(d_phi, at<float>(ws_c, L.off_phi), L.N * sizeof(float),
+                           hipMemcpyDeviceToDevice, s));
+  return RISM3D_OK;
+}
+
+size_t rism3d_transform_workspace_bytes(int nx, int ny, int nz) {
+  AxisPlan p;
+  if (!plan_axis(nx, &p) || !plan_axis(ny, &p) || !plan_axis(nz, &p)) {
+    fail(RISM3D_E_ARG, "grid %dx%dx%d unsupported", nx, ny, nz);
+    return 0;
+  }
+  return align_up(2 * (size_t)nx * sizeof(float2)) + align_up(2 * (size_t)ny * sizeof(float2)) +
+         align_up(2 * (size_t)nz * sizeof(float2));
+}
+
+rism3d_status rism3d_transform(int nx, int ny, int nz, int count, void* d_data, int forward,
+                               void* ws, size_t ws_bytes, hipStream_t s) {
+  Layout L;
+  memset(&L, 0, sizeof(L));
+  if (!plan_axis(nx, &L.px) || !plan_axis(ny, &L.py) || !plan_axis(nz, &L.pz))
+    return fail(RISM3D_E_ARG, "grid %dx%dx%d unsupported", nx, ny, nz);
+  if (count < 1 || !d_data) return fail(RISM3D_E_ARG, "count < 1 or null data");
+  const size_t need = rism3d_transform_workspace_bytes(nx, ny, nz);
+  if (!ws || (((uintptr_t)ws) & 255) || ws_bytes < need)
+    return fail(RISM3D_E_WORKSPACE, "transform workspace must hold %zu aligned bytes", need);
+  L.nx = nx;
+  L.ny = ny;
+  L.nz = nz;
+  L.npair = count;
+  L.N = (size_t)nx * ny * nz;
+  const size_t offs[3] = {0, align_up(2 * (size_t)nx * sizeof(float2)),
+                          align_up(2 * (size_t)nx * sizeof(float2)) +
+                              align_up(2 * (size_t)ny * sizeof(float2))};
+  const int dims[3] = {nx, ny, nz};
+  const float2* tw[3];
+  for (int a = 0; a < 3; ++a) {
+    hipLaunchKernelGGL(k_twiddles, dim3(blocks_for(2 * dims[a], 256)), dim3(256), 0, s, dims[a],
+                       at<float2>(ws, offs[a]), (double2*)nullptr);
+    tw[a] = at<float2>(ws, offs[a]);
+  }
+  launch_fft3_on(L, static_cast<float2*>(d_data), tw, forward, (const int*)nullptr, s);
+  LAUNCH_CHECK();
+  return RISM3D_OK;
+}
+
+const char* rism3d_last_error(void) { return g_error.c_str(); }
+
+void rism3d_constants(double* coulomb, double* kboltz, double* screen, double* d_min,
+                      double* beta_u_cap) {
+  if (coulomb) *coulomb = kCoulomb;
+  if (kboltz) *kboltz = kBoltzmann;
+  if (screen) *screen = kScreen;
+  if (d_min) *d_min = kDMin;
+  if (beta_u_cap) *beta_u_cap = kBetaUCap;
+}
+
+}  // extern "C"

@@ -1,0 +1,283 @@
+"""Python binding of librism3d.so (argument marshalling only).
+
+Every step of the computation runs in the library's HIP kernels; this module
+only builds the C structs of ``include/rism3d.h``, passes torch device pointers
+and the current HIP stream, and converts status codes into exceptions.  The
+function names follow the C entry points.  There is no fallback: if the
+library is not built, importing the binding raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "librism3d.so")
+MAX_SITES = 8
+MAX_DEPTH = 16
+
+STATUS = {0: "OK", 1: "E_ARG", 2: "E_DEVICE", 3: "E_NOCONV", 4: "E_NONFINITE", 5: "E_WORKSPACE"}
+CLOSURES = {"kh": 0, "hnc": 1, "pse": 2}
+
+
+class RismError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("n_atoms", ctypes.c_int),
+        ("xyz", ctypes.c_void_p), ("q", ctypes.c_void_p),
+        ("sigma", ctypes.c_void_p), ("eps", ctypes.c_void_p),
+        ("n_sites", ctypes.c_int),
+        ("site_q", ctypes.c_void_p), ("site_sigma", ctypes.c_void_p),
+        ("site_eps", ctypes.c_void_p), ("site_rho", ctypes.c_void_p),
+        ("n_k", ctypes.c_int), ("dk", ctypes.c_double), ("chi", ctypes.c_void_p),
+        ("temperature", ctypes.c_double),
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("spacing", ctypes.c_double), ("center", ctypes.c_double * 3),
+    ]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [
+        ("closure", ctypes.c_int), ("pse_order", ctypes.c_int), ("tol", ctypes.c_double),
+        ("max_iter", ctypes.c_int), ("mdiis_depth", ctypes.c_int),
+        ("mdiis_eta", ctypes.c_double), ("eta_dynamic", ctypes.c_int),
+        ("check_every", ctypes.c_int), ("anchor_every", ctypes.c_int),
+    ]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("rms", ctypes.c_double),
+                ("restarts", ctypes.c_int), ("warm_start_used", ctypes.c_int)]
+
+
+class ThermoOut(ctypes.Structure):
+    _fields_ = [("sfe", ctypes.c_double), ("sfe_site", ctypes.c_double * MAX_SITES)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp, sz, st = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p
+    sig = {
+        "rism3d_workspace_bytes": (sz, [P(Problem), P(Opts)]),
+        "rism3d_potential": (ctypes.c_int, [P(Problem), P(Opts), vp, sz, st]),
+        "rism3d_solve": (ctypes.c_int, [P(Problem), P(Opts), vp, vp, sz, vp, P(Info), st]),
+        "rism3d_thermo": (ctypes.c_int, [P(Problem), P(Opts), vp, sz, P(ThermoOut), st]),
+        "rism3d_get_tau": (ctypes.c_int, [P(Problem), P(Opts), vp, sz, vp, st]),
+        "rism3d_map": (ctypes.c_int, [P(Problem), P(Opts), vp, vp, sz, vp,
+                                      P(ctypes.c_double), st]),
+        "rism3d_get_potential": (ctypes.c_int, [P(Problem), P(Opts), vp, sz, vp, vp, st]),
+        "rism3d_transform_workspace_bytes": (sz, [ctypes.c_int] * 3),
+        "rism3d_transform": (ctypes.c_int, [ctypes.c_int] * 4 + [vp, ctypes.c_int, vp, sz, st]),
+        "rism3d_last_error": (ctypes.c_char_p, []),
+        "rism3d_constants": (None, [P(ctypes.c_double)] * 5),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+LIB = _load()
+EXPORTED = ("rism3d_workspace_bytes", "rism3d_potential", "rism3d_solve", "rism3d_thermo",
+            "rism3d_get_tau", "rism3d_map", "rism3d_get_potential",
+            "rism3d_transform_workspace_bytes", "rism3d_transform", "rism3d_last_error",
+            "rism3d_constants")
+
+
+def last_error() -> str:
+    return LIB.rism3d_last_error().decode()
+
+
+def _check(status: int, allow=()):
+    if status != 0 and status not in allow:
+        raise RismError(status, last_error())
+    return status
+
+
+def constants():
+    vals = [ctypes.c_double() for _ in range(5)]
+    LIB.rism3d_constants(*[ctypes.byref(v) for v in vals])
+    return dict(zip(("coulomb", "kboltz", "screen", "d_min", "beta_u_cap"),
+                    (v.value for v in vals)))
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else int(t.data_ptr())
+
+
+class DeviceProblem:
+    """The problem statement of ``include/rism3d.h`` with its large arrays on
+    the device (float64 torch tensors) and the per-site arrays on the host."""
+
+    def __init__(self, problem, chi: np.ndarray, dk: float, device="cuda"):
+        sol = problem.solute
+        dev = torch.device(device)
+        f64 = torch.float64
+        self.problem = problem
+        self.n_atoms = sol.n_atoms
+        self.xyz = torch.as_tensor(np.ascontiguousarray(sol.xyz), dtype=f64).to(dev)
+        self.q = torch.as_tensor(np.ascontiguousarray(sol.q), dtype=f64).to(dev)
+        self.sigma = torch.as_tensor(np.ascontiguousarray(sol.sigma), dtype=f64).to(dev)
+        self.eps = torch.as_tensor(np.ascontiguousarray(sol.eps), dtype=f64).to(dev)
+        self.chi = torch.as_tensor(np.ascontiguousarray(chi), dtype=f64).to(dev)
+        q, sg, ep, rho = (np.ascontiguousarray(a, dtype=np.float64)
+                          for a in problem.solvent.site_arrays())
+        self._host = (q, sg, ep, rho)
+        g = problem.grid
+        self.shape = (len(q), g.nz, g.ny, g.nx)
+        s = Problem()
+        s.n_atoms = self.n_atoms
+        s.xyz, s.q, s.sigma, s.eps = (_ptr(t) if self.n_atoms else None
+                                      for t in (self.xyz, self.q, self.sigma, self.eps))
+        s.n_sites = len(q)
+        s.site_q, s.site_sigma, s.site_eps, s.site_rho = (a.ctypes.data for a in self._host)
+        s.n_k = int(chi.shape[-1])
+        s.dk = float(dk)
+        s.chi = _ptr(self.chi)
+        s.temperature = float(problem.solvent.temperature)
+        s.nx, s.ny, s.nz = g.nx, g.ny, g.nz
+        s.spacing = float(g.spacing)
+        s.center[:] = [float(c) for c in g.center]
+        self.struct = s
+
+
+def make_opts(options, check_every: int = 0, anchor_every: int = 0, **override) -> Opts:
+    o = Opts()
+    o.closure = CLOSURES[override.get("closure", options.closure)]
+    o.pse_order = int(override.get("pse_order", options.pse_order))
+    o.tol = float(override.get("tol", options.tol))
+    o.max_iter = int(override.get("max_iter", options.max_iter))
+    o.mdiis_depth = int(override.get("mdiis_depth", options.mdiis_depth))
+    o.mdiis_eta = float(override.get("mdiis_eta", options.mdiis_eta))
+    o.eta_dynamic = int(bool(override.get("eta_dynamic", options.eta_dynamic)))
+    o.check_every = int(check_every)
+    o.anchor_every = int(anchor_every)
+    return o
+
+
+# --- thin wrappers with the C names ---------------------------------------
+
+
+def rism3d_workspace_bytes(dp: DeviceProblem, opts: Opts) -> int:
+    n = LIB.rism3d_workspace_bytes(ctypes.byref(dp.struct), ctypes.byref(opts))
+    if n == 0:
+        raise RismError(1, last_error())
+    return int(n)
+
+
+def rism3d_potential(dp, opts, ws: torch.Tensor, stream=None):
+    _check(LIB.rism3d_potential(ctypes.byref(dp.struct), ctypes.byref(opts), _ptr(ws),
+                                ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def rism3d_solve(dp, opts, ws, tau0=None, g_out=None, stream=None, allow_noconv=False) -> Info:
+    info = Info()
+    allow = (3,) if allow_noconv else ()
+    info.status = _check(LIB.rism3d_solve(ctypes.byref(dp.struct), ctypes.byref(opts), _ptr(tau0),
+                                          _ptr(ws), ws.numel() * ws.element_size(), _ptr(g_out),
+                                          ctypes.byref(info), _stream(stream)), allow)
+    return info
+
+
+def rism3d_thermo(dp, opts, ws, stream=None):
+    out = ThermoOut()
+    _check(LIB.rism3d_thermo(ctypes.byref(dp.struct), ctypes.byref(opts), _ptr(ws),
+                             ws.numel() * ws.element_size(), ctypes.byref(out), _stream(stream)))
+    nv = dp.struct.n_sites
+    return out.sfe, np.array(out.sfe_site[:nv])
+
+
+def rism3d_get_tau(dp, opts, ws, tau_out, stream=None):
+    _check(LIB.rism3d_get_tau(ctypes.byref(dp.struct), ctypes.byref(opts), _ptr(ws),
+                              ws.numel() * ws.element_size(), _ptr(tau_out), _stream(stream)))
+
+
+def rism3d_map(dp, opts, ws, tau, res_out, stream=None) -> float:
+    rms = ctypes.c_double()
+    _check(LIB.rism3d_map(ctypes.byref(dp.struct), ctypes.byref(opts), _ptr(tau), _ptr(ws),
+                          ws.numel() * ws.element_size(), _ptr(res_out), ctypes.byref(rms),
+                          _stream(stream)))
+    return rms.value
+
+
+def rism3d_get_potential(dp, opts, ws, w_out=None, phi_out=None, stream=None):
+    _check(LIB.rism3d_get_potential(ctypes.byref(dp.struct), ctypes.byref(opts), _ptr(ws),
+                                    ws.numel() * ws.element_size(), _ptr(w_out), _ptr(phi_out),
+                                    _stream(stream)))
+
+
+def rism3d_transform(data: torch.Tensor, forward: bool, ws: Optional[torch.Tensor] = None,
+                     stream=None):
+    """In-place shifted 3D transform of complex64 data [count, nz, ny, nx]."""
+    assert data.dtype == torch.complex64 and data.is_contiguous() and data.dim() == 4
+    count, nz, ny, nx = data.shape
+    need = LIB.rism3d_transform_workspace_bytes(nx, ny, nz)
+    if need == 0:
+        raise RismError(1, last_error())
+    if ws is None:
+        ws = torch.empty(need, dtype=torch.uint8, device=data.device)
+    _check(LIB.rism3d_transform(nx, ny, nz, count, _ptr(data), int(bool(forward)), _ptr(ws),
+                                ws.numel(), _stream(stream)))
+    return data
+
+
+# --- convenience -------------------------------------------------------------
+
+
+def alloc_workspace(nbytes: int, device="cuda") -> torch.Tensor:
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-ws.data_ptr()) % 256
+    return ws[off:off + nbytes]
+
+
+class Solver:
+    """Owns a workspace for one problem and runs potential -> solve -> thermo."""
+
+    def __init__(self, dp: DeviceProblem, opts: Opts):
+        self.dp = dp
+        self.opts = opts
+        self.nbytes = rism3d_workspace_bytes(dp, opts)
+        self.ws = alloc_workspace(self.nbytes, dp.xyz.device)
+
+    def potential(self, stream=None):
+        rism3d_potential(self.dp, self.opts, self.ws, stream)
+
+    def solve(self, tau0=None, g_out=None, stream=None, allow_noconv=False) -> Info:
+        return rism3d_solve(self.dp, self.opts, self.ws, tau0, g_out, stream, allow_noconv)
+
+    def thermo(self, stream=None):
+        return rism3d_thermo(self.dp, self.opts, self.ws, stream)
+
+    def tau(self) -> torch.Tensor:
+        t = torch.empty(self.dp.shape, dtype=torch.float32, device=self.ws.device)
+        rism3d_get_tau(self.dp, self.opts, self.ws, t)
+        return t
+
+    def fields(self):
+        w = torch.empty(self.dp.shape, dtype=torch.float32, device=self.ws.device)
+        phi = torch.empty(self.dp.shape[1:], dtype=torch.float32, device=self.ws.device)
+        rism3d_get_potential(self.dp, self.opts, self.ws, w, phi)
+        return w, phi
+
+    def map(self, tau: torch.Tensor):
+        res = torch.empty(self.dp.shape, dtype=torch.float32, device=self.ws.device)
+        rms = rism3d_map(self.dp, self.opts, self.ws, tau.contiguous(), res)
+        return res, rms
