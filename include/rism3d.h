@@ -190,6 +190,16 @@ size_t rism3d_transform_workspace_bytes(int nx, int ny, int nz);
 rism3d_status rism3d_transform(int nx, int ny, int nz, int count, void* d_data, int forward,
                                void* d_ws, size_t ws_bytes, hipStream_t stream);
 
+/* Kernel timing, for profiling (thread-local switch).  While enabled, calls on
+ * this thread record a pair of HIP events on the call's stream around every
+ * kernel launch and add the elapsed time to a per-family total when the call
+ * synchronises.  rism3d_timing_read(i, ...) fills the name, launch count and
+ * total milliseconds of family i and returns the number of families (call with
+ * i = -1 to get the count only).  Enabling costs two event records per launch. */
+void rism3d_timing_enable(int on);
+void rism3d_timing_reset(void);
+int rism3d_timing_read(int family, const char** name, long* launches, double* total_ms);
+
 /* Thread-local message describing the last error on this thread ("" if none). */
 const char* rism3d_last_error(void);
 

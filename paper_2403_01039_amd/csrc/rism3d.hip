@@ -10,6 +10,8 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
+#include <vector>
 
 #include "common.hpp"
 #include "fft.hpp"
@@ -46,6 +48,76 @@ rism3d_status fail(rism3d_status s, const char* fmt, ...) {
       return fail(RISM3D_E_DEVICE, "kernel launch failed (%s:%d): %s", __FILE__, __LINE__, \
                   hipGetErrorString(e_));                                                   \
   } while (0)
+
+// ---------------------------------------------------------------------------
+// Optional per-family kernel timing with HIP events (thread-local).
+// ---------------------------------------------------------------------------
+enum Family {
+  F_UPDATE32, F_UPDATE64, F_FFT32, F_FFT64, F_CONTRACT32, F_CONTRACT64, F_RESIDUAL32,
+  F_RESIDUAL64, F_CONTROL, F_POTENTIAL, F_FTILDE, F_SETUP, F_OUTPUT, F_SFE, F_COUNT
+};
+const char* const kFamilyNames[F_COUNT] = {
+    "update_closure_f32", "update_closure_f64", "fft_axis_f32", "fft_axis_f64",
+    "contract_f32", "contract_f64", "residual_gram_f32", "residual_gram_f64", "mdiis_control",
+    "potential", "long_range_spectrum", "setup_tables", "output", "free_energy"};
+
+struct Timer {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  struct Pending {
+    int fam;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  double ms[F_COUNT] = {};
+  long count[F_COUNT] = {};
+  hipEvent_t get() {
+    if (pool.empty()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      return e;
+    }
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  // Harvest completed pairs (the caller has synchronised the stream).
+  void harvest() {
+    std::vector<Pending> keep;
+    for (const Pending& p : pending) {
+      if (hipEventQuery(p.b) != hipSuccess) {
+        keep.push_back(p);
+        continue;
+      }
+      float t = 0.0f;
+      if (hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) {
+        ms[p.fam] += t;
+        count[p.fam] += 1;
+      }
+      pool.push_back(p.a);
+      pool.push_back(p.b);
+    }
+    pending.swap(keep);
+  }
+};
+thread_local Timer g_timer;
+
+struct TimedScope {
+  hipEvent_t a = nullptr;
+  int fam;
+  hipStream_t s;
+  TimedScope(int f, hipStream_t st) : fam(f), s(st) {
+    if (g_timer.on && (a = g_timer.get())) hipEventRecord(a, s);
+  }
+  ~TimedScope() {
+    if (!a) return;
+    hipEvent_t b = g_timer.get();
+    if (!b) return;
+    hipEventRecord(b, s);
+    g_timer.pending.push_back({fam, a, b});
+  }
+};
+#define TIMED(fam, s) TimedScope timed_scope_##__LINE__(fam, s)
 
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
@@ -217,9 +289,12 @@ unsigned blocks_for(size_t n, int threads) { return (unsigned)((n + threads - 1)
 template <int NV>
 void launch_potential_nv(const Layout& L, void* ws, double dr, const SiteConsts& sc,
                          hipStream_t s) {
-  hipLaunchKernelGGL(k_potential<NV>, dim3(blocks_for(L.N, kPotThreads)), dim3(kPotThreads), 0, s,
-                     at<double4>(ws, L.off_atoms), at<double2>(ws, L.off_lj), L.n_atoms, L.nx, L.ny,
-                     L.nz, dr, sc, at<float>(ws, L.off_w), at<float>(ws, L.off_phi));
+  {
+    TIMED(F_POTENTIAL, s);
+    hipLaunchKernelGGL(k_potential<NV>, dim3(blocks_for(L.N, kPotThreads)), dim3(kPotThreads), 0, s,
+                       at<double4>(ws, L.off_atoms), at<double2>(ws, L.off_lj), L.n_atoms, L.nx, L.ny,
+                       L.nz, dr, sc, at<float>(ws, L.off_w), at<float>(ws, L.off_phi));
+  }
 }
 
 void launch_potential(const Layout& L, void* ws, double dr, const SiteConsts& sc, hipStream_t s) {
@@ -240,15 +315,21 @@ void launch_contract_nv(const Layout& L, void* ws, bool anchor, float inv_dkt, c
                         hipStream_t s) {
   const dim3 grid(blocks_for(L.half, kElemThreads)), block(kElemThreads);
   if (anchor)
-    hipLaunchKernelGGL((k_contract<NV, double2, true>), grid, block, 0, s,
-                       at<double2>(ws, L.off_spec), L.nx, L.ny, L.nz, (float)L.dkx, (float)L.dky,
-                       (float)L.dkz, at<double2>(ws, L.off_F), at<double>(ws, L.off_chi64),
-                       at<double>(ws, L.off_q64), inv_dkt, L.m_tab, done);
+    {
+      TIMED(F_CONTRACT64, s);
+      hipLaunchKernelGGL((k_contract<NV, double2, true>), grid, block, 0, s,
+                         at<double2>(ws, L.off_spec), L.nx, L.ny, L.nz, (float)L.dkx, (float)L.dky,
+                         (float)L.dkz, at<double2>(ws, L.off_F), at<double>(ws, L.off_chi64),
+                         at<double>(ws, L.off_q64), inv_dkt, L.m_tab, done);
+    }
   else
-    hipLaunchKernelGGL((k_contract<NV, float2, false>), grid, block, 0, s,
-                       at<float2>(ws, L.off_spec), L.nx, L.ny, L.nz, (float)L.dkx, (float)L.dky,
-                       (float)L.dkz, (const float2*)nullptr, at<float>(ws, L.off_chi32),
-                       (const float*)nullptr, inv_dkt, L.m_tab, done);
+    {
+      TIMED(F_CONTRACT32, s);
+      hipLaunchKernelGGL((k_contract<NV, float2, false>), grid, block, 0, s,
+                         at<float2>(ws, L.off_spec), L.nx, L.ny, L.nz, (float)L.dkx, (float)L.dky,
+                         (float)L.dkz, (const float2*)nullptr, at<float>(ws, L.off_chi32),
+                         (const float*)nullptr, inv_dkt, L.m_tab, done);
+    }
 }
 
 void launch_contract(const Layout& L, void* ws, bool anchor, float inv_dkt, const int* done,
@@ -285,8 +366,11 @@ void launch_fft3_on(const Layout& L, C* spec, const C* const tw[3], int forward,
       const int outer = axis == 1 ? L.npair * L.nz : L.npair * L.ny;
       grid = (unsigned)outer * tiles_x;
     }
-    hipLaunchKernelGGL(k_fft_axis<C>, dim3(grid), dim3(kFftThreads), 0, s, spec, L.nx, L.ny,
-                       L.nz, L.npair, axis, p, tw[axis], forward, lines, done);
+    {
+      TIMED((std::is_same<C, double2>::value ? F_FFT64 : F_FFT32), s);
+      hipLaunchKernelGGL(k_fft_axis<C>, dim3(grid), dim3(kFftThreads), 0, s, spec, L.nx, L.ny,
+                         L.nz, L.npair, axis, p, tw[axis], forward, lines, done);
+    }
   }
 }
 
@@ -318,15 +402,21 @@ void launch_iteration(const Layout& L, void* ws, const rism3d_opts* op, const fl
   const int order = op->closure == RISM3D_PSE ? op->pse_order : 1;
   const dim3 eg(blocks_for((size_t)L.npair * L.N, kElemThreads)), eb(kElemThreads);
   if (anchor)
-    hipLaunchKernelGGL(k_update_closure<true>, eg, eb, 0, s, st, tau0, at<float>(ws, L.off_tau),
-                       at<float>(ws, L.off_res), at<float>(ws, L.off_w),
-                       at<float>(ws, L.off_tref), at<float>(ws, L.off_dg),
-                       at<void>(ws, L.off_spec), L.N, L.nv, L.npair, L.M, kind, order);
+    {
+      TIMED(F_UPDATE64, s);
+      hipLaunchKernelGGL(k_update_closure<true>, eg, eb, 0, s, st, tau0, at<float>(ws, L.off_tau),
+                         at<float>(ws, L.off_res), at<float>(ws, L.off_w),
+                         at<float>(ws, L.off_tref), at<float>(ws, L.off_dg),
+                         at<void>(ws, L.off_spec), L.N, L.nv, L.npair, L.M, kind, order);
+    }
   else
-    hipLaunchKernelGGL(k_update_closure<false>, eg, eb, 0, s, st, tau0, at<float>(ws, L.off_tau),
-                       at<float>(ws, L.off_res), at<float>(ws, L.off_w),
-                       at<float>(ws, L.off_tref), at<float>(ws, L.off_dg),
-                       at<void>(ws, L.off_spec), L.N, L.nv, L.npair, L.M, kind, order);
+    {
+      TIMED(F_UPDATE32, s);
+      hipLaunchKernelGGL(k_update_closure<false>, eg, eb, 0, s, st, tau0, at<float>(ws, L.off_tau),
+                         at<float>(ws, L.off_res), at<float>(ws, L.off_w),
+                         at<float>(ws, L.off_tref), at<float>(ws, L.off_dg),
+                         at<void>(ws, L.off_spec), L.N, L.nv, L.npair, L.M, kind, order);
+    }
   if (anchor) launch_fft3<double2>(L, ws, 1, done, s);
   else launch_fft3<float2>(L, ws, 1, done, s);
   launch_contract(L, ws, anchor, inv_dkt, done, s);
@@ -336,21 +426,30 @@ void launch_iteration(const Layout& L, void* ws, const rism3d_opts* op, const fl
   unsigned nblk = blocks_for(work, kRedThreads);
   if (nblk > (unsigned)kRedBlocks) nblk = kRedBlocks;
   if (anchor)
-    hipLaunchKernelGGL(k_residual<true>, dim3(nblk), dim3(kRedThreads), 0, s, st,
-                       at<void>(ws, L.off_spec), at<float>(ws, L.off_w), at<float>(ws, L.off_tau),
-                       at<float>(ws, L.off_res), at<float>(ws, L.off_tref),
-                       at<float>(ws, L.off_rref), at<float>(ws, L.off_dg), L.N, L.nv, L.npair,
-                       L.M, kind, order, at<double>(ws, L.off_part));
+    {
+      TIMED(F_RESIDUAL64, s);
+      hipLaunchKernelGGL(k_residual<true>, dim3(nblk), dim3(kRedThreads), 0, s, st,
+                         at<void>(ws, L.off_spec), at<float>(ws, L.off_w), at<float>(ws, L.off_tau),
+                         at<float>(ws, L.off_res), at<float>(ws, L.off_tref),
+                         at<float>(ws, L.off_rref), at<float>(ws, L.off_dg), L.N, L.nv, L.npair,
+                         L.M, kind, order, at<double>(ws, L.off_part));
+    }
   else
-    hipLaunchKernelGGL(k_residual<false>, dim3(nblk), dim3(kRedThreads), 0, s, st,
-                       at<void>(ws, L.off_spec), at<float>(ws, L.off_w), at<float>(ws, L.off_tau),
-                       at<float>(ws, L.off_res), at<float>(ws, L.off_tref),
-                       at<float>(ws, L.off_rref), at<float>(ws, L.off_dg), L.N, L.nv, L.npair,
-                       L.M, kind, order, at<double>(ws, L.off_part));
+    {
+      TIMED(F_RESIDUAL32, s);
+      hipLaunchKernelGGL(k_residual<false>, dim3(nblk), dim3(kRedThreads), 0, s, st,
+                         at<void>(ws, L.off_spec), at<float>(ws, L.off_w), at<float>(ws, L.off_tau),
+                         at<float>(ws, L.off_res), at<float>(ws, L.off_tref),
+                         at<float>(ws, L.off_rref), at<float>(ws, L.off_dg), L.N, L.nv, L.npair,
+                         L.M, kind, order, at<double>(ws, L.off_part));
+    }
   const double inv_count = 1.0 / ((double)L.N * (double)L.nv);
-  hipLaunchKernelGGL(k_control, dim3(1), dim3(kRedThreads), 0, s, st, at<double>(ws, L.off_part),
-                     (int)nblk, L.M, inv_count, op->tol, op->max_iter, (float)op->mdiis_eta,
-                     op->eta_dynamic);
+  {
+    TIMED(F_CONTROL, s);
+    hipLaunchKernelGGL(k_control, dim3(1), dim3(kRedThreads), 0, s, st, at<double>(ws, L.off_part),
+                       (int)nblk, L.M, inv_count, op->tol, op->max_iter, (float)op->mdiis_eta,
+                       op->eta_dynamic);
+  }
 }
 
 int order_of(const rism3d_opts* op) { return op->closure == RISM3D_PSE ? op->pse_order : 1; }
@@ -395,9 +494,12 @@ rism3d_status rism3d_potential(const rism3d_problem* pr, const rism3d_opts* op, 
   launch_potential(L, ws, pr->spacing, sc, s);
   LAUNCH_CHECK();
   const double pref = 4.0 * M_PI * L.beta * kCoulomb / (kScreen * kScreen) / L.dv;
-  hipLaunchKernelGGL(k_ftilde, dim3(blocks_for(L.half, 256)), dim3(256), 0, s,
-                     at<double2>(ws, L.off_ph), at<double4>(ws, L.off_atoms), L.n_atoms, L.nx, L.ny,
-                     L.nz, L.dkx, L.dky, L.dkz, pref, at<double2>(ws, L.off_F));
+  {
+    TIMED(F_FTILDE, s);
+    hipLaunchKernelGGL(k_ftilde, dim3(blocks_for(L.half, 256)), dim3(256), 0, s,
+                       at<double2>(ws, L.off_ph), at<double4>(ws, L.off_atoms), L.n_atoms, L.nx, L.ny,
+                       L.nz, L.dkx, L.dky, L.dkz, pref, at<double2>(ws, L.off_F));
+  }
   LAUNCH_CHECK();
   hipLaunchKernelGGL(k_chi_tables, dim3(blocks_for((size_t)L.m_tab * L.nv, 256)), dim3(256), 0, s,
                      pr->chi, L.nv, pr->n_k, L.m_tab, 1.0 / (double)L.N, sc,
@@ -441,6 +543,7 @@ rism3d_status rism3d_solve(const rism3d_problem* pr, const rism3d_opts* op, cons
     launched += todo;
     HIP_TRY(hipMemcpyAsync(&host, dst, sizeof(IterState), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    if (g_timer.on) g_timer.harvest();
     if (host.done || launched >= op->max_iter) break;
   }
   if (g_out) {
@@ -483,9 +586,12 @@ rism3d_status rism3d_thermo(const rism3d_problem* pr, const rism3d_opts* op, con
   const SiteConsts sc = site_consts(pr, L.beta);
   unsigned nblk = blocks_for(L.N, kRedThreads);
   if (nblk > (unsigned)kRedBlocks) nblk = kRedBlocks;
-  hipLaunchKernelGGL(k_sfe_partial, dim3(nblk), dim3(kRedThreads), 0, s, dst,
-                     at<float>(ws, L.off_tau), at<float>(ws, L.off_w), at<float>(ws, L.off_phi),
-                     L.N, L.nv, (int)op->closure, order_of(op), sc, at<double>(ws, L.off_part));
+  {
+    TIMED(F_SFE, s);
+    hipLaunchKernelGGL(k_sfe_partial, dim3(nblk), dim3(kRedThreads), 0, s, dst,
+                       at<float>(ws, L.off_tau), at<float>(ws, L.off_w), at<float>(ws, L.off_phi),
+                       L.N, L.nv, (int)op->closure, order_of(op), sc, at<double>(ws, L.off_part));
+  }
   const double scale = L.dv / L.beta;   // k_B T dV
   hipLaunchKernelGGL(k_sfe_reduce, dim3(1), dim3(kRedThreads), 0, s, at<double>(ws, L.off_part),
                      (int)nblk, L.nv, scale, sc, at<double>(ws, L.off_out));
@@ -493,6 +599,7 @@ rism3d_status rism3d_thermo(const rism3d_problem* pr, const rism3d_opts* op, con
   double res[kMaxSites + 1];
   HIP_TRY(hipMemcpyAsync(res, at<double>(ws, L.off_out), sizeof(res), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
+  if (g_timer.on) g_timer.harvest();
   memset(out, 0, sizeof(*out));
   out->sfe = res[kMaxSites];
   for (int g = 0; g < L.nv; ++g) out->sfe_site[g] = res[g];
@@ -599,6 +706,25 @@ rism3d_status rism3d_transform(int nx, int ny, int nz, int count, void* d_data, 
   launch_fft3_on(L, static_cast<float2*>(d_data), tw, forward, (const int*)nullptr, s);
   LAUNCH_CHECK();
   return RISM3D_OK;
+}
+
+void rism3d_timing_enable(int on) { g_timer.on = on != 0; }
+
+void rism3d_timing_reset(void) {
+  for (int f = 0; f < F_COUNT; ++f) {
+    g_timer.ms[f] = 0.0;
+    g_timer.count[f] = 0;
+  }
+}
+
+int rism3d_timing_read(int family, const char** name, long* launches, double* total_ms) {
+  g_timer.harvest();
+  if (family >= 0 && family < F_COUNT) {
+    if (name) *name = kFamilyNames[family];
+    if (launches) *launches = g_timer.count[family];
+    if (total_ms) *total_ms = g_timer.ms[family];
+  }
+  return F_COUNT;
 }
 
 const char* rism3d_last_error(void) { return g_error.c_str(); }

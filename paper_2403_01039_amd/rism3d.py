@@ -80,6 +80,10 @@ def _load():
         "rism3d_get_potential": (ctypes.c_int, [P(Problem), P(Opts), vp, sz, vp, vp, st]),
         "rism3d_transform_workspace_bytes": (sz, [ctypes.c_int] * 3),
         "rism3d_transform": (ctypes.c_int, [ctypes.c_int] * 4 + [vp, ctypes.c_int, vp, sz, st]),
+        "rism3d_timing_enable": (None, [ctypes.c_int]),
+        "rism3d_timing_reset": (None, []),
+        "rism3d_timing_read": (ctypes.c_int, [ctypes.c_int, P(ctypes.c_char_p), P(ctypes.c_long),
+                                              P(ctypes.c_double)]),
         "rism3d_last_error": (ctypes.c_char_p, []),
         "rism3d_constants": (None, [P(ctypes.c_double)] * 5),
     }
@@ -93,8 +97,8 @@ def _load():
 LIB = _load()
 EXPORTED = ("rism3d_workspace_bytes", "rism3d_potential", "rism3d_solve", "rism3d_thermo",
             "rism3d_get_tau", "rism3d_map", "rism3d_get_potential",
-            "rism3d_transform_workspace_bytes", "rism3d_transform", "rism3d_last_error",
-            "rism3d_constants")
+            "rism3d_transform_workspace_bytes", "rism3d_transform", "rism3d_timing_enable",
+            "rism3d_timing_reset", "rism3d_timing_read", "rism3d_last_error", "rism3d_constants")
 
 
 def last_error() -> str:
@@ -112,6 +116,27 @@ def constants():
     LIB.rism3d_constants(*[ctypes.byref(v) for v in vals])
     return dict(zip(("coulomb", "kboltz", "screen", "d_min", "beta_u_cap"),
                     (v.value for v in vals)))
+
+
+def timing_enable(on: bool = True):
+    LIB.rism3d_timing_enable(int(bool(on)))
+
+
+def timing_reset():
+    LIB.rism3d_timing_reset()
+
+
+def timing_read() -> dict:
+    """{family: (launches, total_ms)} of the kernel timing collected on this thread."""
+    n = LIB.rism3d_timing_read(-1, None, None, None)
+    out = {}
+    for i in range(n):
+        name = ctypes.c_char_p()
+        cnt = ctypes.c_long()
+        ms = ctypes.c_double()
+        LIB.rism3d_timing_read(i, ctypes.byref(name), ctypes.byref(cnt), ctypes.byref(ms))
+        out[name.value.decode()] = (int(cnt.value), float(ms.value))
+    return out
 
 
 def _stream(stream=None) -> int:

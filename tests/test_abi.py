@@ -1,0 +1,122 @@
+"""The C-ABI library without a GPU: it loads, exports every entry point the
+header declares, agrees with the oracle on unit constants, and rejects bad
+arguments in its host-side checks (no device work is launched here)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rism3d.h")
+
+
+@pytest.fixture(scope="module")
+def R():
+    lib = os.path.join(ROOT, "paper_2403_01039_amd", "_lib", "librism3d.so")
+    if not os.path.exists(lib):
+        import __graft_entry__
+        __graft_entry__.build()
+    from paper_2403_01039_amd import rism3d
+    return rism3d
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rism3d_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(R):
+    names = _declared()
+    assert len(names) >= 10
+    lib = ctypes.CDLL(R.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(R.EXPORTED)
+
+
+def test_constants_agree_with_oracle(R):
+    from oracle import rism3d as O
+    c = R.constants()
+    assert c["coulomb"] == O.COULOMB
+    assert c["kboltz"] == O.KBOLTZ
+    assert c["screen"] == O.SCREEN
+    assert c["d_min"] == O.D_MIN
+    assert c["beta_u_cap"] == O.BETA_U_CAP
+
+
+def _fake_problem(R, n=(16, 16, 16), nv=3, n_k=4096, dk=0.0307, n_atoms=4):
+    keep = [np.zeros(nv) + v for v in (0.4, 3.0, 0.1, 0.0334)]
+    p = R.Problem()
+    p.n_atoms = n_atoms
+    fake = 0x1000   # never dereferenced: only host-side checks run here
+    p.xyz = p.q = p.sigma = p.eps = fake
+    p.n_sites = nv
+    p.site_q, p.site_sigma, p.site_eps, p.site_rho = (a.ctypes.data for a in keep)
+    p.n_k = n_k
+    p.dk = dk
+    p.chi = fake
+    p.temperature = 298.15
+    p.nx, p.ny, p.nz = n
+    p.spacing = 0.5
+    return p, keep
+
+
+def _opts(R, **kw):
+    o = R.Opts()
+    o.closure, o.pse_order, o.tol, o.max_iter = 0, 3, 1e-6, 100
+    o.mdiis_depth, o.mdiis_eta, o.eta_dynamic, o.check_every, o.anchor_every = 5, 0.7, 0, 0, 0
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def test_workspace_size_and_history_scaling(R):
+    p, keep = _fake_problem(R)
+    n5 = R.LIB.rism3d_workspace_bytes(ctypes.byref(p), ctypes.byref(_opts(R, mdiis_depth=5)))
+    n6 = R.LIB.rism3d_workspace_bytes(ctypes.byref(p), ctypes.byref(_opts(R, mdiis_depth=6)))
+    N = 16 ** 3
+    # one more MDIIS pair = one tau and one residual grid per site (FP32), plus
+    # one more FP64 partial sum per reduction block (1024 blocks)
+    grow = 2 * 3 * N * 4 + 1024 * 8
+    assert grow <= n6 - n5 <= grow + 4 * 256
+
+
+@pytest.mark.parametrize("field,value,msg", [
+    ("n_sites", 9, "n_sites"), ("nx", 7, "unsupported"), ("nx", 1024, "unsupported"),
+    ("temperature", 0.0, "temperature"), ("spacing", -1.0, "spacing"), ("n_k", 1, "table"),
+])
+def test_bad_problem_is_rejected(R, field, value, msg):
+    p, keep = _fake_problem(R)
+    setattr(p, field, value)
+    assert R.LIB.rism3d_workspace_bytes(ctypes.byref(p), ctypes.byref(_opts(R))) == 0
+    assert msg in R.last_error()
+
+
+@pytest.mark.parametrize("field,value", [("mdiis_depth", 0), ("mdiis_depth", 17), ("tol", 0.0),
+                                         ("closure", 7), ("max_iter", 0), ("mdiis_eta", 0.0)])
+def test_bad_options_are_rejected(R, field, value):
+    p, keep = _fake_problem(R)
+    assert R.LIB.rism3d_workspace_bytes(ctypes.byref(p), ctypes.byref(_opts(R, **{field: value}))) == 0
+
+
+def test_short_chi_table_is_rejected(R):
+    """The table must reach the largest |k| of the grid (no silent extrapolation)."""
+    p, keep = _fake_problem(R, n_k=100)
+    assert R.LIB.rism3d_workspace_bytes(ctypes.byref(p), ctypes.byref(_opts(R))) == 0
+    assert "susceptibility table ends" in R.last_error()
+
+
+def test_null_workspace_is_rejected_without_device_work(R):
+    p, keep = _fake_problem(R)
+    st = R.LIB.rism3d_potential(ctypes.byref(p), ctypes.byref(_opts(R)), None, 0, None)
+    assert st == 5 and "workspace" in R.last_error()
+    st = R.LIB.rism3d_potential(ctypes.byref(p), ctypes.byref(_opts(R)), 0x1001, 1 << 40, None)
+    assert st == 5 and "aligned" in R.last_error()
+
+
+def test_transform_sizes(R):
+    assert R.LIB.rism3d_transform_workspace_bytes(7, 8, 8) == 0
+    assert R.LIB.rism3d_transform_workspace_bytes(96, 20, 18) > 0
