@@ -38,10 +38,18 @@ def kernel_bytes(nv: int, N: int, M: int, m_avg: float, fam: str) -> float:
         return nv * N * 4 * (2 * m_avg + 4) + 8 * P * N
     if fam == "update_closure_f64":   # read m tau_i, m R_i, w; write tau; write FP64 spectra
         return nv * N * 4 * (2 * m_avg + 2) + 16 * P * N
-    if fam == "fft_axis_f32" or fam == "contract_f32":
+    if fam.startswith("fft_") and fam.endswith("_f32") or fam == "contract_f32":
         return 16 * P * N
-    if fam == "fft_axis_f64" or fam == "contract_f64":
+    if fam.startswith("fft_") and fam.endswith("_f64") or fam == "contract_f64":
         return 32 * P * N
+    if fam == "update_fftx_f32":      # update + closure, spectra written once after the x pass
+        return nv * N * 4 * (2 * m_avg + 4) + 8 * P * N
+    if fam == "update_fftx_f64":
+        return nv * N * 4 * (2 * m_avg + 2) + 16 * P * N
+    if fam == "fftx_residual_f32":    # spectra read once, then the residual + Gram row
+        return 8 * P * N + nv * N * 4 * (2 + max(m_avg - 1, 0) + 1)
+    if fam == "fftx_residual_f64":
+        return 16 * P * N + nv * N * 4 * (2 + max(m_avg - 1, 0) + 3)
     if fam == "residual_gram_f32":    # read spectra, R_ref, dg, (m-1) R_i; write R
         return 8 * P * N + nv * N * 4 * (2 + max(m_avg - 1, 0) + 1)
     if fam == "residual_gram_f64":    # read FP64 spectra, tau, w, (m-1) R_i; write R, tau_ref, R_ref

@@ -69,8 +69,10 @@ typedef enum { RISM3D_KH = 0, RISM3D_HNC = 1, RISM3D_PSE = 2 } rism3d_closure;
  * solvent calculation, on a uniform k grid (dk in A^-1).  The table must reach
  * past the largest |k| of the grid: (n_k - 1) * dk >= |k|_max.
  *
- * Grid: nx, ny, nz points (each 2..512, with prime factors 2, 3 and 5 only),
- * spacing in A, center in A.
+ * Grid: nx, ny, nz points (each even, 2..512, with prime factors 2, 3 and 5
+ * only; an odd axis would have a self-mirrored half-integer frequency at which
+ * the analytic long-range spectrum of Eq 30 is not Hermitian), spacing in A,
+ * center in A.
  */
 typedef struct {
   int n_atoms;

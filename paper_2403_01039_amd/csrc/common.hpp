@@ -65,6 +65,7 @@ struct IterState {
   int final_slot;                     // slot of the accepted iterate
   int warm;                           // 1 if a caller tau0 seeded iteration 0
   int prepared;                       // magic set by rism3d_potential
+  int ticket;                         // workgroups of the fused residual kernel that finished
 };
 
 constexpr int kPreparedMagic = 0x52495344;  // "RISD"

@@ -253,4 +253,171 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_axis(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Fixed-size passes for the common axis lengths.  The radix plan, tile shape
+// and index arithmetic are compile-time constants; every thread issues all its
+// global loads before touching LDS (memory-level parallelism), and the radix
+// passes run in place in one LDS tile (each thread holds its butterfly inputs
+// in registers across the barrier), which halves the LDS footprint of the
+// ping-pong kernel and doubles its occupancy.
+// ---------------------------------------------------------------------------
+template <int N> struct FixedPlan { static constexpr int n = 0; };
+template <> struct FixedPlan<32>  { static constexpr int n = 2; static constexpr int r[4] = {8, 4, 1, 1}; };
+template <> struct FixedPlan<64>  { static constexpr int n = 2; static constexpr int r[4] = {8, 8, 1, 1}; };
+template <> struct FixedPlan<96>  { static constexpr int n = 3; static constexpr int r[4] = {8, 4, 3, 1}; };
+template <> struct FixedPlan<128> { static constexpr int n = 3; static constexpr int r[4] = {8, 4, 4, 1}; };
+template <> struct FixedPlan<192> { static constexpr int n = 3; static constexpr int r[4] = {8, 8, 3, 1}; };
+template <> struct FixedPlan<256> { static constexpr int n = 3; static constexpr int r[4] = {8, 8, 4, 1}; };
+template <> struct FixedPlan<512> { static constexpr int n = 3; static constexpr int r[4] = {8, 8, 8, 1}; };
+
+inline bool fixed_fft_size(int n) {
+  return n == 32 || n == 64 || n == 96 || n == 128 || n == 192 || n == 256 || n == 512;
+}
+
+template <typename C> constexpr int fixed_tile() { return sizeof(C) == 8 ? 4096 : 2048; }
+
+template <typename C, int N, int AXIS>
+constexpr int fixed_lines() {
+  return AXIS == 0 ? (fixed_tile<C>() / N < 1 ? 1 : fixed_tile<C>() / N)
+                   : (fixed_tile<C>() / N > 32 ? 32 : fixed_tile<C>() / N);
+}
+
+// LDS layout of a tile: element i of line b lives at b * PITCH + i + (i >> 3).
+// The skew of one slot every 8 elements makes the stride-R writes of the first
+// Stockham pass conflict-free, and the odd pitch does the same for the
+// transposed (one lane per line) accesses of the y and z passes.
+template <int N> struct Lds {
+  static constexpr int PITCH = N + N / 8 + 1;
+  __device__ static inline int at(int b, int i) { return b * PITCH + i + (i >> 3); }
+};
+
+template <int R, int NS, int N, int LINES, typename C, typename S>
+__device__ inline void pass_inplace(C* buf, int nl, const C* tw2, S sgn) {
+  constexpr int NB = N / R;
+  constexpr int MAXB = (LINES * NB + kFftThreads - 1) / kFftThreads;
+  constexpr int STEP2 = (2 * N) / (NS * R);
+  const int nbf = nl * NB;
+  C v[MAXB][R];
+#pragma unroll
+  for (int q = 0; q < MAXB; ++q) {
+    const int t = threadIdx.x + q * kFftThreads;
+    if (t < nbf) {
+      const int b = t / NB;
+      const int j = t - b * NB;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = buf[Lds<N>::at(b, j + r * NB)];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < MAXB; ++q) {
+    const int t = threadIdx.x + q * kFftThreads;
+    if (t < nbf) {
+      const int b = t / NB;
+      const int j = t - b * NB;
+      const int k = j % NS;
+      if (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const C w = tw2[(r * k * STEP2) % (2 * N)];
+          v[q][r] = (sgn < S(0)) ? cmul(v[q][r], w) : cmulc(v[q][r], w);
+        }
+      }
+      Dft<R, C, S>::run(v[q], sgn);
+      const int d0 = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[Lds<N>::at(b, d0 + r * NS)] = v[q][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <int P, int NS, int N, int LINES, typename C, typename S>
+__device__ inline void passes_from(C* buf, int nl, const C* tw2, S sgn) {
+  if constexpr (P < FixedPlan<N>::n) {
+    constexpr int R = FixedPlan<N>::r[P];
+    pass_inplace<R, NS, N, LINES>(buf, nl, tw2, sgn);
+    passes_from<P + 1, NS * R, N, LINES>(buf, nl, tw2, sgn);
+  }
+}
+
+template <typename C, int N, int AXIS>
+__global__ __launch_bounds__(kFftThreads) void k_fft_fixed(
+    C* __restrict__ data, int nx, int ny, int nz, int npair, const C* __restrict__ tw2_g,
+    int forward, const int* __restrict__ done) {
+  using S = typename ScalarOf<C>::type;
+  constexpr int LINES = fixed_lines<C, N, AXIS>();
+  constexpr int TILE = LINES * N;
+  constexpr int EPT = (TILE + kFftThreads - 1) / kFftThreads;
+  if (done && *done) return;
+  __shared__ C buf[LINES * Lds<N>::PITCH];
+  __shared__ C tw2[2 * N];
+  for (int i = threadIdx.x; i < 2 * N; i += kFftThreads) tw2[i] = tw2_g[i];
+
+  size_t base;
+  int nl;
+  size_t istride;
+  if (AXIS == 0) {
+    const size_t rows = (size_t)npair * nz * ny;
+    const size_t row0 = (size_t)blockIdx.x * LINES;
+    if (row0 >= rows) return;
+    nl = (int)((rows - row0) < (size_t)LINES ? (rows - row0) : (size_t)LINES);
+    base = row0 * N;
+    istride = 1;
+  } else {
+    const int tiles_x = (nx + LINES - 1) / LINES;
+    const int outer = blockIdx.x / tiles_x;
+    const int x0 = (blockIdx.x - outer * tiles_x) * LINES;
+    nl = (nx - x0) < LINES ? (nx - x0) : LINES;
+    if (AXIS == 1) {
+      base = (size_t)outer * N * nx + x0;
+      istride = nx;
+    } else {
+      const int p = outer / ny;
+      const int y = outer - p * ny;
+      base = ((size_t)p * N * ny + y) * nx + x0;
+      istride = (size_t)ny * nx;
+    }
+  }
+  const int total = nl * N;
+  C v[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int f = threadIdx.x + e * kFftThreads;
+    if (f < total) {
+      if (AXIS == 0) v[e] = data[base + f];
+      else {
+        const int i = f / nl, b = f - i * nl;
+        v[e] = data[base + b + i * istride];
+      }
+    }
+  }
+  __syncthreads();   // twiddles visible
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int f = threadIdx.x + e * kFftThreads;
+    if (f < total) {
+      int b, i;
+      if (AXIS == 0) { b = f / N; i = f - b * N; }
+      else { i = f / nl; b = f - i * nl; }
+      buf[Lds<N>::at(b, i)] = forward ? cmul(v[e], tw2[i]) : v[e];
+    }
+  }
+  __syncthreads();
+  passes_from<0, 1, N, LINES>(buf, nl, tw2, forward ? S(-1) : S(1));
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int f = threadIdx.x + e * kFftThreads;
+    if (f < total) {
+      int b, i;
+      if (AXIS == 0) { b = f / N; i = f - b * N; }
+      else { i = f / nl; b = f - i * nl; }
+      C o = buf[Lds<N>::at(b, i)];
+      if (!forward) o = cmulc(o, tw2[i]);
+      if (AXIS == 0) data[base + f] = o;
+      else data[base + b + i * istride] = o;
+    }
+  }
+}
+
 }  // namespace rism

@@ -1,0 +1,255 @@
+// Fused iteration kernels for grids whose x length has a fixed-size FFT plan:
+//   k_update_fftx    MDIIS update + closure (steps 6 and 2) fused with the
+//                    forward x-axis transform of step 3;
+//   k_fftx_residual  inverse x-axis transform of step 5 fused with the
+//                    residual (Eq 33) and the MDIIS Gram row.
+// Each saves one full read and write of the packed spectra per iteration.
+#pragma once
+
+#include <type_traits>
+
+#include "fft.hpp"
+#include "iterate.hpp"
+
+namespace rism {
+
+template <bool ANCHOR>
+using PrecC = typename std::conditional<ANCHOR, double2, float2>::type;
+
+template <bool ANCHOR, int N>
+__global__ __launch_bounds__(kFftThreads) void k_update_fftx(
+    const IterState* __restrict__ st, const float* __restrict__ tau0, float* __restrict__ tau_hist,
+    const float* __restrict__ res_hist, const float* __restrict__ w,
+    const float* __restrict__ tau_ref, float* __restrict__ dg_out, void* __restrict__ spec_v,
+    int ny, int nz, int nv, int npair, int M, int kind, int order,
+    const PrecC<ANCHOR>* __restrict__ tw2_g) {
+  using C = PrecC<ANCHOR>;
+  using S = typename ScalarOf<C>::type;
+  constexpr int LINES = fixed_lines<C, N, 0>();
+  constexpr int Q = N / 4;
+  if (st->done) return;
+  __shared__ C buf[LINES * Lds<N>::PITCH];
+  __shared__ C tw2[2 * N];
+  for (int i = threadIdx.x; i < 2 * N; i += kFftThreads) tw2[i] = tw2_g[i];
+  const size_t plane = (size_t)nz * ny;
+  const size_t rows = (size_t)npair * plane;
+  const size_t row0 = (size_t)blockIdx.x * LINES;
+  if (row0 >= rows) return;
+  const int nl = (int)((rows - row0) < (size_t)LINES ? (rows - row0) : (size_t)LINES);
+  const size_t N3 = (size_t)N * plane;
+  const UpdateCtl u = load_update_ctl(st, M);
+  __syncthreads();
+  for (int t = threadIdx.x; t < nl * Q; t += kFftThreads) {
+    const int b = t / Q;
+    const int i0 = (t - b * Q) * 4;
+    const size_t row = row0 + b;
+    const int p = (int)(row / plane);
+    const size_t n = (row - (size_t)p * plane) * N + i0;
+    double o64[2][4];
+    float o32[2][4];
+    update_points<ANCHOR, 4>(u, tau0, tau_hist, res_hist, w, tau_ref, dg_out, N3, nv, p, n, kind,
+                             order, o64, o32);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const C val = ANCHOR ? make_c((S)o64[0][v], (S)o64[1][v]) : make_c((S)o32[0][v], (S)o32[1][v]);
+      buf[Lds<N>::at(b, i0 + v)] = cmul(val, tw2[i0 + v]);   // exp(-i pi a / n)
+    }
+  }
+  __syncthreads();
+  passes_from<0, 1, N, LINES>(buf, nl, tw2, S(-1));
+  C* spec = static_cast<C*>(spec_v) + row0 * N;
+  for (int f = threadIdx.x; f < nl * N; f += kFftThreads) {
+    const int b = f / N, i = f - b * N;
+    spec[f] = buf[Lds<N>::at(b, i)];
+  }
+}
+
+template <bool ANCHOR, int N>
+__global__ __launch_bounds__(kFftThreads) void k_fftx_residual(
+    const IterState* __restrict__ st, const void* __restrict__ spec_v,
+    const float* __restrict__ w, const float* __restrict__ tau_hist, float* __restrict__ res_hist,
+    float* __restrict__ tau_ref, float* __restrict__ r_ref, const float* __restrict__ dg, int ny,
+    int nz, int nv, int npair, int M, int kind, int order, const PrecC<ANCHOR>* __restrict__ tw2_g,
+    double* __restrict__ partials) {
+  using C = PrecC<ANCHOR>;
+  using S = typename ScalarOf<C>::type;
+  constexpr int LINES = fixed_lines<C, N, 0>();
+  constexpr int Q = N / 4;
+  if (st->done) return;
+  __shared__ C buf[LINES * Lds<N>::PITCH];
+  __shared__ C tw2[2 * N];
+  __shared__ double red[kFftThreads / 64];
+  for (int i = threadIdx.x; i < 2 * N; i += kFftThreads) tw2[i] = tw2_g[i];
+  const size_t plane = (size_t)nz * ny;
+  const size_t rows = (size_t)npair * plane;
+  const size_t row0 = (size_t)blockIdx.x * LINES;
+  const int nl = (int)((rows - row0) < (size_t)LINES ? (rows - row0) : (size_t)LINES);
+  const size_t N3 = (size_t)N * plane;
+  const int dest = st->dest;
+  const unsigned mask = other_slots(st, M, dest);
+  const C* spec = static_cast<const C*>(spec_v) + row0 * N;
+  for (int f = threadIdx.x; f < nl * N; f += kFftThreads) {
+    const int b = f / N, i = f - b * N;
+    buf[Lds<N>::at(b, i)] = spec[f];
+  }
+  __syncthreads();
+  passes_from<0, 1, N, LINES>(buf, nl, tw2, S(1));
+  double acc[kMaxDepth + 1];
+#pragma unroll
+  for (int i = 0; i <= kMaxDepth; ++i) acc[i] = 0.0;
+  for (int t = threadIdx.x; t < nl * Q; t += kFftThreads) {
+    const int b = t / Q;
+    const int i0 = (t - b * Q) * 4;
+    const size_t row = row0 + b;
+    const int p = (int)(row / plane);
+    const size_t n = (row - (size_t)p * plane) * N + i0;
+    float hre[4], him[4];
+    double h64[2][4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const C h = cmulc(buf[Lds<N>::at(b, i0 + v)], tw2[i0 + v]);   // exp(+i pi a / n)
+      hre[v] = (float)h.x;
+      him[v] = (float)h.y;
+      h64[0][v] = (double)h.x;
+      h64[1][v] = (double)h.y;
+    }
+    residual_points<ANCHOR, 4>(hre, him, h64, w, tau_hist, res_hist, tau_ref, r_ref, dg, N3, nv,
+                               p, n, dest, mask, kind, order, acc);
+  }
+  write_partials(acc, M, partials, red);
+}
+
+}  // namespace rism
+
+namespace rism {
+
+// ---------------------------------------------------------------------------
+// k_zcz: forward z transform + k-space contraction (Eq 13, Eq 32) + inverse z
+// transform in one pass over the packed spectra.  A workgroup owns, for every
+// site pair, the z-columns (x0..x0+B-1, y) and their mirror columns
+// (nx-1-x, ny-1-y), so each k-point meets its partner -k on chip.  Requires an
+// even ny (columns y < ny/2 pair with y' = ny-1-y >= ny/2).
+// ---------------------------------------------------------------------------
+template <typename C, int NZ, int NV>
+constexpr int zcz_cols() {
+  // largest B (<= 16) with the 2 * P * B columns of NZ in ~64 KB of LDS
+  constexpr int P = (NV + 1) / 2;
+  constexpr int per_col = 2 * P * Lds<NZ>::PITCH * (int)sizeof(C);
+  return per_col * 16 <= 65536 ? 16 : per_col * 8 <= 65536 ? 8 : per_col * 4 <= 65536 ? 4 : 2;
+}
+
+template <typename C, int NZ, int NV, bool WITHF>
+__global__ __launch_bounds__(kFftThreads) void k_zcz(
+    C* __restrict__ spec, int nx, int ny, const C* __restrict__ tw2_g, float dkx, float dky,
+    float dkz, const C* __restrict__ F, const typename ScalarOf<C>::type* __restrict__ chi,
+    const typename ScalarOf<C>::type* __restrict__ qtab, float inv_dkt, int m_tab,
+    const int* __restrict__ done) {
+  using S = typename ScalarOf<C>::type;
+  constexpr int P = (NV + 1) / 2;
+  constexpr int B = zcz_cols<C, NZ, NV>();
+  constexpr int LINES = 2 * P * B;     // line l = (side * P + p) * B + b
+  if (*done) return;
+  __shared__ C buf[LINES * Lds<NZ>::PITCH];
+  __shared__ C tw2[2 * NZ];
+  for (int i = threadIdx.x; i < 2 * NZ; i += kFftThreads) tw2[i] = tw2_g[i];
+  const int tiles_x = (nx + B - 1) / B;
+  const int jy = blockIdx.x / tiles_x;                 // 0 .. ny/2 - 1
+  const int x0 = (blockIdx.x - jy * tiles_x) * B;
+  const int nb = (nx - x0) < B ? (nx - x0) : B;
+  const int jy2 = ny - 1 - jy;
+  const size_t N = (size_t)nx * ny * NZ;
+  const size_t zs = (size_t)nx * ny;
+  // element (l, z) <-> global address; side 1 columns run backwards in x
+  auto addr = [&](int side, int p, int b, int z) -> size_t {
+    const int x = side ? nx - 1 - (x0 + b) : x0 + b;
+    return (size_t)p * N + (size_t)z * zs + (size_t)(side ? jy2 : jy) * nx + x;
+  };
+  const int total = 2 * P * nb * NZ;
+  __syncthreads();
+  for (int f = threadIdx.x; f < total; f += kFftThreads) {
+    const int b = f % nb;
+    const int r = f / nb;                // (side, p, z) with z fastest after b
+    const int z = r % NZ;
+    const int sp = r / NZ;               // side * P + p
+    const int side = sp / P, p = sp - side * P;
+    const C v = spec[addr(side, p, b, z)];
+    buf[Lds<NZ>::at(sp * B + b, z)] = cmul(v, tw2[z]);
+  }
+  __syncthreads();
+  // forward z passes over all 2 P B lines (unused tail lines carry stale data and are not stored)
+  passes_from<0, 1, NZ, LINES>(buf, LINES, tw2, S(-1));
+
+  // contraction: (b, jz) on side 0 with its mirror (b, NZ-1-jz) on side 1
+  for (int t = threadIdx.x; t < nb * NZ; t += kFftThreads) {
+    const int b = t / NZ;
+    const int jz = t - b * NZ;
+    const int jx = x0 + b;
+    const float kx = (2 * jx < nx) ? (jx + 0.5f) * dkx : (jx + 0.5f - nx) * dkx;
+    const float ky = (2 * jy < ny) ? (jy + 0.5f) * dky : (jy + 0.5f - ny) * dky;
+    const float kz = (2 * jz < NZ) ? (jz + 0.5f) * dkz : (jz + 0.5f - NZ) * dkz;
+    const float kmag = sqrtf(kx * kx + ky * ky + kz * kz);
+    const float xk = kmag * inv_dkt;
+    int m;
+    S fr;
+    if (xk >= (float)(m_tab - 1)) {
+      m = m_tab - 2;
+      fr = S(1);
+    } else {
+      m = (int)xk;
+      fr = (S)(xk - (float)m);
+    }
+    C X[NV];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const C z = buf[Lds<NZ>::at(p * B + b, jz)];
+      const C zb = buf[Lds<NZ>::at((P + p) * B + b, NZ - 1 - jz)];
+      X[2 * p] = make_c(S(0.5) * (z.x + zb.x), S(0.5) * (z.y - zb.y));
+      if (2 * p + 1 < NV) X[2 * p + 1] = make_c(S(0.5) * (z.y + zb.y), S(-0.5) * (z.x - zb.x));
+    }
+    C Fk = make_c(S(0), S(0));
+    if (WITHF) {
+      // F is stored for the first half of the linear k index; the second half is conjugate
+      const size_t L = ((size_t)jz * ny + jy) * nx + jx;
+      const size_t Lb = N - 1 - L;
+      Fk = L < (N + 1) / 2 ? F[L] : cconj(F[Lb]);
+    }
+    const S* c0 = chi + (size_t)m * NV * NV;
+    const S* c1 = c0 + NV * NV;
+    C H[NV];
+#pragma unroll
+    for (int g = 0; g < NV; ++g) {
+      C acc = make_c(S(0), S(0));
+      if (WITHF) {
+        const S* q0 = qtab + (size_t)m * NV;
+        const S Q = q0[g] + fr * (q0[NV + g] - q0[g]);
+        acc = make_c(-Fk.x * Q, -Fk.y * Q);
+      }
+#pragma unroll
+      for (int gp = 0; gp < NV; ++gp) {
+        const S c = c0[gp * NV + g] + fr * (c1[gp * NV + g] - c0[gp * NV + g]);
+        acc.x += X[gp].x * c;
+        acc.y += X[gp].y * c;
+      }
+      H[g] = acc;
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const C a = H[2 * p];
+      const C bb = (2 * p + 1 < NV) ? H[2 * p + 1] : make_c(S(0), S(0));
+      buf[Lds<NZ>::at(p * B + b, jz)] = make_c(a.x - bb.y, a.y + bb.x);
+      buf[Lds<NZ>::at((P + p) * B + b, NZ - 1 - jz)] = make_c(a.x + bb.y, -a.y + bb.x);
+    }
+  }
+  __syncthreads();
+  passes_from<0, 1, NZ, LINES>(buf, LINES, tw2, S(1));
+  for (int f = threadIdx.x; f < total; f += kFftThreads) {
+    const int b = f % nb;
+    const int r = f / nb;
+    const int z = r % NZ;
+    const int sp = r / NZ;
+    const int side = sp / P, p = sp - side * P;
+    spec[addr(side, p, b, z)] = cmulc(buf[Lds<NZ>::at(sp * B + b, z)], tw2[z]);
+  }
+}
+
+}  // namespace rism

@@ -52,6 +52,7 @@ __global__ void k_init_state(IterState* st, float eta, int warm) {
   st->warm = warm;
   st->last_rms = 0.0;
   st->last_rr = 0.0;
+  st->ticket = 0;
 }
 
 __global__ void k_mark_prepared(IterState* st) {
@@ -71,57 +72,156 @@ __global__ void k_mark_prepared(IterState* st) {
 // the anchor, with dg kept for the residual.  Two sites share one complex grid
 // (site 2p real part, site 2p+1 imaginary part).
 // ---------------------------------------------------------------------------
-template <bool ANCHOR>
+// V consecutive floats (V = 4: one 16-byte access).
+template <int V>
+__device__ inline void ldv(const float* __restrict__ p, float* o) {
+  if constexpr (V == 4) {
+    const float4 t = *reinterpret_cast<const float4*>(p);
+    o[0] = t.x; o[1] = t.y; o[2] = t.z; o[3] = t.w;
+  } else {
+#pragma unroll
+    for (int i = 0; i < V; ++i) o[i] = p[i];
+  }
+}
+template <int V>
+__device__ inline void stv(float* __restrict__ p, const float* v) {
+  if constexpr (V == 4) {
+    *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < V; ++i) p[i] = v[i];
+  }
+}
+
+// Per-workgroup copy of what the update needs from the state.
+struct UpdateCtl {
+  float cf[kMaxDepth];
+  float eta;
+  int dest, newest, first, M;
+};
+
+__device__ inline UpdateCtl load_update_ctl(const IterState* __restrict__ st, int M) {
+  UpdateCtl u;
+#pragma unroll
+  for (int i = 0; i < kMaxDepth; ++i) u.cf[i] = i < M ? st->coef[i] : 0.0f;
+  u.eta = st->eta;
+  u.dest = st->dest;
+  u.newest = st->newest;
+  u.first = st->iter == 0;
+  u.M = M;
+  return u;
+}
+
+// The update + closure of V consecutive points n.. of pair p: stores the new tau
+// (and dg in the FP32 path) and returns the two sites' FFT inputs.
+// ANCHOR: c_sr = g - 1 - tau (FP64).  Otherwise dc = dg - delta.
+template <bool ANCHOR, int V>
+__device__ inline void update_points(const UpdateCtl& u, const float* __restrict__ tau0,
+                                     float* __restrict__ tau_hist,
+                                     const float* __restrict__ res_hist,
+                                     const float* __restrict__ w,
+                                     const float* __restrict__ tau_ref, float* __restrict__ dg_out,
+                                     size_t N, int nv, int p, size_t n, int kind, int order,
+                                     double (*o64)[V], float (*o32)[V]) {
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      o64[s][v] = 0.0;
+      o32[s][v] = 0.0f;
+    }
+  for (int s = 0; s < 2; ++s) {
+    const int g = 2 * p + s;
+    if (g >= nv) break;
+    const size_t gn = (size_t)g * N + n;
+    float tau[V];
+    if (u.first) {
+      if (tau0) ldv<V>(tau0 + gn, tau);
+      else
+#pragma unroll
+        for (int v = 0; v < V; ++v) tau[v] = 0.0f;
+    } else {
+      float tb[V], dt[V], dr[V];
+      ldv<V>(tau_hist + (size_t)u.newest * nv * N + gn, tb);
+#pragma unroll
+      for (int v = 0; v < V; ++v) dt[v] = dr[v] = 0.0f;
+#pragma unroll
+      for (int i = 0; i < kMaxDepth; ++i) {
+        const float c = u.cf[i];   // zero beyond M and for unused slots
+        if (c != 0.0f) {
+          float ti[V], ri[V];
+          ldv<V>(tau_hist + (size_t)i * nv * N + gn, ti);
+          ldv<V>(res_hist + (size_t)i * nv * N + gn, ri);
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            dt[v] += c * (ti[v] - tb[v]);
+            dr[v] += c * ri[v];
+          }
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < V; ++v) tau[v] = tb[v] + (dt[v] + u.eta * dr[v]);
+    }
+    stv<V>(tau_hist + (size_t)u.dest * nv * N + gn, tau);
+    float wv[V];
+    ldv<V>(w + gn, wv);
+    if (ANCHOR) {
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const double d = -(double)wv[v] + (double)tau[v];
+        o64[s][v] = closure_g(d, kind, order) - 1.0 - (double)tau[v];
+      }
+    } else {
+      float tr[V], dg[V];
+      ldv<V>(tau_ref + gn, tr);
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const float delta = tau[v] - tr[v];
+        dg[v] = closure_dg(-wv[v] + tr[v], delta, kind, order);
+        o32[s][v] = dg[v] - delta;
+      }
+      stv<V>(dg_out + gn, dg);
+    }
+  }
+}
+
+template <bool ANCHOR, int V>
 __global__ __launch_bounds__(kElemThreads) void k_update_closure(
     const IterState* __restrict__ st, const float* __restrict__ tau0, float* __restrict__ tau_hist,
     const float* __restrict__ res_hist, const float* __restrict__ w,
     const float* __restrict__ tau_ref, float* __restrict__ dg_out, void* __restrict__ spec,
     size_t N, int nv, int npair, int M, int kind, int order) {
   if (st->done) return;
-  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (size_t)npair * N) return;
-  const int p = (int)(idx / N);
-  const size_t n = idx - (size_t)p * N;
-  const bool first = st->iter == 0;
-  const int dest = st->dest;
-  const int b = st->newest;
-  const float eta = st->eta;
-  double o64[2] = {0.0, 0.0};
-  float o32[2] = {0.0f, 0.0f};
-  for (int s = 0; s < 2; ++s) {
-    const int g = 2 * p + s;
-    if (g >= nv) break;
-    float tau = 0.0f;
-    if (first) {
-      if (tau0) tau = tau0[(size_t)g * N + n];
-    } else {
-      const float tb = tau_hist[((size_t)b * nv + g) * N + n];
-      float dt = 0.0f, dr = 0.0f;
-      for (int i = 0; i < M; ++i) {
-        const float c = st->coef[i];
-        if (c != 0.0f) {
-          const size_t o = ((size_t)i * nv + g) * N + n;
-          dt += c * (tau_hist[o] - tb);
-          dr += c * res_hist[o];
-        }
-      }
-      tau = tb + (dt + eta * dr);
+  const size_t NQ = N / V;
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (size_t)npair * NQ) return;
+  const int p = (int)(q / NQ);
+  const size_t n = (q - (size_t)p * NQ) * V;
+  const UpdateCtl u = load_update_ctl(st, M);
+  double o64[2][V];
+  float o32[2][V];
+  update_points<ANCHOR, V>(u, tau0, tau_hist, res_hist, w, tau_ref, dg_out, N, nv, p, n, kind,
+                           order, o64, o32);
+  const size_t o = (size_t)p * N + n;
+  if (ANCHOR) {
+    double2* sp = static_cast<double2*>(spec) + o;
+#pragma unroll
+    for (int v = 0; v < V; ++v) sp[v] = make_double2(o64[0][v], o64[1][v]);
+  } else {
+    float* sp = reinterpret_cast<float*>(static_cast<float2*>(spec) + o);
+    float pk[2 * V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      pk[2 * v] = o32[0][v];
+      pk[2 * v + 1] = o32[1][v];
     }
-    tau_hist[((size_t)dest * nv + g) * N + n] = tau;
-    const size_t gn = (size_t)g * N + n;
-    if (ANCHOR) {
-      const double d = -(double)w[gn] + (double)tau;
-      o64[s] = closure_g(d, kind, order) - 1.0 - (double)tau;
+    if constexpr (V == 4) {
+      stv<4>(sp, pk);
+      stv<4>(sp + 4, pk + 4);
     } else {
-      const float tr = tau_ref[gn];
-      const float delta = tau - tr;
-      const float dg = closure_dg(-w[gn] + tr, delta, kind, order);
-      dg_out[gn] = dg;
-      o32[s] = dg - delta;
+      stv<2 * V>(sp, pk);
     }
   }
-  if (ANCHOR) static_cast<double2*>(spec)[idx] = make_double2(o64[0], o64[1]);
-  else static_cast<float2*>(spec)[idx] = make_float2(o32[0], o32[1]);
 }
 
 // ---------------------------------------------------------------------------
@@ -225,7 +325,77 @@ __device__ inline double block_sum(double v, double* lds) {
   return s;
 }
 
-template <bool ANCHOR>
+// The residual of V consecutive points n.. of pair p from the transformed
+// values h (hre/him in FP32, h64 in FP64), accumulated into the Gram partials.
+template <bool ANCHOR, int V>
+__device__ inline void residual_points(const float* hre, const float* him, const double (*h64)[V],
+                                       const float* __restrict__ w,
+                                       const float* __restrict__ tau_hist,
+                                       float* __restrict__ res_hist, float* __restrict__ tau_ref,
+                                       float* __restrict__ r_ref, const float* __restrict__ dg,
+                                       size_t N, int nv, int p, size_t n, int dest, unsigned mask,
+                                       int kind, int order, double* acc) {
+  for (int s = 0; s < 2; ++s) {
+    const int g = 2 * p + s;
+    if (g >= nv) break;
+    const size_t gn = (size_t)g * N + n;
+    const size_t od = (size_t)dest * nv * N + gn;
+    float R[V];
+    if (ANCHOR) {
+      float tau[V], wv[V];
+      ldv<V>(tau_hist + od, tau);
+      ldv<V>(w + gn, wv);
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const double gg = closure_g(-(double)wv[v] + (double)tau[v], kind, order);
+        R[v] = (float)(h64[s][v] + 1.0 - gg);
+      }
+      stv<V>(tau_ref + gn, tau);
+      stv<V>(r_ref + gn, R);
+    } else {
+      float rr[V], dd[V];
+      ldv<V>(r_ref + gn, rr);
+      ldv<V>(dg + gn, dd);
+#pragma unroll
+      for (int v = 0; v < V; ++v) R[v] = rr[v] + ((s ? him[v] : hre[v]) - dd[v]);
+    }
+    stv<V>(res_hist + od, R);
+#pragma unroll
+    for (int v = 0; v < V; ++v) acc[kMaxDepth] += (double)R[v] * (double)R[v];
+#pragma unroll
+    for (int i = 0; i < kMaxDepth; ++i) {
+      if (mask & (1u << i)) {
+        float ri[V];
+        ldv<V>(res_hist + (size_t)i * nv * N + gn, ri);
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[i] += (double)R[v] * (double)ri[v];
+      }
+    }
+  }
+}
+
+__device__ inline unsigned other_slots(const IterState* __restrict__ st, int M, int dest) {
+  unsigned mask = 0;
+  for (int i = 0; i < M; ++i)
+    if (st->stored[i] && i != dest) mask |= 1u << i;
+  return mask;
+}
+
+// Write this block's partial sums (fixed block order, reduced in fixed order).
+__device__ inline void write_partials(const double* acc, int M, double* __restrict__ partials,
+                                      double* red) {
+#pragma unroll
+  for (int i = 0; i < kMaxDepth; ++i) {
+    if (i < M) {   // M is uniform: every thread takes the same branches
+      const double s = block_sum(acc[i], red);
+      if (threadIdx.x == 0) partials[(size_t)blockIdx.x * (M + 1) + i] = s;
+    }
+  }
+  const double s = block_sum(acc[kMaxDepth], red);
+  if (threadIdx.x == 0) partials[(size_t)blockIdx.x * (M + 1) + M] = s;
+}
+
+template <bool ANCHOR, int V>
 __global__ __launch_bounds__(kRedThreads) void k_residual(
     const IterState* __restrict__ st, const void* __restrict__ spec, const float* __restrict__ w,
     const float* __restrict__ tau_hist, float* __restrict__ res_hist, float* __restrict__ tau_ref,
@@ -234,134 +404,113 @@ __global__ __launch_bounds__(kRedThreads) void k_residual(
   if (st->done) return;
   __shared__ double red[kRedThreads / 64];
   const int dest = st->dest;
-  unsigned mask = 0;
-  for (int i = 0; i < M; ++i)
-    if (st->stored[i] && i != dest) mask |= 1u << i;
+  const unsigned mask = other_slots(st, M, dest);
   double acc[kMaxDepth + 1];
 #pragma unroll
   for (int i = 0; i <= kMaxDepth; ++i) acc[i] = 0.0;
-  const size_t total = (size_t)npair * N;
-  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (size_t)gridDim.x * blockDim.x) {
-    const int p = (int)(idx / N);
-    const size_t n = idx - (size_t)p * N;
-    double2 h64 = make_double2(0.0, 0.0);
-    float2 h32 = make_float2(0.0f, 0.0f);
-    if (ANCHOR) h64 = static_cast<const double2*>(spec)[idx];
-    else h32 = static_cast<const float2*>(spec)[idx];
-    for (int s = 0; s < 2; ++s) {
-      const int g = 2 * p + s;
-      if (g >= nv) break;
-      const size_t gn = (size_t)g * N + n;
-      const size_t od = (size_t)dest * nv * N + gn;
-      float R;
-      if (ANCHOR) {
-        const float tau = tau_hist[od];
-        const double gg = closure_g(-(double)w[gn] + (double)tau, kind, order);
-        R = (float)((s ? h64.y : h64.x) + 1.0 - gg);
-        tau_ref[gn] = tau;
-        r_ref[gn] = R;
-      } else {
-        R = r_ref[gn] + ((s ? h32.y : h32.x) - dg[gn]);
-      }
-      res_hist[od] = R;
-      acc[kMaxDepth] += (double)R * (double)R;
+  const size_t NQ = N / V;
+  const size_t total = (size_t)npair * NQ;
+  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+       q += (size_t)gridDim.x * blockDim.x) {
+    const int p = (int)(q / NQ);
+    const size_t n = (q - (size_t)p * NQ) * V;
+    const size_t o = (size_t)p * N + n;
+    float hre[V], him[V];
+    double h64[2][V];
+    if (ANCHOR) {
+      const double2* sp = static_cast<const double2*>(spec) + o;
 #pragma unroll
-      for (int i = 0; i < kMaxDepth; ++i) {
-        if (mask & (1u << i)) acc[i] += (double)R * (double)res_hist[(size_t)i * nv * N + gn];
+      for (int v = 0; v < V; ++v) {
+        const double2 t = sp[v];
+        h64[0][v] = t.x;
+        h64[1][v] = t.y;
+      }
+    } else {
+      const float* sp = reinterpret_cast<const float*>(static_cast<const float2*>(spec) + o);
+      float pk[2 * V];
+      if constexpr (V == 4) {
+        ldv<4>(sp, pk);
+        ldv<4>(sp + 4, pk + 4);
+      } else {
+        ldv<2 * V>(sp, pk);
+      }
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        hre[v] = pk[2 * v];
+        him[v] = pk[2 * v + 1];
       }
     }
+    residual_points<ANCHOR, V>(hre, him, h64, w, tau_hist, res_hist, tau_ref, r_ref, dg, N, nv, p,
+                               n, dest, mask, kind, order, acc);
   }
-  for (int i = 0; i < M; ++i) {
-    const double s = block_sum(acc[i], red);
-    if (threadIdx.x == 0) partials[(size_t)blockIdx.x * (M + 1) + i] = s;
-  }
-  const double s = block_sum(acc[kMaxDepth], red);
-  if (threadIdx.x == 0) partials[(size_t)blockIdx.x * (M + 1) + M] = s;
+  write_partials(acc, M, partials, red);
 }
 
-// ---------------------------------------------------------------------------
-// Step 6-7 control (one workgroup): reduce the partials in fixed order, RMS
-// (Eq 41 as a true root-mean-square), convergence / failure flags, the ring of
-// MDIIS pairs, the FP64 bordered Gram solve (Lagrange multiplier for
-// sum c_i = 1) with partial pivoting, restarts, the next coefficients.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kRedThreads) void k_control(
-    IterState* __restrict__ st, const double* __restrict__ partials, int nblocks, int M,
-    double inv_count, double tol, int max_iter, float eta_static, int eta_dynamic) {
-  if (st->done) return;
-  __shared__ double red[kRedThreads / 64];
-  __shared__ double sums[kMaxDepth + 1];
-  for (int q = 0; q <= M; ++q) {
-    double v = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) v += partials[(size_t)b * (M + 1) + q];
-    const double s = block_sum(v, red);
-    if (threadIdx.x == 0) sums[q] = s;
-  }
-  __syncthreads();
-  if (threadIdx.x != 0) return;
-
-  const int dest = st->dest;
+// One control step on a (shared-memory) copy of the state; single thread.
+__device__ inline void control_step(IterState& st, const double* sums,
+                                    double (*A)[kMaxDepth + 2], int M, double inv_count,
+                                    double tol, int max_iter, float eta_static, int eta_dynamic) {
+  const int dest = st.dest;
   const double rr = sums[M];
   const double rms = sqrt(rr * inv_count);
-  st->iter += 1;
-  st->last_rms = rms;
-  st->last_rr = rr;
+  st.iter += 1;
+  st.last_rms = rms;
+  st.last_rr = rr;
   if (!(rr == rr) || rr > 1.0e300) {
-    st->status = RISM3D_E_NONFINITE;
-    st->final_slot = dest;
-    st->done = 1;
+    st.status = RISM3D_E_NONFINITE;
+    st.final_slot = dest;
+    st.done = 1;
     return;
   }
   if (rms < tol) {
-    st->converged = 1;
-    st->final_slot = dest;
-    st->done = 1;
+    st.converged = 1;
+    st.final_slot = dest;
+    st.done = 1;
     return;
   }
-  if (st->iter >= max_iter) {
-    st->status = RISM3D_E_NOCONV;
-    st->final_slot = dest;
-    st->done = 1;
+  if (st.iter >= max_iter) {
+    st.status = RISM3D_E_NOCONV;
+    st.final_slot = dest;
+    st.done = 1;
     return;
   }
   // The destination slot's old pair (the oldest, when the ring was full) has
   // been overwritten by the new iterate: drop it.
-  st->stored[dest] = 0;
+  st.stored[dest] = 0;
   int best = -1;
   double best_rms = 0.0;
   for (int i = 0; i < M; ++i) {
-    if (st->stored[i] && (best < 0 || st->rms_slot[i] < best_rms)) {
+    if (st.stored[i] && (best < 0 || st.rms_slot[i] < best_rms)) {
       best = i;
-      best_rms = st->rms_slot[i];
+      best_rms = st.rms_slot[i];
     }
   }
   if (best >= 0 && rms > 10.0 * best_rms) {
-    for (int i = 0; i < M; ++i) st->stored[i] = (i == best);
-    st->newest = best;
-    st->restarts += 1;
+    for (int i = 0; i < M; ++i) st.stored[i] = (i == best);
+    st.newest = best;
+    st.restarts += 1;
   } else {
-    st->stored[dest] = 1;
-    st->newest = dest;
-    st->rms_slot[dest] = rms;
-    st->stamp[dest] = ++st->stamp_counter;
+    st.stored[dest] = 1;
+    st.newest = dest;
+    st.rms_slot[dest] = rms;
+    st.stamp[dest] = ++st.stamp_counter;
     for (int i = 0; i < M; ++i) {
-      if (st->stored[i] && i != dest) {
-        st->gram[dest][i] = sums[i];
-        st->gram[i][dest] = sums[i];
+      if (st.stored[i] && i != dest) {
+        st.gram[dest][i] = sums[i];
+        st.gram[i][dest] = sums[i];
       }
     }
-    st->gram[dest][dest] = rr;
+    st.gram[dest][dest] = rr;
   }
   // Stored slots, oldest first.
   int slot[kMaxDepth];
   int m = 0;
   for (int i = 0; i < M; ++i)
-    if (st->stored[i]) slot[m++] = i;
+    if (st.stored[i]) slot[m++] = i;
   for (int a = 1; a < m; ++a) {
     const int v = slot[a];
     int b = a - 1;
-    while (b >= 0 && st->stamp[slot[b]] > st->stamp[v]) {
+    while (b >= 0 && st.stamp[slot[b]] > st.stamp[v]) {
       slot[b + 1] = slot[b];
       --b;
     }
@@ -372,33 +521,30 @@ __global__ __launch_bounds__(kRedThreads) void k_control(
   if (m == 1) {
     c[0] = 1.0;
   } else {
-    double A[kMaxDepth + 1][kMaxDepth + 1];
-    double rhs[kMaxDepth + 1];
+    // Bordered system [[B, -1], [-1^T, 0]] [c; lam] = [0; -1], B normalised by
+    // its largest diagonal; rhs kept in column n of A.
     double scale = 0.0;
-    for (int i = 0; i < m; ++i) scale = fmax(scale, st->gram[slot[i]][slot[i]]);
+    for (int i = 0; i < m; ++i) scale = fmax(scale, st.gram[slot[i]][slot[i]]);
     const int n = m + 1;
     for (int i = 0; i < m; ++i) {
-      for (int j = 0; j < m; ++j) A[i][j] = st->gram[slot[i]][slot[j]] / scale;
+      for (int j = 0; j < m; ++j) A[i][j] = st.gram[slot[i]][slot[j]] / scale;
       A[i][m] = -1.0;
       A[m][i] = -1.0;
-      rhs[i] = 0.0;
+      A[i][n] = 0.0;
     }
     A[m][m] = 0.0;
-    rhs[m] = -1.0;
+    A[m][n] = -1.0;
     double min_piv = 1.0e300;
     for (int col = 0; col < n && ok; ++col) {
       int piv = col;
       for (int r = col + 1; r < n; ++r)
         if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
       if (piv != col) {
-        for (int j = 0; j < n; ++j) {
+        for (int j = 0; j <= n; ++j) {
           const double t = A[col][j];
           A[col][j] = A[piv][j];
           A[piv][j] = t;
         }
-        const double t = rhs[col];
-        rhs[col] = rhs[piv];
-        rhs[piv] = t;
       }
       const double pv = A[col][col];
       min_piv = fmin(min_piv, fabs(pv));
@@ -408,50 +554,115 @@ __global__ __launch_bounds__(kRedThreads) void k_control(
       }
       for (int r = col + 1; r < n; ++r) {
         const double f = A[r][col] / pv;
-        for (int j = col; j < n; ++j) A[r][j] -= f * A[col][j];
-        rhs[r] -= f * rhs[col];
+        for (int j = col; j <= n; ++j) A[r][j] -= f * A[col][j];
       }
     }
     if (ok && min_piv >= 1.0e-12) {
-      double sol[kMaxDepth + 1];
       for (int r = n - 1; r >= 0; --r) {
-        double s = rhs[r];
-        for (int j = r + 1; j < n; ++j) s -= A[r][j] * sol[j];
-        sol[r] = s / A[r][r];
+        double s = A[r][n];
+        for (int j = r + 1; j < n; ++j) s -= A[r][j] * A[j][n];
+        A[r][n] = s / A[r][r];   // solution overwrites the rhs column
       }
-      for (int i = 0; i < m; ++i) c[i] = sol[i];
+      for (int i = 0; i < m; ++i) c[i] = A[i][n];
     } else {
       ok = false;
     }
     if (!ok) {   // ill-conditioned subspace: restart from the best stored pair
       int b = slot[0];
       for (int i = 1; i < m; ++i)
-        if (st->rms_slot[slot[i]] < st->rms_slot[b]) b = slot[i];
-      for (int i = 0; i < M; ++i) st->stored[i] = (i == b);
-      st->newest = b;
+        if (st.rms_slot[slot[i]] < st.rms_slot[b]) b = slot[i];
+      for (int i = 0; i < M; ++i) st.stored[i] = (i == b);
+      st.newest = b;
       slot[0] = b;
       m = 1;
       c[0] = 1.0;
-      st->restarts += 1;
+      st.restarts += 1;
     }
   }
-  for (int i = 0; i < M; ++i) st->coef[i] = 0.0f;
-  for (int i = 0; i < m; ++i) st->coef[slot[i]] = (float)c[i];
+  for (int i = 0; i < M; ++i) st.coef[i] = 0.0f;
+  for (int i = 0; i < m; ++i) st.coef[slot[i]] = (float)c[i];
   float eta = eta_static;
   if (eta_dynamic) eta = (float)fmin(fmax(-0.2 * log(rms), 0.1), 1.0);
-  st->eta = eta;
+  st.eta = eta;
   // Next destination: a free slot while the ring is not full, else the oldest.
   int next = -1;
   if (m < M) {
     for (int i = 0; i < M; ++i)
-      if (!st->stored[i]) {
+      if (!st.stored[i]) {
         next = i;
         break;
       }
   } else {
     next = slot[0];
   }
-  st->dest = next;
+  st.dest = next;
+}
+
+// Shared-memory scratch of the control step.
+struct ControlScratch {
+  IterState st;
+  double red[kRedThreads / 64];
+  double wsum[kRedThreads / 64][kMaxDepth + 1];
+  double sums[kMaxDepth + 1];
+  double A[kMaxDepth + 1][kMaxDepth + 2];
+};
+
+// Reduce the partials of `nblocks` blocks in fixed order and run one control
+// step on the state; all threads of the calling workgroup participate.
+__device__ inline void control_block(IterState* __restrict__ st_g,
+                                     const double* __restrict__ partials, int nblocks, int M,
+                                     double inv_count, double tol, int max_iter, float eta_static,
+                                     int eta_dynamic, ControlScratch& cs) {
+  {
+    const int* src = reinterpret_cast<const int*>(st_g);
+    int* dst = reinterpret_cast<int*>(&cs.st);
+    for (int i = threadIdx.x; i < (int)(sizeof(IterState) / sizeof(int)); i += blockDim.x)
+      dst[i] = src[i];
+  }
+  // Each thread sums its strided blocks for all M+1 quantities at once (loads
+  // in flight together), then one LDS pass combines the per-wave sums in
+  // fixed order.
+  double v[kMaxDepth + 1];
+#pragma unroll
+  for (int q = 0; q <= kMaxDepth; ++q) v[q] = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+    const double* pb = partials + (size_t)b * (M + 1);
+#pragma unroll
+    for (int q = 0; q <= kMaxDepth; ++q)
+      if (q <= M) v[q] += pb[q];
+  }
+#pragma unroll
+  for (int q = 0; q <= kMaxDepth; ++q) {
+    if (q <= M) {
+      for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_down(v[q], off, 64);
+      if ((threadIdx.x & 63) == 0) cs.wsum[threadIdx.x >> 6][q] = v[q];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x <= M) {
+    double t = 0.0;
+    for (int wv = 0; wv < (int)(blockDim.x >> 6); ++wv) t += cs.wsum[wv][threadIdx.x];
+    cs.sums[threadIdx.x] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    control_step(cs.st, cs.sums, cs.A, M, inv_count, tol, max_iter, eta_static, eta_dynamic);
+  __syncthreads();
+  {
+    const int* src = reinterpret_cast<const int*>(&cs.st);
+    int* dst = reinterpret_cast<int*>(st_g);
+    for (int i = threadIdx.x; i < (int)(sizeof(IterState) / sizeof(int)); i += blockDim.x)
+      dst[i] = src[i];
+  }
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_control(
+    IterState* __restrict__ st_g, const double* __restrict__ partials, int nblocks, int M,
+    double inv_count, double tol, int max_iter, float eta_static, int eta_dynamic) {
+  __shared__ ControlScratch cs;
+  if (st_g->done) return;
+  control_block(st_g, partials, nblocks, M, inv_count, tol, max_iter, eta_static, eta_dynamic,
+                cs);
 }
 
 // ---------------------------------------------------------------------------

@@ -16,6 +16,7 @@
 #include "common.hpp"
 #include "fft.hpp"
 #include "iterate.hpp"
+#include "fused.hpp"
 #include "setup.hpp"
 
 using namespace rism;
@@ -53,13 +54,18 @@ rism3d_status fail(rism3d_status s, const char* fmt, ...) {
 // Optional per-family kernel timing with HIP events (thread-local).
 // ---------------------------------------------------------------------------
 enum Family {
-  F_UPDATE32, F_UPDATE64, F_FFT32, F_FFT64, F_CONTRACT32, F_CONTRACT64, F_RESIDUAL32,
-  F_RESIDUAL64, F_CONTROL, F_POTENTIAL, F_FTILDE, F_SETUP, F_OUTPUT, F_SFE, F_COUNT
+  F_UPDATE32, F_UPDATE64, F_FFTX32, F_FFTY32, F_FFTZ32, F_FFTX64, F_FFTY64, F_FFTZ64,
+  F_CONTRACT32, F_CONTRACT64, F_RESIDUAL32, F_RESIDUAL64, F_CONTROL, F_UPDFFT32, F_UPDFFT64,
+  F_FFTRES32, F_FFTRES64, F_ZCZ32, F_ZCZ64, F_POTENTIAL, F_FTILDE, F_SETUP, F_OUTPUT, F_SFE,
+  F_COUNT
 };
 const char* const kFamilyNames[F_COUNT] = {
-    "update_closure_f32", "update_closure_f64", "fft_axis_f32", "fft_axis_f64",
-    "contract_f32", "contract_f64", "residual_gram_f32", "residual_gram_f64", "mdiis_control",
-    "potential", "long_range_spectrum", "setup_tables", "output", "free_energy"};
+    "update_closure_f32", "update_closure_f64", "fft_x_f32", "fft_y_f32", "fft_z_f32",
+    "fft_x_f64", "fft_y_f64", "fft_z_f64", "contract_f32", "contract_f64", "residual_gram_f32",
+    "residual_gram_f64", "mdiis_control", "update_fftx_f32", "update_fftx_f64",
+    "fftx_residual_f32", "fftx_residual_f64", "zfft_contract_f32", "zfft_contract_f64",
+    "potential", "long_range_spectrum",
+    "setup_tables", "output", "free_energy"};
 
 struct Timer {
   bool on = false;
@@ -176,9 +182,12 @@ rism3d_status make_layout(const rism3d_problem* pr, const rism3d_opts* op, Layou
     return fail(RISM3D_E_ARG, "invalid susceptibility table (n_k, dk, chi)");
   if (!(pr->temperature > 0.0)) return fail(RISM3D_E_ARG, "temperature must be > 0");
   if (!(pr->spacing > 0.0)) return fail(RISM3D_E_ARG, "spacing must be > 0");
-  if (!plan_axis(pr->nx, &L->px) || !plan_axis(pr->ny, &L->py) || !plan_axis(pr->nz, &L->pz))
+  if (!plan_axis(pr->nx, &L->px) || !plan_axis(pr->ny, &L->py) || !plan_axis(pr->nz, &L->pz) ||
+      (pr->nx | pr->ny | pr->nz) & 1)
     return fail(RISM3D_E_ARG,
-                "grid %dx%dx%d unsupported: each axis must be 2..%d with prime factors 2, 3, 5",
+                "grid %dx%dx%d unsupported: each axis must be even, 2..%d, with prime factors "
+                "2, 3, 5 (an odd axis has a self-mirrored half-integer frequency where the "
+                "analytic long-range spectrum is not Hermitian)",
                 pr->nx, pr->ny, pr->nz, kFftMaxN);
   if (op->closure != RISM3D_KH && op->closure != RISM3D_HNC && op->closure != RISM3D_PSE)
     return fail(RISM3D_E_ARG, "unknown closure %d", (int)op->closure);
@@ -236,7 +245,13 @@ rism3d_status make_layout(const rism3d_problem* pr, const rism3d_opts* op, Layou
   L->off_dg = take(nv * N * sizeof(float));
   L->off_spec = take((size_t)L->npair * N * sizeof(double2));   // float2 in the bulk iterations
   const size_t part_q = (size_t)((M + 1) > nv ? (M + 1) : nv);
-  L->off_part = take((size_t)kRedBlocks * part_q * sizeof(double));
+  size_t part_blocks = kRedBlocks;
+  if (fixed_fft_size(pr->nx)) {   // one partial row per workgroup of the fused residual
+    const size_t lines = (size_t)(2048 / pr->nx > 1 ? 2048 / pr->nx : 1);
+    const size_t b = ((size_t)L->npair * pr->nz * pr->ny + lines - 1) / lines;
+    if (b > part_blocks) part_blocks = b;
+  }
+  L->off_part = take(part_blocks * part_q * sizeof(double));
   const size_t na = pr->n_atoms > 0 ? (size_t)pr->n_atoms : 1;
   L->off_atoms = take(na * sizeof(double4));
   L->off_lj = take(na * nv * sizeof(double2));
@@ -346,49 +361,194 @@ void launch_contract(const Layout& L, void* ws, bool anchor, float inv_dkt, cons
   }
 }
 
+template <typename C, int N, int AXIS>
+void launch_fixed_n(const Layout& L, C* spec, const C* tw, int forward, const int* done,
+                    hipStream_t s) {
+  constexpr int LINES = fixed_lines<C, N, AXIS>();
+  unsigned grid;
+  if (AXIS == 0) {
+    const size_t rows = (size_t)L.npair * L.nz * L.ny;
+    grid = (unsigned)((rows + LINES - 1) / LINES);
+  } else {
+    const int tiles_x = (L.nx + LINES - 1) / LINES;
+    const int outer = AXIS == 1 ? L.npair * L.nz : L.npair * L.ny;
+    grid = (unsigned)outer * tiles_x;
+  }
+  hipLaunchKernelGGL((k_fft_fixed<C, N, AXIS>), dim3(grid), dim3(kFftThreads), 0, s, spec, L.nx,
+                     L.ny, L.nz, L.npair, tw, forward, done);
+}
+
+template <typename C, int AXIS>
+bool launch_fixed_axis(int n, const Layout& L, C* spec, const C* tw, int forward, const int* done,
+                       hipStream_t s) {
+  switch (n) {
+    case 32: launch_fixed_n<C, 32, AXIS>(L, spec, tw, forward, done, s); return true;
+    case 64: launch_fixed_n<C, 64, AXIS>(L, spec, tw, forward, done, s); return true;
+    case 96: launch_fixed_n<C, 96, AXIS>(L, spec, tw, forward, done, s); return true;
+    case 128: launch_fixed_n<C, 128, AXIS>(L, spec, tw, forward, done, s); return true;
+    case 192: launch_fixed_n<C, 192, AXIS>(L, spec, tw, forward, done, s); return true;
+    case 256: launch_fixed_n<C, 256, AXIS>(L, spec, tw, forward, done, s); return true;
+    case 512: launch_fixed_n<C, 512, AXIS>(L, spec, tw, forward, done, s); return true;
+    default: return false;
+  }
+}
+
+// One axis pass of the shifted transform over all packed pairs.
+template <typename C>
+void launch_axis(const Layout& L, C* spec, const C* const tw[3], int axis, int forward,
+                 const int* done, hipStream_t s) {
+  const bool f64 = std::is_same<C, double2>::value;
+  const AxisPlan& p = axis == 0 ? L.px : (axis == 1 ? L.py : L.pz);
+  TIMED((f64 ? F_FFTX64 : F_FFTX32) + axis, s);
+  bool ok = false;
+  if (fixed_fft_size(p.n)) {
+    if (axis == 0) ok = launch_fixed_axis<C, 0>(p.n, L, spec, tw[axis], forward, done, s);
+    else if (axis == 1) ok = launch_fixed_axis<C, 1>(p.n, L, spec, tw[axis], forward, done, s);
+    else ok = launch_fixed_axis<C, 2>(p.n, L, spec, tw[axis], forward, done, s);
+  }
+  if (ok) return;
+  const int lines = fft_lines_per_block<C>(axis, p.n, L.nx);
+  unsigned grid;
+  if (axis == 0) {
+    const size_t rows = (size_t)L.npair * L.nz * L.ny;
+    grid = (unsigned)((rows + lines - 1) / lines);
+  } else {
+    const int tiles_x = (L.nx + lines - 1) / lines;
+    const int outer = axis == 1 ? L.npair * L.nz : L.npair * L.ny;
+    grid = (unsigned)outer * tiles_x;
+  }
+  hipLaunchKernelGGL(k_fft_axis<C>, dim3(grid), dim3(kFftThreads), 0, s, spec, L.nx, L.ny, L.nz,
+                     L.npair, axis, p, tw[axis], forward, lines, done);
+}
+
 // Forward (forward != 0) or inverse 3D transform of all packed pairs, one
-// kernel per axis; C = float2 (bulk) or double2 (anchor).
+// kernel per axis; C = float2 (bulk) or double2 (anchor).  Common lengths use
+// the fixed-size kernels, others the generic runtime-plan kernel.
 template <typename C>
 void launch_fft3_on(const Layout& L, C* spec, const C* const tw[3], int forward, const int* done,
-                    hipStream_t s) {
+                    hipStream_t s, bool skip_x = false) {
   const int axes_fwd[3] = {0, 1, 2};
   const int axes_inv[3] = {2, 1, 0};
   for (int k = 0; k < 3; ++k) {
     const int axis = forward ? axes_fwd[k] : axes_inv[k];
-    const AxisPlan& p = axis == 0 ? L.px : (axis == 1 ? L.py : L.pz);
-    const int lines = fft_lines_per_block<C>(axis, p.n, L.nx);
-    unsigned grid;
-    if (axis == 0) {
-      const size_t rows = (size_t)L.npair * L.nz * L.ny;
-      grid = (unsigned)((rows + lines - 1) / lines);
-    } else {
-      const int tiles_x = (L.nx + lines - 1) / lines;
-      const int outer = axis == 1 ? L.npair * L.nz : L.npair * L.ny;
-      grid = (unsigned)outer * tiles_x;
-    }
-    {
-      TIMED((std::is_same<C, double2>::value ? F_FFT64 : F_FFT32), s);
-      hipLaunchKernelGGL(k_fft_axis<C>, dim3(grid), dim3(kFftThreads), 0, s, spec, L.nx, L.ny,
-                         L.nz, L.npair, axis, p, tw[axis], forward, lines, done);
-    }
+    if (skip_x && axis == 0) continue;
+    launch_axis(L, spec, tw, axis, forward, done, s);
   }
 }
 
 template <typename C>
-void launch_fft3(const Layout& L, void* ws, int forward, const int* done, hipStream_t s);
+void launch_fft3(const Layout& L, void* ws, int forward, const int* done, hipStream_t s,
+                 bool skip_x = false);
 
 template <>
-void launch_fft3<float2>(const Layout& L, void* ws, int forward, const int* done, hipStream_t s) {
+void launch_fft3<float2>(const Layout& L, void* ws, int forward, const int* done, hipStream_t s,
+                         bool skip_x) {
   const float2* tw[3] = {at<float2>(ws, L.off_tw32[0]), at<float2>(ws, L.off_tw32[1]),
                          at<float2>(ws, L.off_tw32[2])};
-  launch_fft3_on(L, at<float2>(ws, L.off_spec), tw, forward, done, s);
+  launch_fft3_on(L, at<float2>(ws, L.off_spec), tw, forward, done, s, skip_x);
 }
 
 template <>
-void launch_fft3<double2>(const Layout& L, void* ws, int forward, const int* done, hipStream_t s) {
+void launch_fft3<double2>(const Layout& L, void* ws, int forward, const int* done, hipStream_t s,
+                          bool skip_x) {
   const double2* tw[3] = {at<double2>(ws, L.off_tw64[0]), at<double2>(ws, L.off_tw64[1]),
                           at<double2>(ws, L.off_tw64[2])};
-  launch_fft3_on(L, at<double2>(ws, L.off_spec), tw, forward, done, s);
+  launch_fft3_on(L, at<double2>(ws, L.off_spec), tw, forward, done, s, skip_x);
+}
+
+// Fused z transform + contraction + inverse z transform.
+bool zcz_supported(const Layout& L) {
+  return (L.ny % 2) == 0 && (L.nz == 64 || L.nz == 96 || L.nz == 128 || L.nz == 256);
+}
+
+template <typename C, int NZ, int NV>
+void launch_zcz_n(const Layout& L, void* ws, float inv_dkt, const int* done, hipStream_t s) {
+  constexpr bool F64 = std::is_same<C, double2>::value;
+  constexpr int B = zcz_cols<C, NZ, NV>();
+  const int tiles_x = (L.nx + B - 1) / B;
+  const dim3 grid((unsigned)(L.ny / 2) * tiles_x), block(kFftThreads);
+  using S = typename ScalarOf<C>::type;
+  TIMED(F64 ? F_ZCZ64 : F_ZCZ32, s);
+  hipLaunchKernelGGL((k_zcz<C, NZ, NV, F64>), grid, block, 0, s, at<C>(ws, L.off_spec), L.nx,
+                     L.ny, at<C>(ws, F64 ? L.off_tw64[2] : L.off_tw32[2]), (float)L.dkx,
+                     (float)L.dky, (float)L.dkz, F64 ? at<C>(ws, L.off_F) : (const C*)nullptr,
+                     at<S>(ws, F64 ? L.off_chi64 : L.off_chi32),
+                     F64 ? at<S>(ws, L.off_q64) : (const S*)nullptr, inv_dkt, L.m_tab, done);
+}
+
+template <typename C, int NZ>
+void launch_zcz_nz(const Layout& L, void* ws, float inv_dkt, const int* done, hipStream_t s) {
+  switch (L.nv) {
+    case 1: launch_zcz_n<C, NZ, 1>(L, ws, inv_dkt, done, s); break;
+    case 2: launch_zcz_n<C, NZ, 2>(L, ws, inv_dkt, done, s); break;
+    case 3: launch_zcz_n<C, NZ, 3>(L, ws, inv_dkt, done, s); break;
+    case 4: launch_zcz_n<C, NZ, 4>(L, ws, inv_dkt, done, s); break;
+    case 5: launch_zcz_n<C, NZ, 5>(L, ws, inv_dkt, done, s); break;
+    case 6: launch_zcz_n<C, NZ, 6>(L, ws, inv_dkt, done, s); break;
+    case 7: launch_zcz_n<C, NZ, 7>(L, ws, inv_dkt, done, s); break;
+    default: launch_zcz_n<C, NZ, 8>(L, ws, inv_dkt, done, s); break;
+  }
+}
+
+template <typename C>
+void launch_zcz(const Layout& L, void* ws, float inv_dkt, const int* done, hipStream_t s) {
+  switch (L.nz) {
+    case 64: launch_zcz_nz<C, 64>(L, ws, inv_dkt, done, s); break;
+    case 96: launch_zcz_nz<C, 96>(L, ws, inv_dkt, done, s); break;
+    case 128: launch_zcz_nz<C, 128>(L, ws, inv_dkt, done, s); break;
+    default: launch_zcz_nz<C, 256>(L, ws, inv_dkt, done, s); break;
+  }
+}
+
+// Fused first and last kernels of an iteration (x-axis transform fused with the
+// update+closure and with the residual+Gram+control).
+template <bool ANCHOR, int N>
+void launch_fused_n(const Layout& L, void* ws, const rism3d_opts* op, const float* tau0,
+                    bool first_half, hipStream_t s) {
+  using C = PrecC<ANCHOR>;
+  constexpr int LINES = fixed_lines<C, N, 0>();
+  IterState* st = at<IterState>(ws, L.off_state);
+  const int kind = (int)op->closure;
+  const int order = op->closure == RISM3D_PSE ? op->pse_order : 1;
+  const size_t rows = (size_t)L.npair * L.nz * L.ny;
+  const dim3 grid((unsigned)((rows + LINES - 1) / LINES)), block(kFftThreads);
+  const C* tw = at<C>(ws, ANCHOR ? L.off_tw64[0] : L.off_tw32[0]);
+  if (first_half) {
+    TIMED(ANCHOR ? F_UPDFFT64 : F_UPDFFT32, s);
+    hipLaunchKernelGGL((k_update_fftx<ANCHOR, N>), grid, block, 0, s, st, tau0,
+                       at<float>(ws, L.off_tau), at<float>(ws, L.off_res), at<float>(ws, L.off_w),
+                       at<float>(ws, L.off_tref), at<float>(ws, L.off_dg),
+                       at<void>(ws, L.off_spec), L.ny, L.nz, L.nv, L.npair, L.M, kind, order, tw);
+  } else {
+    {
+      TIMED(ANCHOR ? F_FFTRES64 : F_FFTRES32, s);
+      hipLaunchKernelGGL((k_fftx_residual<ANCHOR, N>), grid, block, 0, s, st,
+                         at<void>(ws, L.off_spec), at<float>(ws, L.off_w),
+                         at<float>(ws, L.off_tau), at<float>(ws, L.off_res),
+                         at<float>(ws, L.off_tref), at<float>(ws, L.off_rref),
+                         at<float>(ws, L.off_dg), L.ny, L.nz, L.nv, L.npair, L.M, kind, order, tw,
+                         at<double>(ws, L.off_part));
+    }
+    TIMED(F_CONTROL, s);
+    const double inv_count = 1.0 / ((double)L.N * (double)L.nv);
+    hipLaunchKernelGGL(k_control, dim3(1), dim3(kRedThreads), 0, s, st,
+                       at<double>(ws, L.off_part), (int)grid.x, L.M, inv_count, op->tol,
+                       op->max_iter, (float)op->mdiis_eta, op->eta_dynamic);
+  }
+}
+
+template <bool ANCHOR>
+void launch_fused(const Layout& L, void* ws, const rism3d_opts* op, const float* tau0,
+                  bool first_half, hipStream_t s) {
+  switch (L.nx) {
+    case 32: launch_fused_n<ANCHOR, 32>(L, ws, op, tau0, first_half, s); break;
+    case 64: launch_fused_n<ANCHOR, 64>(L, ws, op, tau0, first_half, s); break;
+    case 96: launch_fused_n<ANCHOR, 96>(L, ws, op, tau0, first_half, s); break;
+    case 128: launch_fused_n<ANCHOR, 128>(L, ws, op, tau0, first_half, s); break;
+    case 192: launch_fused_n<ANCHOR, 192>(L, ws, op, tau0, first_half, s); break;
+    case 256: launch_fused_n<ANCHOR, 256>(L, ws, op, tau0, first_half, s); break;
+    default: launch_fused_n<ANCHOR, 512>(L, ws, op, tau0, first_half, s); break;
+  }
 }
 
 // One evaluation of the 3D-RISM map plus the MDIIS bookkeeping: update +
@@ -400,49 +560,70 @@ void launch_iteration(const Layout& L, void* ws, const rism3d_opts* op, const fl
   const int* done = &st->done;
   const int kind = (int)op->closure;
   const int order = op->closure == RISM3D_PSE ? op->pse_order : 1;
-  const dim3 eg(blocks_for((size_t)L.npair * L.N, kElemThreads)), eb(kElemThreads);
-  if (anchor)
-    {
-      TIMED(F_UPDATE64, s);
-      hipLaunchKernelGGL(k_update_closure<true>, eg, eb, 0, s, st, tau0, at<float>(ws, L.off_tau),
-                         at<float>(ws, L.off_res), at<float>(ws, L.off_w),
-                         at<float>(ws, L.off_tref), at<float>(ws, L.off_dg),
-                         at<void>(ws, L.off_spec), L.N, L.nv, L.npair, L.M, kind, order);
+  if (fixed_fft_size(L.nx)) {
+    if (anchor) launch_fused<true>(L, ws, op, tau0, true, s);
+    else launch_fused<false>(L, ws, op, tau0, true, s);
+    if (zcz_supported(L)) {
+      // y pass, then z + contraction + z fused, then inverse y pass
+      const float2* tw32[3] = {at<float2>(ws, L.off_tw32[0]), at<float2>(ws, L.off_tw32[1]),
+                               at<float2>(ws, L.off_tw32[2])};
+      const double2* tw64[3] = {at<double2>(ws, L.off_tw64[0]), at<double2>(ws, L.off_tw64[1]),
+                                at<double2>(ws, L.off_tw64[2])};
+      if (anchor) {
+        launch_axis(L, at<double2>(ws, L.off_spec), tw64, 1, 1, done, s);
+        launch_zcz<double2>(L, ws, inv_dkt, done, s);
+        launch_axis(L, at<double2>(ws, L.off_spec), tw64, 1, 0, done, s);
+      } else {
+        launch_axis(L, at<float2>(ws, L.off_spec), tw32, 1, 1, done, s);
+        launch_zcz<float2>(L, ws, inv_dkt, done, s);
+        launch_axis(L, at<float2>(ws, L.off_spec), tw32, 1, 0, done, s);
+      }
+    } else {
+      if (anchor) launch_fft3<double2>(L, ws, 1, done, s, true);
+      else launch_fft3<float2>(L, ws, 1, done, s, true);
+      launch_contract(L, ws, anchor, inv_dkt, done, s);
+      if (anchor) launch_fft3<double2>(L, ws, 0, done, s, true);
+      else launch_fft3<float2>(L, ws, 0, done, s, true);
     }
-  else
-    {
-      TIMED(F_UPDATE32, s);
-      hipLaunchKernelGGL(k_update_closure<false>, eg, eb, 0, s, st, tau0, at<float>(ws, L.off_tau),
-                         at<float>(ws, L.off_res), at<float>(ws, L.off_w),
-                         at<float>(ws, L.off_tref), at<float>(ws, L.off_dg),
-                         at<void>(ws, L.off_spec), L.N, L.nv, L.npair, L.M, kind, order);
-    }
+    if (anchor) launch_fused<true>(L, ws, op, tau0, false, s);
+    else launch_fused<false>(L, ws, op, tau0, false, s);
+    return;
+  }
+  const bool v4 = (L.N % 4) == 0;
+  const size_t quads = (size_t)L.npair * (v4 ? L.N / 4 : L.N);
+  const dim3 eg(blocks_for(quads, kElemThreads)), eb(kElemThreads);
+#define RISM_UPDATE_ARGS                                                                    \
+  st, tau0, at<float>(ws, L.off_tau), at<float>(ws, L.off_res), at<float>(ws, L.off_w),     \
+      at<float>(ws, L.off_tref), at<float>(ws, L.off_dg), at<void>(ws, L.off_spec), L.N, L.nv, \
+      L.npair, L.M, kind, order
+  {
+    TIMED(anchor ? F_UPDATE64 : F_UPDATE32, s);
+    if (anchor && v4) hipLaunchKernelGGL((k_update_closure<true, 4>), eg, eb, 0, s, RISM_UPDATE_ARGS);
+    else if (anchor) hipLaunchKernelGGL((k_update_closure<true, 1>), eg, eb, 0, s, RISM_UPDATE_ARGS);
+    else if (v4) hipLaunchKernelGGL((k_update_closure<false, 4>), eg, eb, 0, s, RISM_UPDATE_ARGS);
+    else hipLaunchKernelGGL((k_update_closure<false, 1>), eg, eb, 0, s, RISM_UPDATE_ARGS);
+  }
+#undef RISM_UPDATE_ARGS
   if (anchor) launch_fft3<double2>(L, ws, 1, done, s);
   else launch_fft3<float2>(L, ws, 1, done, s);
   launch_contract(L, ws, anchor, inv_dkt, done, s);
   if (anchor) launch_fft3<double2>(L, ws, 0, done, s);
   else launch_fft3<float2>(L, ws, 0, done, s);
-  const size_t work = (size_t)L.npair * L.N;
-  unsigned nblk = blocks_for(work, kRedThreads);
+  unsigned nblk = blocks_for(quads, kRedThreads);
   if (nblk > (unsigned)kRedBlocks) nblk = kRedBlocks;
-  if (anchor)
-    {
-      TIMED(F_RESIDUAL64, s);
-      hipLaunchKernelGGL(k_residual<true>, dim3(nblk), dim3(kRedThreads), 0, s, st,
-                         at<void>(ws, L.off_spec), at<float>(ws, L.off_w), at<float>(ws, L.off_tau),
-                         at<float>(ws, L.off_res), at<float>(ws, L.off_tref),
-                         at<float>(ws, L.off_rref), at<float>(ws, L.off_dg), L.N, L.nv, L.npair,
-                         L.M, kind, order, at<double>(ws, L.off_part));
-    }
-  else
-    {
-      TIMED(F_RESIDUAL32, s);
-      hipLaunchKernelGGL(k_residual<false>, dim3(nblk), dim3(kRedThreads), 0, s, st,
-                         at<void>(ws, L.off_spec), at<float>(ws, L.off_w), at<float>(ws, L.off_tau),
-                         at<float>(ws, L.off_res), at<float>(ws, L.off_tref),
-                         at<float>(ws, L.off_rref), at<float>(ws, L.off_dg), L.N, L.nv, L.npair,
-                         L.M, kind, order, at<double>(ws, L.off_part));
-    }
+#define RISM_RESID_ARGS                                                                       \
+  st, at<void>(ws, L.off_spec), at<float>(ws, L.off_w), at<float>(ws, L.off_tau),             \
+      at<float>(ws, L.off_res), at<float>(ws, L.off_tref), at<float>(ws, L.off_rref),         \
+      at<float>(ws, L.off_dg), L.N, L.nv, L.npair, L.M, kind, order, at<double>(ws, L.off_part)
+  {
+    TIMED(anchor ? F_RESIDUAL64 : F_RESIDUAL32, s);
+    const dim3 rg(nblk), rb(kRedThreads);
+    if (anchor && v4) hipLaunchKernelGGL((k_residual<true, 4>), rg, rb, 0, s, RISM_RESID_ARGS);
+    else if (anchor) hipLaunchKernelGGL((k_residual<true, 1>), rg, rb, 0, s, RISM_RESID_ARGS);
+    else if (v4) hipLaunchKernelGGL((k_residual<false, 4>), rg, rb, 0, s, RISM_RESID_ARGS);
+    else hipLaunchKernelGGL((k_residual<false, 1>), rg, rb, 0, s, RISM_RESID_ARGS);
+  }
+#undef RISM_RESID_ARGS
   const double inv_count = 1.0 / ((double)L.N * (double)L.nv);
   {
     TIMED(F_CONTROL, s);

@@ -86,6 +86,7 @@ def test_workspace_size_and_history_scaling(R):
 
 @pytest.mark.parametrize("field,value,msg", [
     ("n_sites", 9, "n_sites"), ("nx", 7, "unsupported"), ("nx", 1024, "unsupported"),
+    ("ny", 15, "even"),
     ("temperature", 0.0, "temperature"), ("spacing", -1.0, "spacing"), ("n_k", 1, "table"),
 ])
 def test_bad_problem_is_rejected(R, field, value, msg):
