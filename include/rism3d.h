@@ -202,6 +202,16 @@ void rism3d_timing_enable(int on);
 void rism3d_timing_reset(void);
 int rism3d_timing_read(int family, const char** name, long* launches, double* total_ms);
 
+/* Execution of the iteration: by default one anchor period of iterations is
+ * captured into a HIP graph the first time a (workspace, problem shape,
+ * options) combination is solved and replayed afterwards (the graph is keyed
+ * by the workspace address, so a workspace freed and reallocated at the same
+ * address must be preceded by rism3d_release_graphs()).  rism3d_use_graphs(0)
+ * launches the kernels directly instead.  rism3d_release_graphs() destroys
+ * the library-owned graph cache (host-side handles). */
+void rism3d_use_graphs(int on);
+void rism3d_release_graphs(void);
+
 /* Thread-local message describing the last error on this thread ("" if none). */
 const char* rism3d_last_error(void);
 

@@ -18,7 +18,7 @@ using PrecC = typename std::conditional<ANCHOR, double2, float2>::type;
 
 template <bool ANCHOR, int N>
 __global__ __launch_bounds__(kFftThreads) void k_update_fftx(
-    const IterState* __restrict__ st, const float* __restrict__ tau0, float* __restrict__ tau_hist,
+    const IterState* __restrict__ st, float* __restrict__ tau_hist,
     const float* __restrict__ res_hist, const float* __restrict__ w,
     const float* __restrict__ tau_ref, float* __restrict__ dg_out, void* __restrict__ spec_v,
     int ny, int nz, int nv, int npair, int M, int kind, int order,
@@ -47,8 +47,8 @@ __global__ __launch_bounds__(kFftThreads) void k_update_fftx(
     const size_t n = (row - (size_t)p * plane) * N + i0;
     double o64[2][4];
     float o32[2][4];
-    update_points<ANCHOR, 4>(u, tau0, tau_hist, res_hist, w, tau_ref, dg_out, N3, nv, p, n, kind,
-                             order, o64, o32);
+    update_points<ANCHOR, 4>(u, tau_hist, res_hist, w, tau_ref, dg_out, N3, nv, p, n, kind, order,
+                             o64, o32);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const C val = ANCHOR ? make_c((S)o64[0][v], (S)o64[1][v]) : make_c((S)o32[0][v], (S)o32[1][v]);

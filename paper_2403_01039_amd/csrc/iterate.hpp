@@ -55,6 +55,13 @@ __global__ void k_init_state(IterState* st, float eta, int warm) {
   st->ticket = 0;
 }
 
+// Place the starting tau (the caller's, or zero) in history slot 0, where the
+// first update reads it; keeps the iteration kernels independent of the call.
+__global__ void k_init_tau(const float* __restrict__ tau0, float* __restrict__ slot0, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) slot0[i] = tau0 ? tau0[i] : 0.0f;
+}
+
 __global__ void k_mark_prepared(IterState* st) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     st->prepared = kPreparedMagic;
@@ -116,8 +123,7 @@ __device__ inline UpdateCtl load_update_ctl(const IterState* __restrict__ st, in
 // (and dg in the FP32 path) and returns the two sites' FFT inputs.
 // ANCHOR: c_sr = g - 1 - tau (FP64).  Otherwise dc = dg - delta.
 template <bool ANCHOR, int V>
-__device__ inline void update_points(const UpdateCtl& u, const float* __restrict__ tau0,
-                                     float* __restrict__ tau_hist,
+__device__ inline void update_points(const UpdateCtl& u, float* __restrict__ tau_hist,
                                      const float* __restrict__ res_hist,
                                      const float* __restrict__ w,
                                      const float* __restrict__ tau_ref, float* __restrict__ dg_out,
@@ -136,10 +142,7 @@ __device__ inline void update_points(const UpdateCtl& u, const float* __restrict
     const size_t gn = (size_t)g * N + n;
     float tau[V];
     if (u.first) {
-      if (tau0) ldv<V>(tau0 + gn, tau);
-      else
-#pragma unroll
-        for (int v = 0; v < V; ++v) tau[v] = 0.0f;
+      ldv<V>(tau_hist + (size_t)u.dest * nv * N + gn, tau);   // the start, placed by k_init_tau
     } else {
       float tb[V], dt[V], dr[V];
       ldv<V>(tau_hist + (size_t)u.newest * nv * N + gn, tb);
@@ -187,7 +190,7 @@ __device__ inline void update_points(const UpdateCtl& u, const float* __restrict
 
 template <bool ANCHOR, int V>
 __global__ __launch_bounds__(kElemThreads) void k_update_closure(
-    const IterState* __restrict__ st, const float* __restrict__ tau0, float* __restrict__ tau_hist,
+    const IterState* __restrict__ st, float* __restrict__ tau_hist,
     const float* __restrict__ res_hist, const float* __restrict__ w,
     const float* __restrict__ tau_ref, float* __restrict__ dg_out, void* __restrict__ spec,
     size_t N, int nv, int npair, int M, int kind, int order) {
@@ -200,8 +203,8 @@ __global__ __launch_bounds__(kElemThreads) void k_update_closure(
   const UpdateCtl u = load_update_ctl(st, M);
   double o64[2][V];
   float o32[2][V];
-  update_points<ANCHOR, V>(u, tau0, tau_hist, res_hist, w, tau_ref, dg_out, N, nv, p, n, kind,
-                           order, o64, o32);
+  update_points<ANCHOR, V>(u, tau_hist, res_hist, w, tau_ref, dg_out, N, nv, p, n, kind, order,
+                           o64, o32);
   const size_t o = (size_t)p * N + n;
   if (ANCHOR) {
     double2* sp = static_cast<double2*>(spec) + o;
@@ -446,6 +449,147 @@ __global__ __launch_bounds__(kRedThreads) void k_residual(
   write_partials(acc, M, partials, red);
 }
 
+// Bordered MDIIS system of the m stored slots, embedded in a fixed (MM+1) x
+// (MM+1) system so every index is a compile-time constant and the matrix lives
+// in registers: rows/columns 0..m-1 hold B / max diag(B) with the -1 border in
+// column/row MM; rows m..MM-1 are identity rows (their c_i = 0).  Gaussian
+// elimination with partial pivoting in FP64.  Returns false (restart) when a
+// pivot falls below 1e-12.
+template <int MM>
+__device__ inline bool bordered_solve(const IterState& st, const int* slot, int m, double* c) {
+  constexpr int n = MM + 1;
+  double A[n][n + 1];
+  double scale = 0.0;
+#pragma unroll
+  for (int i = 0; i < MM; ++i)
+    if (i < m) scale = fmax(scale, st.gram[slot[i]][slot[i]]);
+  const double inv = 1.0 / scale;
+#pragma unroll
+  for (int i = 0; i < n; ++i) {
+#pragma unroll
+    for (int j = 0; j <= n; ++j) {
+      double a = 0.0;
+      if (i < MM && j < MM) {
+        if (i < m && j < m) a = st.gram[slot[i]][slot[j]] * inv;
+        else if (i == j) a = 1.0;
+      } else if (i < MM && j == MM) {
+        a = i < m ? -1.0 : 0.0;
+      } else if (i == MM && j < MM) {
+        a = j < m ? -1.0 : 0.0;
+      } else if (i == MM && j == n) {
+        a = -1.0;   // right-hand side of the constraint row
+      }
+      A[i][j] = a;
+    }
+  }
+  double min_piv = 1.0e300;
+#pragma unroll
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    double best = fabs(A[col][col]);
+#pragma unroll
+    for (int r = col + 1; r < n; ++r)
+      if (fabs(A[r][col]) > best) {
+        best = fabs(A[r][col]);
+        piv = r;
+      }
+#pragma unroll
+    for (int r = col + 1; r < n; ++r) {
+      if (r == piv) {
+#pragma unroll
+        for (int j = 0; j <= n; ++j) {
+          const double t = A[col][j];
+          A[col][j] = A[r][j];
+          A[r][j] = t;
+        }
+      }
+    }
+    const double pv = A[col][col];
+    min_piv = fmin(min_piv, fabs(pv));
+    if (!(fabs(pv) >= 1.0e-300)) return false;
+#pragma unroll
+    for (int r = col + 1; r < n; ++r) {
+      const double f = A[r][col] / pv;
+#pragma unroll
+      for (int j = col; j <= n; ++j) A[r][j] -= f * A[col][j];
+    }
+  }
+  if (min_piv < 1.0e-12) return false;
+  double x[n];
+#pragma unroll
+  for (int r = n - 1; r >= 0; --r) {
+    double t = A[r][n];
+#pragma unroll
+    for (int j = r + 1; j < n; ++j) t -= A[r][j] * x[j];
+    x[r] = t / A[r][r];
+  }
+#pragma unroll
+  for (int i = 0; i < MM; ++i)
+    if (i < m) c[i] = x[i];
+  return true;
+}
+
+// LDS-resident fallback for depths beyond the register version.
+__device__ inline bool bordered_solve_lds(const IterState& st, const int* slot, int m, double* c,
+                                          double (*A)[kMaxDepth + 2]) {
+  double scale = 0.0;
+  for (int i = 0; i < m; ++i) scale = fmax(scale, st.gram[slot[i]][slot[i]]);
+  const int n = m + 1;
+  for (int i = 0; i < m; ++i) {
+    for (int j = 0; j < m; ++j) A[i][j] = st.gram[slot[i]][slot[j]] / scale;
+    A[i][m] = -1.0;
+    A[m][i] = -1.0;
+    A[i][n] = 0.0;
+  }
+  A[m][m] = 0.0;
+  A[m][n] = -1.0;
+  double min_piv = 1.0e300;
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
+    if (piv != col) {
+      for (int j = 0; j <= n; ++j) {
+        const double t = A[col][j];
+        A[col][j] = A[piv][j];
+        A[piv][j] = t;
+      }
+    }
+    const double pv = A[col][col];
+    min_piv = fmin(min_piv, fabs(pv));
+    if (fabs(pv) < 1.0e-300) return false;
+    for (int r = col + 1; r < n; ++r) {
+      const double f = A[r][col] / pv;
+      for (int j = col; j <= n; ++j) A[r][j] -= f * A[col][j];
+    }
+  }
+  if (min_piv < 1.0e-12) return false;
+  for (int r = n - 1; r >= 0; --r) {
+    double s = A[r][n];
+    for (int j = r + 1; j < n; ++j) s -= A[r][j] * A[j][n];
+    A[r][n] = s / A[r][r];
+  }
+  for (int i = 0; i < m; ++i) c[i] = A[i][n];
+  return true;
+}
+
+__device__ inline bool bordered_dispatch(const IterState& st, const int* slot, int m, int M,
+                                         double* c, double (*A)[kMaxDepth + 2]) {
+  switch (M) {
+    case 1: return bordered_solve<1>(st, slot, m, c);
+    case 2: return bordered_solve<2>(st, slot, m, c);
+    case 3: return bordered_solve<3>(st, slot, m, c);
+    case 4: return bordered_solve<4>(st, slot, m, c);
+    case 5: return bordered_solve<5>(st, slot, m, c);
+    case 6: return bordered_solve<6>(st, slot, m, c);
+    case 7: return bordered_solve<7>(st, slot, m, c);
+    case 8: return bordered_solve<8>(st, slot, m, c);
+    case 9: return bordered_solve<9>(st, slot, m, c);
+    case 10: return bordered_solve<10>(st, slot, m, c);
+    default: return bordered_solve_lds(st, slot, m, c, A);
+  }
+}
+
 // One control step on a (shared-memory) copy of the state; single thread.
 __device__ inline void control_step(IterState& st, const double* sums,
                                     double (*A)[kMaxDepth + 2], int M, double inv_count,
@@ -517,67 +661,19 @@ __device__ inline void control_step(IterState& st, const double* sums,
     slot[b + 1] = v;
   }
   double c[kMaxDepth];
-  bool ok = true;
   if (m == 1) {
     c[0] = 1.0;
-  } else {
-    // Bordered system [[B, -1], [-1^T, 0]] [c; lam] = [0; -1], B normalised by
-    // its largest diagonal; rhs kept in column n of A.
-    double scale = 0.0;
-    for (int i = 0; i < m; ++i) scale = fmax(scale, st.gram[slot[i]][slot[i]]);
-    const int n = m + 1;
-    for (int i = 0; i < m; ++i) {
-      for (int j = 0; j < m; ++j) A[i][j] = st.gram[slot[i]][slot[j]] / scale;
-      A[i][m] = -1.0;
-      A[m][i] = -1.0;
-      A[i][n] = 0.0;
-    }
-    A[m][m] = 0.0;
-    A[m][n] = -1.0;
-    double min_piv = 1.0e300;
-    for (int col = 0; col < n && ok; ++col) {
-      int piv = col;
-      for (int r = col + 1; r < n; ++r)
-        if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
-      if (piv != col) {
-        for (int j = 0; j <= n; ++j) {
-          const double t = A[col][j];
-          A[col][j] = A[piv][j];
-          A[piv][j] = t;
-        }
-      }
-      const double pv = A[col][col];
-      min_piv = fmin(min_piv, fabs(pv));
-      if (fabs(pv) < 1.0e-300) {
-        ok = false;
-        break;
-      }
-      for (int r = col + 1; r < n; ++r) {
-        const double f = A[r][col] / pv;
-        for (int j = col; j <= n; ++j) A[r][j] -= f * A[col][j];
-      }
-    }
-    if (ok && min_piv >= 1.0e-12) {
-      for (int r = n - 1; r >= 0; --r) {
-        double s = A[r][n];
-        for (int j = r + 1; j < n; ++j) s -= A[r][j] * A[j][n];
-        A[r][n] = s / A[r][r];   // solution overwrites the rhs column
-      }
-      for (int i = 0; i < m; ++i) c[i] = A[i][n];
-    } else {
-      ok = false;
-    }
-    if (!ok) {   // ill-conditioned subspace: restart from the best stored pair
-      int b = slot[0];
-      for (int i = 1; i < m; ++i)
-        if (st.rms_slot[slot[i]] < st.rms_slot[b]) b = slot[i];
-      for (int i = 0; i < M; ++i) st.stored[i] = (i == b);
-      st.newest = b;
-      slot[0] = b;
-      m = 1;
-      c[0] = 1.0;
-      st.restarts += 1;
-    }
+  } else if (!bordered_dispatch(st, slot, m, M, c, A)) {
+    // ill-conditioned subspace: restart from the best stored pair
+    int b = slot[0];
+    for (int i = 1; i < m; ++i)
+      if (st.rms_slot[slot[i]] < st.rms_slot[b]) b = slot[i];
+    for (int i = 0; i < M; ++i) st.stored[i] = (i == b);
+    st.newest = b;
+    slot[0] = b;
+    m = 1;
+    c[0] = 1.0;
+    st.restarts += 1;
   }
   for (int i = 0; i < M; ++i) st.coef[i] = 0.0f;
   for (int i = 0; i < m; ++i) st.coef[slot[i]] = (float)c[i];

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -72,6 +73,7 @@ struct Timer {
   std::vector<hipEvent_t> pool;
   struct Pending {
     int fam;
+    int tag;   // iteration index within the chunk (-1: not an iteration kernel)
     hipEvent_t a, b;
   };
   std::vector<Pending> pending;
@@ -87,8 +89,10 @@ struct Timer {
     pool.pop_back();
     return e;
   }
-  // Harvest completed pairs (the caller has synchronised the stream).
-  void harvest() {
+  // Harvest completed pairs (the caller has synchronised the stream).  Only
+  // iterations that executed (tag < executed) are counted: the launches that
+  // follow convergence inside a chunk exit immediately.
+  void harvest(int executed = 1 << 30) {
     std::vector<Pending> keep;
     for (const Pending& p : pending) {
       if (hipEventQuery(p.b) != hipSuccess) {
@@ -96,9 +100,13 @@ struct Timer {
         continue;
       }
       float t = 0.0f;
-      if (hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) {
-        ms[p.fam] += t;
-        count[p.fam] += 1;
+      if (p.tag < executed) {
+        if (hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) {
+          ms[p.fam] += t;
+          count[p.fam] += 1;
+        } else {
+          (void)hipGetLastError();
+        }
       }
       pool.push_back(p.a);
       pool.push_back(p.b);
@@ -107,20 +115,52 @@ struct Timer {
   }
 };
 thread_local Timer g_timer;
+thread_local int g_iter_tag = -1;
+thread_local bool g_capturing = false;     // a graph capture is in progress
+thread_local bool g_capture_bad = false;   // an event node could not be added
+
+// Records an event on s.  Under stream capture a plain hipEventRecord only
+// tracks dependencies, so an explicit event-record node is appended to the
+// captured graph instead; its timestamp is taken when the graph runs.
+bool record_event(hipEvent_t e, hipStream_t s) {
+  if (!g_capturing) return hipEventRecord(e, s) == hipSuccess;
+  hipStreamCaptureStatus st;
+  unsigned long long id = 0;
+  hipGraph_t g = nullptr;
+  const hipGraphNode_t* deps = nullptr;
+  size_t nd = 0;
+  hipGraphNode_t node = nullptr;
+  if (hipStreamGetCaptureInfo_v2(s, &st, &id, &g, &deps, &nd) != hipSuccess ||
+      st != hipStreamCaptureStatusActive ||
+      hipGraphAddEventRecordNode(&node, g, deps, nd, e) != hipSuccess ||
+      hipStreamUpdateCaptureDependencies(s, &node, 1, hipStreamSetCaptureDependencies) !=
+          hipSuccess) {
+    (void)hipGetLastError();
+    g_capture_bad = true;
+    return false;
+  }
+  return true;
+}
 
 struct TimedScope {
   hipEvent_t a = nullptr;
   int fam;
   hipStream_t s;
   TimedScope(int f, hipStream_t st) : fam(f), s(st) {
-    if (g_timer.on && (a = g_timer.get())) hipEventRecord(a, s);
+    if (g_timer.on && (a = g_timer.get()) && !record_event(a, s)) {
+      g_timer.pool.push_back(a);
+      a = nullptr;
+    }
   }
   ~TimedScope() {
     if (!a) return;
     hipEvent_t b = g_timer.get();
     if (!b) return;
-    hipEventRecord(b, s);
-    g_timer.pending.push_back({fam, a, b});
+    if (!record_event(b, s)) {
+      g_timer.pool.push_back(b);
+      return;   // a stays recorded and unused; it is not reused this chunk
+    }
+    g_timer.pending.push_back({fam, g_iter_tag, a, b});
   }
 };
 #define TIMED(fam, s) TimedScope timed_scope_##__LINE__(fam, s)
@@ -503,8 +543,8 @@ void launch_zcz(const Layout& L, void* ws, float inv_dkt, const int* done, hipSt
 // Fused first and last kernels of an iteration (x-axis transform fused with the
 // update+closure and with the residual+Gram+control).
 template <bool ANCHOR, int N>
-void launch_fused_n(const Layout& L, void* ws, const rism3d_opts* op, const float* tau0,
-                    bool first_half, hipStream_t s) {
+void launch_fused_n(const Layout& L, void* ws, const rism3d_opts* op, bool first_half,
+                    hipStream_t s) {
   using C = PrecC<ANCHOR>;
   constexpr int LINES = fixed_lines<C, N, 0>();
   IterState* st = at<IterState>(ws, L.off_state);
@@ -515,7 +555,7 @@ void launch_fused_n(const Layout& L, void* ws, const rism3d_opts* op, const floa
   const C* tw = at<C>(ws, ANCHOR ? L.off_tw64[0] : L.off_tw32[0]);
   if (first_half) {
     TIMED(ANCHOR ? F_UPDFFT64 : F_UPDFFT32, s);
-    hipLaunchKernelGGL((k_update_fftx<ANCHOR, N>), grid, block, 0, s, st, tau0,
+    hipLaunchKernelGGL((k_update_fftx<ANCHOR, N>), grid, block, 0, s, st,
                        at<float>(ws, L.off_tau), at<float>(ws, L.off_res), at<float>(ws, L.off_w),
                        at<float>(ws, L.off_tref), at<float>(ws, L.off_dg),
                        at<void>(ws, L.off_spec), L.ny, L.nz, L.nv, L.npair, L.M, kind, order, tw);
@@ -538,31 +578,31 @@ void launch_fused_n(const Layout& L, void* ws, const rism3d_opts* op, const floa
 }
 
 template <bool ANCHOR>
-void launch_fused(const Layout& L, void* ws, const rism3d_opts* op, const float* tau0,
-                  bool first_half, hipStream_t s) {
+void launch_fused(const Layout& L, void* ws, const rism3d_opts* op, bool first_half,
+                  hipStream_t s) {
   switch (L.nx) {
-    case 32: launch_fused_n<ANCHOR, 32>(L, ws, op, tau0, first_half, s); break;
-    case 64: launch_fused_n<ANCHOR, 64>(L, ws, op, tau0, first_half, s); break;
-    case 96: launch_fused_n<ANCHOR, 96>(L, ws, op, tau0, first_half, s); break;
-    case 128: launch_fused_n<ANCHOR, 128>(L, ws, op, tau0, first_half, s); break;
-    case 192: launch_fused_n<ANCHOR, 192>(L, ws, op, tau0, first_half, s); break;
-    case 256: launch_fused_n<ANCHOR, 256>(L, ws, op, tau0, first_half, s); break;
-    default: launch_fused_n<ANCHOR, 512>(L, ws, op, tau0, first_half, s); break;
+    case 32: launch_fused_n<ANCHOR, 32>(L, ws, op, first_half, s); break;
+    case 64: launch_fused_n<ANCHOR, 64>(L, ws, op, first_half, s); break;
+    case 96: launch_fused_n<ANCHOR, 96>(L, ws, op, first_half, s); break;
+    case 128: launch_fused_n<ANCHOR, 128>(L, ws, op, first_half, s); break;
+    case 192: launch_fused_n<ANCHOR, 192>(L, ws, op, first_half, s); break;
+    case 256: launch_fused_n<ANCHOR, 256>(L, ws, op, first_half, s); break;
+    default: launch_fused_n<ANCHOR, 512>(L, ws, op, first_half, s); break;
   }
 }
 
 // One evaluation of the 3D-RISM map plus the MDIIS bookkeeping: update +
 // closure, forward FFT, contraction, inverse FFT, residual + Gram row, control.
 // anchor: FP64 evaluation that re-bases the FP32 increments.
-void launch_iteration(const Layout& L, void* ws, const rism3d_opts* op, const float* tau0,
-                      float inv_dkt, bool anchor, hipStream_t s) {
+void launch_iteration(const Layout& L, void* ws, const rism3d_opts* op, float inv_dkt,
+                      bool anchor, hipStream_t s) {
   IterState* st = at<IterState>(ws, L.off_state);
   const int* done = &st->done;
   const int kind = (int)op->closure;
   const int order = op->closure == RISM3D_PSE ? op->pse_order : 1;
   if (fixed_fft_size(L.nx)) {
-    if (anchor) launch_fused<true>(L, ws, op, tau0, true, s);
-    else launch_fused<false>(L, ws, op, tau0, true, s);
+    if (anchor) launch_fused<true>(L, ws, op, true, s);
+    else launch_fused<false>(L, ws, op, true, s);
     if (zcz_supported(L)) {
       // y pass, then z + contraction + z fused, then inverse y pass
       const float2* tw32[3] = {at<float2>(ws, L.off_tw32[0]), at<float2>(ws, L.off_tw32[1]),
@@ -585,15 +625,15 @@ void launch_iteration(const Layout& L, void* ws, const rism3d_opts* op, const fl
       if (anchor) launch_fft3<double2>(L, ws, 0, done, s, true);
       else launch_fft3<float2>(L, ws, 0, done, s, true);
     }
-    if (anchor) launch_fused<true>(L, ws, op, tau0, false, s);
-    else launch_fused<false>(L, ws, op, tau0, false, s);
+    if (anchor) launch_fused<true>(L, ws, op, false, s);
+    else launch_fused<false>(L, ws, op, false, s);
     return;
   }
   const bool v4 = (L.N % 4) == 0;
   const size_t quads = (size_t)L.npair * (v4 ? L.N / 4 : L.N);
   const dim3 eg(blocks_for(quads, kElemThreads)), eb(kElemThreads);
 #define RISM_UPDATE_ARGS                                                                    \
-  st, tau0, at<float>(ws, L.off_tau), at<float>(ws, L.off_res), at<float>(ws, L.off_w),     \
+  st, at<float>(ws, L.off_tau), at<float>(ws, L.off_res), at<float>(ws, L.off_w),     \
       at<float>(ws, L.off_tref), at<float>(ws, L.off_dg), at<void>(ws, L.off_spec), L.N, L.nv, \
       L.npair, L.M, kind, order
   {
@@ -635,9 +675,135 @@ void launch_iteration(const Layout& L, void* ws, const rism3d_opts* op, const fl
 
 int order_of(const rism3d_opts* op) { return op->closure == RISM3D_PSE ? op->pse_order : 1; }
 
+// ---------------------------------------------------------------------------
+// Graph cache: one instantiated graph per (workspace, problem shape, options,
+// timing switch), holding one anchor period of iterations.  Kernel arguments
+// depend only on these, so a graph is valid for every later solve with the
+// same key.  Library-owned, host side; rism3d_release_graphs() frees it.
+// ---------------------------------------------------------------------------
+bool g_use_graphs = true;
+
+struct GraphEntry {
+  std::string key;
+  hipGraphExec_t exec = nullptr;
+  std::vector<Timer::Pending> timing;   // event pairs recorded inside the graph
+  void harvest(int executed) {
+    for (const Timer::Pending& p : timing) {
+      float t = 0.0f;
+      if (p.tag >= executed) continue;
+      if (hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) {
+        g_timer.ms[p.fam] += t;
+        g_timer.count[p.fam] += 1;
+      } else {
+        (void)hipGetLastError();
+      }
+    }
+  }
+};
+
+std::mutex g_graph_mu;
+std::vector<GraphEntry*> g_graphs;   // most recent last
+constexpr size_t kMaxGraphs = 32;
+
+// One capture stream per device (default priority, non-blocking), created on
+// first use and kept for the life of the process.
+hipStream_t capture_stream() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  static std::vector<hipStream_t> streams;
+  if ((int)streams.size() <= dev) streams.resize(dev + 1, nullptr);
+  if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    streams[dev] = nullptr;
+  }
+  return streams[dev];
+}
+
+std::string graph_key(const Layout& L, const void* ws, const rism3d_opts* op, float inv_dkt,
+                      int every) {
+  char buf[512];
+  snprintf(buf, sizeof(buf), "%p|%zu|%d,%d,%d,%d,%d,%d|%d,%d,%.17g,%d,%.17g,%d,%d|%a|%d",
+           ws, L.total, L.nx, L.ny, L.nz, L.nv, L.M, L.m_tab, (int)op->closure, op->pse_order,
+           op->tol, op->max_iter, op->mdiis_eta, op->eta_dynamic, every, (double)inv_dkt,
+           (int)g_timer.on);
+  return buf;
+}
+
+void drop_graph(GraphEntry* e) {
+  if (e->exec) hipGraphExecDestroy(e->exec);
+  for (const Timer::Pending& p : e->timing) {
+    hipEventDestroy(p.a);
+    hipEventDestroy(p.b);
+  }
+  delete e;
+}
+
+GraphEntry* graph_for(const Layout& L, void* ws, const rism3d_opts* op, float inv_dkt, int every,
+                      hipStream_t s) {
+  const std::string key = graph_key(L, ws, op, inv_dkt, every);
+  std::lock_guard<std::mutex> lock(g_graph_mu);
+  for (size_t i = 0; i < g_graphs.size(); ++i) {
+    if (g_graphs[i]->key == key) {
+      GraphEntry* e = g_graphs[i];
+      g_graphs.erase(g_graphs.begin() + i);
+      g_graphs.push_back(e);
+      return e;
+    }
+  }
+  // Capture on a library-owned stream of the current device (the caller's
+  // stream may be the null stream, which cannot be captured); the graph is
+  // then launched on the caller's stream.  Anything recorded by the timer
+  // during the capture belongs to the graph.
+  hipStream_t cs = capture_stream();
+  if (!cs) return nullptr;
+  std::vector<Timer::Pending> before;
+  before.swap(g_timer.pending);
+  hipGraph_t graph = nullptr;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    g_timer.pending.swap(before);
+    return nullptr;
+  }
+  g_capturing = true;
+  g_capture_bad = false;
+  for (int k = 0; k < every; ++k) {
+    g_iter_tag = k;
+    launch_iteration(L, ws, op, inv_dkt, k == 0, cs);
+  }
+  g_iter_tag = -1;
+  g_capturing = false;
+  const hipError_t ec = hipStreamEndCapture(cs, &graph);
+  GraphEntry* e = new GraphEntry;
+  e->key = key;
+  e->timing.swap(g_timer.pending);
+  g_timer.pending.swap(before);
+  if (ec != hipSuccess || !graph || g_capture_bad ||
+      hipGraphInstantiate(&e->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    if (graph) hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    drop_graph(e);
+    return nullptr;
+  }
+  hipGraphDestroy(graph);
+  if (g_graphs.size() >= kMaxGraphs) {
+    drop_graph(g_graphs.front());
+    g_graphs.erase(g_graphs.begin());
+  }
+  g_graphs.push_back(e);
+  return e;
+}
+
 }  // namespace
 
 extern "C" {
+
+void rism3d_use_graphs(int on) { g_use_graphs = on != 0; }
+
+void rism3d_release_graphs(void) {
+  std::lock_guard<std::mutex> lock(g_graph_mu);
+  for (GraphEntry* e : g_graphs) drop_graph(e);
+  g_graphs.clear();
+}
 
 size_t rism3d_workspace_bytes(const rism3d_problem* problem, const rism3d_opts* opts) {
   Layout L;
@@ -711,20 +877,41 @@ rism3d_status rism3d_solve(const rism3d_problem* pr, const rism3d_opts* op, cons
     return fail(RISM3D_E_WORKSPACE, "workspace not prepared: call rism3d_potential first");
   hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1), 0, s, dst, (float)op->mdiis_eta,
                      tau0 ? 1 : 0);
+  hipLaunchKernelGGL(k_init_tau, dim3(blocks_for((size_t)L.nv * L.N, kElemThreads)),
+                     dim3(kElemThreads), 0, s, tau0, at<float>(ws, L.off_tau),
+                     (size_t)L.nv * L.N);
   LAUNCH_CHECK();
   const float inv_dkt = (float)(1.0 / pr->dk);
-  const int chunk = op->check_every > 0 ? op->check_every : kDefaultCheckEvery;
   const int every = op->anchor_every > 0 ? op->anchor_every : kDefaultAnchorEvery;
+  // One anchor period (an FP64 anchor evaluation + every-1 FP32 increments) is
+  // captured once into a HIP graph per workspace and options, then replayed;
+  // the host reads the small device state after each replay.
+  GraphEntry* graph = g_use_graphs ? graph_for(L, ws, op, inv_dkt, every, s) : nullptr;
+  const int chunk = graph ? every : (op->check_every > 0 ? op->check_every : kDefaultCheckEvery);
   int launched = 0;
+  int iter_before = 0;
   for (;;) {
-    const int todo = (op->max_iter - launched) < chunk ? (op->max_iter - launched) : chunk;
-    for (int k = 0; k < todo; ++k)
-      launch_iteration(L, ws, op, tau0, inv_dkt, ((launched + k) % every) == 0, s);
+    if (graph) {
+      HIP_TRY(hipGraphLaunch(graph->exec, s));
+      launched += every;
+    } else {
+      const int todo = (op->max_iter - launched) < chunk ? (op->max_iter - launched) : chunk;
+      for (int k = 0; k < todo; ++k) {
+        g_iter_tag = k;
+        launch_iteration(L, ws, op, inv_dkt, ((launched + k) % every) == 0, s);
+      }
+      g_iter_tag = -1;
+      launched += todo;
+    }
     LAUNCH_CHECK();
-    launched += todo;
     HIP_TRY(hipMemcpyAsync(&host, dst, sizeof(IterState), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    if (g_timer.on) g_timer.harvest();
+    if (g_timer.on) {
+      const int executed = host.iter - iter_before;
+      if (graph) graph->harvest(executed);
+      g_timer.harvest(executed);
+    }
+    iter_before = host.iter;
     if (host.done || launched >= op->max_iter) break;
   }
   if (g_out) {
@@ -821,7 +1008,10 @@ rism3d_status rism3d_map(const rism3d_problem* pr, const rism3d_opts* op, const 
   one.max_iter = 1;
   one.tol = 0.0;   // never "converged": the single evaluation always runs to the end
   hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1), 0, s, dst, (float)op->mdiis_eta, 1);
-  launch_iteration(L, ws, &one, d_tau, (float)(1.0 / pr->dk), true, s);
+  hipLaunchKernelGGL(k_init_tau, dim3(blocks_for((size_t)L.nv * L.N, kElemThreads)),
+                     dim3(kElemThreads), 0, s, d_tau, at<float>(ws, L.off_tau),
+                     (size_t)L.nv * L.N);
+  launch_iteration(L, ws, &one, (float)(1.0 / pr->dk), true, s);
   const size_t n = (size_t)L.nv * L.N;
   hipLaunchKernelGGL(k_copy_floats, dim3(blocks_for(n, kElemThreads)), dim3(kElemThreads), 0, s,
                      at<float>(ws, L.off_res), d_res, n);   // slot 0 holds R

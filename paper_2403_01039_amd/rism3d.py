@@ -84,6 +84,8 @@ def _load():
         "rism3d_timing_reset": (None, []),
         "rism3d_timing_read": (ctypes.c_int, [ctypes.c_int, P(ctypes.c_char_p), P(ctypes.c_long),
                                               P(ctypes.c_double)]),
+        "rism3d_use_graphs": (None, [ctypes.c_int]),
+        "rism3d_release_graphs": (None, []),
         "rism3d_last_error": (ctypes.c_char_p, []),
         "rism3d_constants": (None, [P(ctypes.c_double)] * 5),
     }
@@ -98,7 +100,8 @@ LIB = _load()
 EXPORTED = ("rism3d_workspace_bytes", "rism3d_potential", "rism3d_solve", "rism3d_thermo",
             "rism3d_get_tau", "rism3d_map", "rism3d_get_potential",
             "rism3d_transform_workspace_bytes", "rism3d_transform", "rism3d_timing_enable",
-            "rism3d_timing_reset", "rism3d_timing_read", "rism3d_last_error", "rism3d_constants")
+            "rism3d_timing_reset", "rism3d_timing_read", "rism3d_use_graphs",
+            "rism3d_release_graphs", "rism3d_last_error", "rism3d_constants")
 
 
 def last_error() -> str:
@@ -116,6 +119,14 @@ def constants():
     LIB.rism3d_constants(*[ctypes.byref(v) for v in vals])
     return dict(zip(("coulomb", "kboltz", "screen", "d_min", "beta_u_cap"),
                     (v.value for v in vals)))
+
+
+def use_graphs(on: bool = True):
+    LIB.rism3d_use_graphs(int(bool(on)))
+
+
+def release_graphs():
+    LIB.rism3d_release_graphs()
 
 
 def timing_enable(on: bool = True):
