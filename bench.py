@@ -38,9 +38,11 @@ def kernel_bytes(nv: int, N: int, M: int, m_avg: float, fam: str) -> float:
         return nv * N * 4 * (2 * m_avg + 4) + 8 * P * N
     if fam == "update_closure_f64":   # read m tau_i, m R_i, w; write tau; write FP64 spectra
         return nv * N * 4 * (2 * m_avg + 2) + 16 * P * N
-    if fam.startswith("fft_") and fam.endswith("_f32") or fam == "contract_f32":
+    if fam.startswith("fft_") and fam.endswith("_f32") or fam in ("contract_f32",
+                                                                   "zfft_contract_f32"):
         return 16 * P * N
-    if fam.startswith("fft_") and fam.endswith("_f64") or fam == "contract_f64":
+    if fam.startswith("fft_") and fam.endswith("_f64") or fam in ("contract_f64",
+                                                                   "zfft_contract_f64"):
         return 32 * P * N
     if fam == "update_fftx_f32":      # update + closure, spectra written once after the x pass
         return nv * N * 4 * (2 * m_avg + 4) + 8 * P * N
@@ -115,13 +117,90 @@ def cpu_baseline(prob, chi, dk, iterations: int):
     }
 
 
+# Kernel-name patterns of the iteration kernels -> timing family names.
+FAMILY_PATTERNS = [
+    (r"k_update_fftx<false", "update_fftx_f32"), (r"k_update_fftx<true", "update_fftx_f64"),
+    (r"k_fftx_residual<false", "fftx_residual_f32"), (r"k_fftx_residual<true", "fftx_residual_f64"),
+    (r"k_zcz<HIP_vector_type<float, 2u>|k_zcz<float2", "zfft_contract_f32"),
+    (r"k_zcz<HIP_vector_type<double, 2u>|k_zcz<double2", "zfft_contract_f64"),
+    (r"k_fft_fixed<HIP_vector_type<float, 2u>, \d+, 1|k_fft_fixed<float2, \d+, 1", "fft_y_f32"),
+    (r"k_fft_fixed<HIP_vector_type<double, 2u>, \d+, 1|k_fft_fixed<double2, \d+, 1",
+     "fft_y_f64"),
+    (r"k_control", "mdiis_control"), (r"k_potential", "potential"),
+    (r"k_ftilde", "long_range_spectrum"),
+    (r"elementwise_kernel", "copy_calibration"),
+]
+
+
+def family_of(kernel_name: str):
+    import re
+    for pat, fam in FAMILY_PATTERNS:
+        if re.search(pat, kernel_name):
+            return fam
+    return None
+
+
+def summarize_counters(fetch_csv: str, write_csv: str, copy_bytes: int, out_path: str):
+    """HBM bytes per launch of each kernel family from two rocprofv3 --pmc
+    runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by what the
+    same counter reads for the plain copy of copy_bytes bytes in that run."""
+    import csv
+    import numpy as np
+
+    def load(path, counter):
+        per = {}
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                if row.get("Counter_Name") != counter:
+                    continue
+                fam = family_of(row["Kernel_Name"])
+                if fam:
+                    per.setdefault(fam, []).append(float(row["Counter_Value"]))
+        return per
+
+    def active(per):
+        # Launches that follow convergence inside a replayed anchor period exit
+        # at once and move (almost) no bytes; they are not launches of the step.
+        return {f: [v for v in vals if v >= 0.01 * max(vals)] for f, vals in per.items()}
+
+    fetch = active(load(fetch_csv, "FETCH_SIZE"))
+    write = active(load(write_csv, "WRITE_SIZE"))
+    # the calibration copy is the elementwise dispatch with the largest fetch
+    # (torch.ones before it only writes)
+    f_copy = max(fetch["copy_calibration"]) * 1024.0
+    w_copy = max(write["copy_calibration"]) * 1024.0
+    f_scale, w_scale = copy_bytes / f_copy, copy_bytes / w_copy
+    out = {"source_digest": source_digest(), "copy_bytes": copy_bytes,
+           "fetch_scale": f_scale, "write_scale": w_scale, "kernels": {}}
+    for fam in sorted(set(fetch) & set(write)):
+        if fam == "copy_calibration":
+            continue
+        fb = float(np.mean(fetch[fam])) * 1024.0 * f_scale
+        wb = float(np.mean(write[fam])) * 1024.0 * w_scale
+        out["kernels"][fam] = {"dispatches": len(fetch[fam]), "write_dispatches": len(write[fam]),
+                               "fetch_bytes": fb,
+                               "write_bytes": wb, "bytes_per_launch": fb + wb}
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (the reference "
+                         "dispatch for scaling HBM counters)")
+    ap.add_argument("--summarize-counters", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT"),
+                    help="write per-family HBM bytes from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters[:2], args.copy_calibration_mib << 20,
+                           args.summarize_counters[2])
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -131,9 +210,16 @@ def main():
     from paper_2403_01039_amd import inputs
     from paper_2403_01039_amd import rism3d as R
 
+    dev = torch.device("cuda:0")
+    if args.copy_calibration_mib:
+        n = (args.copy_calibration_mib << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)   # one elementwise kernel: reads and writes n floats
+        torch.cuda.synchronize()
+        del src, dst
     prob = inputs.solute_200_problem(1, saline=True)
     chi, dk = inputs.solvent_table_for(prob.solvent)
-    dev = torch.device("cuda:0")
     dp = R.DeviceProblem(prob, chi, dk, device=dev)
     opts = R.make_opts(prob.options)
     solver = R.Solver(dp, opts)
@@ -145,10 +231,23 @@ def main():
         sfe, _ = solver.thermo(stream)
         return info, sfe
 
-    for _ in range(args.warmup):
+    # Warmup.  The first warmup step times every kernel family (for the
+    # per-family breakdown and to name the dominant family); the timed region
+    # then records events around that family only, since every event record
+    # also orders the stream and timing all families would slow the solve.
+    R.timing_reset()
+    R.timing_enable(True)
+    step()
+    torch.cuda.synchronize()
+    R.timing_enable(False)
+    breakdown = R.timing_read()
+    for _ in range(max(args.warmup - 1, 0)):
         step()
     torch.cuda.synchronize()
+    dominant = max((f for f, (c, ms) in breakdown.items() if c and kernel_bytes(
+        prob.solvent.n_sites, prob.grid.n_points, 1, 1.0, f)), key=lambda f: breakdown[f][1])
     R.timing_reset()
+    R.timing_select(dominant)
     R.timing_enable(True)
     iters = []
     t0 = time.perf_counter()
@@ -158,6 +257,7 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     R.timing_enable(False)
+    R.timing_select(None)
     timing = R.timing_read()
 
     nv = prob.solvent.n_sites
@@ -165,19 +265,22 @@ def main():
     M = prob.options.mdiis_depth
     it_mean = float(np.mean(iters))
     m_avg = float(np.mean([min(k, M) for k in range(int(round(it_mean)))]))
-    kernels = {}
-    for fam, (cnt, ms) in timing.items():
-        if cnt == 0:
-            continue
-        avg_s = ms / cnt * 1e-3
-        b = kernel_bytes(nv, N, M, m_avg, fam)
-        kernels[fam] = {"launches": cnt, "total_ms": round(ms, 3), "avg_us": round(avg_s * 1e6, 2),
-                        "bytes_per_launch": b,
+    def table(tm):
+        out = {}
+        for fam, (cnt, ms) in tm.items():
+            if cnt == 0:
+                continue
+            avg_s = ms / cnt * 1e-3
+            b = kernel_bytes(nv, N, M, m_avg, fam)
+            out[fam] = {"launches": cnt, "total_ms": round(ms, 3),
+                        "avg_us": round(avg_s * 1e6, 2), "bytes_per_launch": b,
                         "gbps": round(b / avg_s / 1e9, 1) if b else None}
-    dominant = max((f for f in kernels if kernels[f]["bytes_per_launch"]),
-                   key=lambda f: kernels[f]["total_ms"])
-    dk_ = kernels[dominant]
-    achieved = dk_["gbps"]
+        return out
+
+
+    kernels = table(breakdown)
+    timed = table(timing)[dominant]
+    achieved = timed["gbps"]
     traffic = None
     if os.path.exists(PROFILE_TRAFFIC):
         with open(PROFILE_TRAFFIC) as f:
@@ -209,8 +312,10 @@ def main():
         "sfe_kcal_mol": sfe,
         "hbm_gbps_effective": b_min_iter * it_mean / (elapsed / args.steps) / 1e9,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic, "kernel": dominant},
-        "kernels": kernels,
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic, "kernel": dominant,
+                     "launches": timed["launches"], "avg_us": timed["avg_us"],
+                     "bytes_per_launch": timed["bytes_per_launch"]},
+        "kernels_first_warmup_step": kernels,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, chi, dk, int(round(it_mean)))

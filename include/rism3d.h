@@ -197,16 +197,21 @@ rism3d_status rism3d_transform(int nx, int ny, int nz, int count, void* d_data, 
  * kernel launch and add the elapsed time to a per-family total when the call
  * synchronises.  rism3d_timing_read(i, ...) fills the name, launch count and
  * total milliseconds of family i and returns the number of families (call with
- * i = -1 to get the count only).  Enabling costs two event records per launch. */
+ * i = -1 to get the count only).  Enabling costs two event records per timed
+ * launch (each record also orders the stream, so timing every family slows a
+ * solve by about a tenth).  rism3d_timing_select(name) restricts the events to
+ * the one family of that name (NULL or "" restores every family); an unknown
+ * name returns RISM3D_E_ARG and leaves the selection unchanged. */
 void rism3d_timing_enable(int on);
+rism3d_status rism3d_timing_select(const char* family);
 void rism3d_timing_reset(void);
 int rism3d_timing_read(int family, const char** name, long* launches, double* total_ms);
 
 /* Execution of the iteration: by default one anchor period of iterations is
  * captured into a HIP graph the first time a (workspace, problem shape,
  * options) combination is solved and replayed afterwards (the graph is keyed
- * by the workspace address, so a workspace freed and reallocated at the same
- * address must be preceded by rism3d_release_graphs()).  rism3d_use_graphs(0)
+ * by the workspace address and layout, which fix every kernel argument, and
+ * touches no memory outside the workspace).  rism3d_use_graphs(0)
  * launches the kernels directly instead.  rism3d_release_graphs() destroys
  * the library-owned graph cache (host-side handles). */
 void rism3d_use_graphs(int on);

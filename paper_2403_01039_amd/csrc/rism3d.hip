@@ -70,6 +70,7 @@ const char* const kFamilyNames[F_COUNT] = {
 
 struct Timer {
   bool on = false;
+  int only = -1;   // time this family only (-1: every family)
   std::vector<hipEvent_t> pool;
   struct Pending {
     int fam;
@@ -147,7 +148,8 @@ struct TimedScope {
   int fam;
   hipStream_t s;
   TimedScope(int f, hipStream_t st) : fam(f), s(st) {
-    if (g_timer.on && (a = g_timer.get()) && !record_event(a, s)) {
+    if (g_timer.on && (g_timer.only < 0 || g_timer.only == f) && (a = g_timer.get()) &&
+        !record_event(a, s)) {
       g_timer.pool.push_back(a);
       a = nullptr;
     }
@@ -725,7 +727,7 @@ std::string graph_key(const Layout& L, const void* ws, const rism3d_opts* op, fl
   snprintf(buf, sizeof(buf), "%p|%zu|%d,%d,%d,%d,%d,%d|%d,%d,%.17g,%d,%.17g,%d,%d|%a|%d",
            ws, L.total, L.nx, L.ny, L.nz, L.nv, L.M, L.m_tab, (int)op->closure, op->pse_order,
            op->tol, op->max_iter, op->mdiis_eta, op->eta_dynamic, every, (double)inv_dkt,
-           (int)g_timer.on);
+           g_timer.on ? g_timer.only : -2);
   return buf;
 }
 
@@ -1080,6 +1082,19 @@ rism3d_status rism3d_transform(int nx, int ny, int nz, int count, void* d_data, 
 }
 
 void rism3d_timing_enable(int on) { g_timer.on = on != 0; }
+
+rism3d_status rism3d_timing_select(const char* family) {
+  if (!family || !family[0]) {
+    g_timer.only = -1;
+    return RISM3D_OK;
+  }
+  for (int f = 0; f < F_COUNT; ++f)
+    if (std::strcmp(family, kFamilyNames[f]) == 0) {
+      g_timer.only = f;
+      return RISM3D_OK;
+    }
+  return fail(RISM3D_E_ARG, "unknown kernel family '%s'", family);
+}
 
 void rism3d_timing_reset(void) {
   for (int f = 0; f < F_COUNT; ++f) {

@@ -84,6 +84,7 @@ def _load():
         "rism3d_timing_reset": (None, []),
         "rism3d_timing_read": (ctypes.c_int, [ctypes.c_int, P(ctypes.c_char_p), P(ctypes.c_long),
                                               P(ctypes.c_double)]),
+        "rism3d_timing_select": (ctypes.c_int, [ctypes.c_char_p]),
         "rism3d_use_graphs": (None, [ctypes.c_int]),
         "rism3d_release_graphs": (None, []),
         "rism3d_last_error": (ctypes.c_char_p, []),
@@ -101,7 +102,7 @@ EXPORTED = ("rism3d_workspace_bytes", "rism3d_potential", "rism3d_solve", "rism3
             "rism3d_get_tau", "rism3d_map", "rism3d_get_potential",
             "rism3d_transform_workspace_bytes", "rism3d_transform", "rism3d_timing_enable",
             "rism3d_timing_reset", "rism3d_timing_read", "rism3d_use_graphs",
-            "rism3d_release_graphs", "rism3d_last_error", "rism3d_constants")
+            "rism3d_release_graphs", "rism3d_timing_select", "rism3d_last_error", "rism3d_constants")
 
 
 def last_error() -> str:
@@ -131,6 +132,11 @@ def release_graphs():
 
 def timing_enable(on: bool = True):
     LIB.rism3d_timing_enable(int(bool(on)))
+
+
+def timing_select(family: Optional[str] = None):
+    """Restrict kernel timing to one family (None: every family)."""
+    _check(LIB.rism3d_timing_select(family.encode() if family else None))
 
 
 def timing_reset():

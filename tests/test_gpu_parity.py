@@ -195,6 +195,48 @@ def test_single_site_64_golden(R):
     assert abs(sfe - ref["sfe_ref"]) <= SFE_RTOL * abs(ref["sfe_ref"])
 
 
+@pytest.mark.parametrize("name", ["solute_200_saline", "warm_20000"])
+def test_full_size_golden(R, name):
+    """The 128^3 workloads (200-atom solute in water + 0.1 M NaCl, and in
+    water) at full size, in the launch configuration the benchmark times
+    (graph replay of anchor periods), against stored oracle values on 6000+
+    sampled points: the potential w and phi, the converged g (oracle at rms
+    1e-10) and the SFE.  The stopping-rule allowance is the oracle's own
+    distance between its rms-1e-6 and rms-1e-10 solutions."""
+    import os
+    ref = np.load(os.path.join(os.path.dirname(__file__), "golden", f"{name}.npz"))
+    seed = 1 if name == "solute_200_saline" else int(name.split("_")[1])
+    prob = (inputs.solute_200_problem(seed, saline=True) if name == "solute_200_saline"
+            else inputs.warmstart_problem(seed))
+    print(f"full-size golden {name}", flush=True)
+    R.use_graphs(True)
+    s, _, _ = _run(R, prob)
+    idx = torch.as_tensor(ref["idx"], device="cuda")
+    w, phi = s.fields()
+    w_s = w.reshape(w.shape[0], -1)[:, idx].cpu().numpy().astype(np.float64)
+    phi_s = phi.reshape(-1)[idx].cpu().numpy().astype(np.float64)
+    w_ref = ref["w_ref"]
+    rel = np.abs(w_s - w_ref) / np.maximum(1.0, np.abs(w_ref))
+    soft = w_ref < 5.0
+    assert rel[soft].max() < 2e-5
+    assert rel[~soft].max() < 1e-3 if (~soft).any() else True
+    assert np.abs(phi_s - ref["phi_ref"]).max() / max(1.0, np.abs(ref["phi_ref"]).max()) < 2e-5
+    g = torch.empty(s.dp.shape, dtype=torch.float32, device="cuda")
+    info = s.solve(g_out=g)
+    sfe, _ = s.thermo()
+    gs = g.reshape(g.shape[0], -1)[:, idx].cpu().numpy()
+    err = np.abs(gs - ref["g_ref"]).max()
+    stop = np.abs(ref["g_tol"] - ref["g_ref"]).max()
+    it_ref = int(ref["iterations_tol"])
+    print(f"  it {info.iterations} (oracle {it_ref}) rms {info.rms:.2e} max|dg| {err:.2e} "
+          f"(oracle stopping error {stop:.2e}) sfe {sfe:.4f} vs {float(ref['sfe_ref']):.4f}",
+          flush=True)
+    assert info.rms < 1e-6
+    assert err <= max(G_TOL, 1.5 * stop)
+    assert abs(sfe - ref["sfe_ref"]) <= SFE_RTOL * abs(ref["sfe_ref"])
+    assert abs(info.iterations - it_ref) <= 0.25 * it_ref
+
+
 def test_empty_solute_is_bulk(R):
     """No solute atoms: u = 0, so g = 1, h = c = 0 is the fixed point (one map)."""
     prob = inputs.small_problem(1, n_atoms=3, shape=(16, 16, 16))
