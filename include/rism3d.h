@@ -154,6 +154,34 @@ rism3d_status rism3d_solve(const rism3d_problem* problem, const rism3d_opts* opt
                            const float* d_tau0, void* d_ws, size_t ws_bytes, float* d_g,
                            rism3d_info* info, hipStream_t stream);
 
+/* Many solutes in one call: for each of the n problems (host array; any mix
+ * of solutes, grids and solvents, one set of options), the work of
+ * rism3d_potential, rism3d_solve and (if thermo != NULL) rism3d_thermo.
+ * Problems whose iteration layout agrees (grid, sites, MDIIS depth,
+ * susceptibility table length and spacing) and whose axis lengths are in
+ * {32, 64, 96, 128, 192, 256, 512} with nz in {64, 96, 128, 256} form a
+ * group; each kernel of an iteration is launched once per group, with one
+ * slab of workgroups per member, and a converged member's workgroups exit at
+ * once while the others iterate.  Other problems iterate as groups of one.
+ * The host reads the members' states after each anchor period.
+ *   d_ws: one device workspace of rism3d_batch_workspace_bytes(n, ...) bytes,
+ *         256-byte aligned, owned by the caller (0 is returned for invalid
+ *         problems or options, with the reason in rism3d_last_error).
+ *   d_tau0: NULL, or a host array of n device pointers (entries may be NULL)
+ *         to starting tau fields as for rism3d_solve.
+ *   d_g: NULL, or a host array of n device pointers (entries may be NULL)
+ *         receiving g of each member.
+ *   info, thermo: NULL, or host arrays of n results.
+ * Returns RISM3D_OK when every member converged; otherwise the status of the
+ * first non-converged member (RISM3D_E_NONFINITE before RISM3D_E_NOCONV),
+ * with every member's results still written. */
+size_t rism3d_batch_workspace_bytes(int n, const rism3d_problem* problems,
+                                    const rism3d_opts* opts);
+rism3d_status rism3d_solve_batch(int n, const rism3d_problem* problems, const rism3d_opts* opts,
+                                 const float* const* d_tau0, void* d_ws, size_t ws_bytes,
+                                 float* const* d_g, rism3d_info* info, rism3d_thermo_out* thermo,
+                                 hipStream_t stream);
+
 /* Eq 17 (HNC), Eq 18 (KH) and the PSE-n form: the solvation free energy of the
  * iterate rism3d_solve returned, as k_B T sum_g rho_g dV sum_r Phi_g(r) with
  * h = g - 1 and c = g - 1 - t, accumulated in float64.  Writes out (host). */

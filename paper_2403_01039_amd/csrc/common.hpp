@@ -136,4 +136,13 @@ __device__ inline float closure_dg(float dref, float delta, int kind, int order)
   return closure_g(dnew, kind, order) - closure_g(dref, kind, order);
 }
 
+// Batched launches: blockIdx.y selects the member of a batch whose
+// workspaces lie bstride bytes apart (bstride = 0 and one member for a single
+// solve).  Null pointers stay null.
+template <typename T>
+__device__ __forceinline__ T* member_ptr(T* p, size_t bstride) {
+  return p ? reinterpret_cast<T*>(reinterpret_cast<uintptr_t>(p) + (size_t)blockIdx.y * bstride)
+           : p;
+}
+
 }  // namespace rism

@@ -344,12 +344,15 @@ __device__ inline void passes_from(C* buf, int nl, const C* tw2, S sgn) {
 template <typename C, int N, int AXIS>
 __global__ __launch_bounds__(kFftThreads) void k_fft_fixed(
     C* __restrict__ data, int nx, int ny, int nz, int npair, const C* __restrict__ tw2_g,
-    int forward, const int* __restrict__ done) {
+    int forward, const int* __restrict__ done, size_t bstride) {
   using S = typename ScalarOf<C>::type;
   constexpr int LINES = fixed_lines<C, N, AXIS>();
   constexpr int TILE = LINES * N;
   constexpr int EPT = (TILE + kFftThreads - 1) / kFftThreads;
+  done = member_ptr(done, bstride);
   if (done && *done) return;
+  data = member_ptr(data, bstride);
+  tw2_g = member_ptr(tw2_g, bstride);
   __shared__ C buf[LINES * Lds<N>::PITCH];
   __shared__ C tw2[2 * N];
   for (int i = threadIdx.x; i < 2 * N; i += kFftThreads) tw2[i] = tw2_g[i];

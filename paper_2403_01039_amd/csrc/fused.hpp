@@ -22,12 +22,20 @@ __global__ __launch_bounds__(kFftThreads) void k_update_fftx(
     const float* __restrict__ res_hist, const float* __restrict__ w,
     const float* __restrict__ tau_ref, float* __restrict__ dg_out, void* __restrict__ spec_v,
     int ny, int nz, int nv, int npair, int M, int kind, int order,
-    const PrecC<ANCHOR>* __restrict__ tw2_g) {
+    const PrecC<ANCHOR>* __restrict__ tw2_g, size_t bstride) {
   using C = PrecC<ANCHOR>;
   using S = typename ScalarOf<C>::type;
   constexpr int LINES = fixed_lines<C, N, 0>();
   constexpr int Q = N / 4;
+  st = member_ptr(st, bstride);
   if (st->done) return;
+  tau_hist = member_ptr(tau_hist, bstride);
+  res_hist = member_ptr(res_hist, bstride);
+  w = member_ptr(w, bstride);
+  tau_ref = member_ptr(tau_ref, bstride);
+  dg_out = member_ptr(dg_out, bstride);
+  spec_v = member_ptr(spec_v, bstride);
+  tw2_g = member_ptr(tw2_g, bstride);
   __shared__ C buf[LINES * Lds<N>::PITCH];
   __shared__ C tw2[2 * N];
   for (int i = threadIdx.x; i < 2 * N; i += kFftThreads) tw2[i] = tw2_g[i];
@@ -70,12 +78,22 @@ __global__ __launch_bounds__(kFftThreads) void k_fftx_residual(
     const float* __restrict__ w, const float* __restrict__ tau_hist, float* __restrict__ res_hist,
     float* __restrict__ tau_ref, float* __restrict__ r_ref, const float* __restrict__ dg, int ny,
     int nz, int nv, int npair, int M, int kind, int order, const PrecC<ANCHOR>* __restrict__ tw2_g,
-    double* __restrict__ partials) {
+    double* __restrict__ partials, size_t bstride) {
   using C = PrecC<ANCHOR>;
   using S = typename ScalarOf<C>::type;
   constexpr int LINES = fixed_lines<C, N, 0>();
   constexpr int Q = N / 4;
+  st = member_ptr(st, bstride);
   if (st->done) return;
+  spec_v = member_ptr(spec_v, bstride);
+  w = member_ptr(w, bstride);
+  tau_hist = member_ptr(tau_hist, bstride);
+  res_hist = member_ptr(res_hist, bstride);
+  tau_ref = member_ptr(tau_ref, bstride);
+  r_ref = member_ptr(r_ref, bstride);
+  dg = member_ptr(dg, bstride);
+  tw2_g = member_ptr(tw2_g, bstride);
+  partials = member_ptr(partials, bstride);
   __shared__ C buf[LINES * Lds<N>::PITCH];
   __shared__ C tw2[2 * N];
   __shared__ double red[kFftThreads / 64];
@@ -143,12 +161,18 @@ __global__ __launch_bounds__(kFftThreads) void k_zcz(
     C* __restrict__ spec, int nx, int ny, const C* __restrict__ tw2_g, float dkx, float dky,
     float dkz, const C* __restrict__ F, const typename ScalarOf<C>::type* __restrict__ chi,
     const typename ScalarOf<C>::type* __restrict__ qtab, float inv_dkt, int m_tab,
-    const int* __restrict__ done) {
+    const int* __restrict__ done, size_t bstride) {
   using S = typename ScalarOf<C>::type;
   constexpr int P = (NV + 1) / 2;
   constexpr int B = zcz_cols<C, NZ, NV>();
   constexpr int LINES = 2 * P * B;     // line l = (side * P + p) * B + b
+  done = member_ptr(done, bstride);
   if (*done) return;
+  spec = member_ptr(spec, bstride);
+  tw2_g = member_ptr(tw2_g, bstride);
+  F = member_ptr(F, bstride);
+  chi = member_ptr(chi, bstride);
+  qtab = member_ptr(qtab, bstride);
   __shared__ C buf[LINES * Lds<NZ>::PITCH];
   __shared__ C tw2[2 * NZ];
   for (int i = threadIdx.x; i < 2 * NZ; i += kFftThreads) tw2[i] = tw2_g[i];

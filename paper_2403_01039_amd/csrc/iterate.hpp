@@ -754,9 +754,12 @@ __device__ inline void control_block(IterState* __restrict__ st_g,
 
 __global__ __launch_bounds__(kRedThreads) void k_control(
     IterState* __restrict__ st_g, const double* __restrict__ partials, int nblocks, int M,
-    double inv_count, double tol, int max_iter, float eta_static, int eta_dynamic) {
+    double inv_count, double tol, int max_iter, float eta_static, int eta_dynamic,
+    size_t bstride) {
   __shared__ ControlScratch cs;
+  st_g = member_ptr(st_g, bstride);
   if (st_g->done) return;
+  partials = member_ptr(partials, bstride);
   control_block(st_g, partials, nblocks, M, inv_count, tol, max_iter, eta_static, eta_dynamic,
                 cs);
 }

@@ -5,6 +5,7 @@
 // Every step of the computation runs in the kernels of setup.hpp, fft.hpp and
 // iterate.hpp.
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -294,10 +295,6 @@ rism3d_status make_layout(const rism3d_problem* pr, const rism3d_opts* op, Layou
     if (b > part_blocks) part_blocks = b;
   }
   L->off_part = take(part_blocks * part_q * sizeof(double));
-  const size_t na = pr->n_atoms > 0 ? (size_t)pr->n_atoms : 1;
-  L->off_atoms = take(na * sizeof(double4));
-  L->off_lj = take(na * nv * sizeof(double2));
-  L->off_ph = take(na * (size_t)(pr->nx + pr->ny + pr->nz) * sizeof(double2));
   L->off_chi32 = take((size_t)L->m_tab * nv * nv * sizeof(float));
   L->off_chi64 = take((size_t)L->m_tab * nv * nv * sizeof(double));
   L->off_q64 = take((size_t)L->m_tab * nv * sizeof(double));
@@ -307,6 +304,13 @@ rism3d_status make_layout(const rism3d_problem* pr, const rism3d_opts* op, Layou
     L->off_tw64[a] = take(2 * (size_t)dims[a] * sizeof(double2));
   }
   L->off_out = take((kMaxSites + 1) * sizeof(double));
+  // Solute-size dependent regions last: every offset above depends only on the
+  // grid, the sites, the MDIIS depth and the table length, so solves of
+  // different solutes on one grid share the offsets the iteration reads.
+  const size_t na = pr->n_atoms > 0 ? (size_t)pr->n_atoms : 1;
+  L->off_atoms = take(na * sizeof(double4));
+  L->off_lj = take(na * nv * sizeof(double2));
+  L->off_ph = take(na * (size_t)(pr->nx + pr->ny + pr->nz) * sizeof(double2));
   L->total = off;
   return RISM3D_OK;
 }
@@ -403,9 +407,16 @@ void launch_contract(const Layout& L, void* ws, bool anchor, float inv_dkt, cons
   }
 }
 
+// A batched launch covers nb members whose workspaces lie stride bytes apart
+// (blockIdx.y selects the member); a single solve is {1, 0}.
+struct Batch {
+  int nb = 1;
+  size_t stride = 0;
+};
+
 template <typename C, int N, int AXIS>
 void launch_fixed_n(const Layout& L, C* spec, const C* tw, int forward, const int* done,
-                    hipStream_t s) {
+                    hipStream_t s, Batch bt = {}) {
   constexpr int LINES = fixed_lines<C, N, AXIS>();
   unsigned grid;
   if (AXIS == 0) {
@@ -416,21 +427,21 @@ void launch_fixed_n(const Layout& L, C* spec, const C* tw, int forward, const in
     const int outer = AXIS == 1 ? L.npair * L.nz : L.npair * L.ny;
     grid = (unsigned)outer * tiles_x;
   }
-  hipLaunchKernelGGL((k_fft_fixed<C, N, AXIS>), dim3(grid), dim3(kFftThreads), 0, s, spec, L.nx,
-                     L.ny, L.nz, L.npair, tw, forward, done);
+  hipLaunchKernelGGL((k_fft_fixed<C, N, AXIS>), dim3(grid, bt.nb), dim3(kFftThreads), 0, s, spec,
+                     L.nx, L.ny, L.nz, L.npair, tw, forward, done, bt.stride);
 }
 
 template <typename C, int AXIS>
 bool launch_fixed_axis(int n, const Layout& L, C* spec, const C* tw, int forward, const int* done,
-                       hipStream_t s) {
+                       hipStream_t s, Batch bt) {
   switch (n) {
-    case 32: launch_fixed_n<C, 32, AXIS>(L, spec, tw, forward, done, s); return true;
-    case 64: launch_fixed_n<C, 64, AXIS>(L, spec, tw, forward, done, s); return true;
-    case 96: launch_fixed_n<C, 96, AXIS>(L, spec, tw, forward, done, s); return true;
-    case 128: launch_fixed_n<C, 128, AXIS>(L, spec, tw, forward, done, s); return true;
-    case 192: launch_fixed_n<C, 192, AXIS>(L, spec, tw, forward, done, s); return true;
-    case 256: launch_fixed_n<C, 256, AXIS>(L, spec, tw, forward, done, s); return true;
-    case 512: launch_fixed_n<C, 512, AXIS>(L, spec, tw, forward, done, s); return true;
+    case 32: launch_fixed_n<C, 32, AXIS>(L, spec, tw, forward, done, s, bt); return true;
+    case 64: launch_fixed_n<C, 64, AXIS>(L, spec, tw, forward, done, s, bt); return true;
+    case 96: launch_fixed_n<C, 96, AXIS>(L, spec, tw, forward, done, s, bt); return true;
+    case 128: launch_fixed_n<C, 128, AXIS>(L, spec, tw, forward, done, s, bt); return true;
+    case 192: launch_fixed_n<C, 192, AXIS>(L, spec, tw, forward, done, s, bt); return true;
+    case 256: launch_fixed_n<C, 256, AXIS>(L, spec, tw, forward, done, s, bt); return true;
+    case 512: launch_fixed_n<C, 512, AXIS>(L, spec, tw, forward, done, s, bt); return true;
     default: return false;
   }
 }
@@ -438,17 +449,17 @@ bool launch_fixed_axis(int n, const Layout& L, C* spec, const C* tw, int forward
 // One axis pass of the shifted transform over all packed pairs.
 template <typename C>
 void launch_axis(const Layout& L, C* spec, const C* const tw[3], int axis, int forward,
-                 const int* done, hipStream_t s) {
+                 const int* done, hipStream_t s, Batch bt = {}) {
   const bool f64 = std::is_same<C, double2>::value;
   const AxisPlan& p = axis == 0 ? L.px : (axis == 1 ? L.py : L.pz);
   TIMED((f64 ? F_FFTX64 : F_FFTX32) + axis, s);
   bool ok = false;
   if (fixed_fft_size(p.n)) {
-    if (axis == 0) ok = launch_fixed_axis<C, 0>(p.n, L, spec, tw[axis], forward, done, s);
-    else if (axis == 1) ok = launch_fixed_axis<C, 1>(p.n, L, spec, tw[axis], forward, done, s);
-    else ok = launch_fixed_axis<C, 2>(p.n, L, spec, tw[axis], forward, done, s);
+    if (axis == 0) ok = launch_fixed_axis<C, 0>(p.n, L, spec, tw[axis], forward, done, s, bt);
+    else if (axis == 1) ok = launch_fixed_axis<C, 1>(p.n, L, spec, tw[axis], forward, done, s, bt);
+    else ok = launch_fixed_axis<C, 2>(p.n, L, spec, tw[axis], forward, done, s, bt);
   }
-  if (ok) return;
+  if (ok) return;   // batches only reach here with fixed-size lengths (batch_plan)
   const int lines = fft_lines_per_block<C>(axis, p.n, L.nx);
   unsigned grid;
   if (axis == 0) {
@@ -504,41 +515,45 @@ bool zcz_supported(const Layout& L) {
 }
 
 template <typename C, int NZ, int NV>
-void launch_zcz_n(const Layout& L, void* ws, float inv_dkt, const int* done, hipStream_t s) {
+void launch_zcz_n(const Layout& L, void* ws, float inv_dkt, const int* done, hipStream_t s,
+                  Batch bt) {
   constexpr bool F64 = std::is_same<C, double2>::value;
   constexpr int B = zcz_cols<C, NZ, NV>();
   const int tiles_x = (L.nx + B - 1) / B;
-  const dim3 grid((unsigned)(L.ny / 2) * tiles_x), block(kFftThreads);
+  const dim3 grid((unsigned)(L.ny / 2) * tiles_x, bt.nb), block(kFftThreads);
   using S = typename ScalarOf<C>::type;
   TIMED(F64 ? F_ZCZ64 : F_ZCZ32, s);
   hipLaunchKernelGGL((k_zcz<C, NZ, NV, F64>), grid, block, 0, s, at<C>(ws, L.off_spec), L.nx,
                      L.ny, at<C>(ws, F64 ? L.off_tw64[2] : L.off_tw32[2]), (float)L.dkx,
                      (float)L.dky, (float)L.dkz, F64 ? at<C>(ws, L.off_F) : (const C*)nullptr,
                      at<S>(ws, F64 ? L.off_chi64 : L.off_chi32),
-                     F64 ? at<S>(ws, L.off_q64) : (const S*)nullptr, inv_dkt, L.m_tab, done);
+                     F64 ? at<S>(ws, L.off_q64) : (const S*)nullptr, inv_dkt, L.m_tab, done,
+                     bt.stride);
 }
 
 template <typename C, int NZ>
-void launch_zcz_nz(const Layout& L, void* ws, float inv_dkt, const int* done, hipStream_t s) {
+void launch_zcz_nz(const Layout& L, void* ws, float inv_dkt, const int* done, hipStream_t s,
+                   Batch bt) {
   switch (L.nv) {
-    case 1: launch_zcz_n<C, NZ, 1>(L, ws, inv_dkt, done, s); break;
-    case 2: launch_zcz_n<C, NZ, 2>(L, ws, inv_dkt, done, s); break;
-    case 3: launch_zcz_n<C, NZ, 3>(L, ws, inv_dkt, done, s); break;
-    case 4: launch_zcz_n<C, NZ, 4>(L, ws, inv_dkt, done, s); break;
-    case 5: launch_zcz_n<C, NZ, 5>(L, ws, inv_dkt, done, s); break;
-    case 6: launch_zcz_n<C, NZ, 6>(L, ws, inv_dkt, done, s); break;
-    case 7: launch_zcz_n<C, NZ, 7>(L, ws, inv_dkt, done, s); break;
-    default: launch_zcz_n<C, NZ, 8>(L, ws, inv_dkt, done, s); break;
+    case 1: launch_zcz_n<C, NZ, 1>(L, ws, inv_dkt, done, s, bt); break;
+    case 2: launch_zcz_n<C, NZ, 2>(L, ws, inv_dkt, done, s, bt); break;
+    case 3: launch_zcz_n<C, NZ, 3>(L, ws, inv_dkt, done, s, bt); break;
+    case 4: launch_zcz_n<C, NZ, 4>(L, ws, inv_dkt, done, s, bt); break;
+    case 5: launch_zcz_n<C, NZ, 5>(L, ws, inv_dkt, done, s, bt); break;
+    case 6: launch_zcz_n<C, NZ, 6>(L, ws, inv_dkt, done, s, bt); break;
+    case 7: launch_zcz_n<C, NZ, 7>(L, ws, inv_dkt, done, s, bt); break;
+    default: launch_zcz_n<C, NZ, 8>(L, ws, inv_dkt, done, s, bt); break;
   }
 }
 
 template <typename C>
-void launch_zcz(const Layout& L, void* ws, float inv_dkt, const int* done, hipStream_t s) {
+void launch_zcz(const Layout& L, void* ws, float inv_dkt, const int* done, hipStream_t s,
+                Batch bt) {
   switch (L.nz) {
-    case 64: launch_zcz_nz<C, 64>(L, ws, inv_dkt, done, s); break;
-    case 96: launch_zcz_nz<C, 96>(L, ws, inv_dkt, done, s); break;
-    case 128: launch_zcz_nz<C, 128>(L, ws, inv_dkt, done, s); break;
-    default: launch_zcz_nz<C, 256>(L, ws, inv_dkt, done, s); break;
+    case 64: launch_zcz_nz<C, 64>(L, ws, inv_dkt, done, s, bt); break;
+    case 96: launch_zcz_nz<C, 96>(L, ws, inv_dkt, done, s, bt); break;
+    case 128: launch_zcz_nz<C, 128>(L, ws, inv_dkt, done, s, bt); break;
+    default: launch_zcz_nz<C, 256>(L, ws, inv_dkt, done, s, bt); break;
   }
 }
 
@@ -546,21 +561,22 @@ void launch_zcz(const Layout& L, void* ws, float inv_dkt, const int* done, hipSt
 // update+closure and with the residual+Gram+control).
 template <bool ANCHOR, int N>
 void launch_fused_n(const Layout& L, void* ws, const rism3d_opts* op, bool first_half,
-                    hipStream_t s) {
+                    hipStream_t s, Batch bt) {
   using C = PrecC<ANCHOR>;
   constexpr int LINES = fixed_lines<C, N, 0>();
   IterState* st = at<IterState>(ws, L.off_state);
   const int kind = (int)op->closure;
   const int order = op->closure == RISM3D_PSE ? op->pse_order : 1;
   const size_t rows = (size_t)L.npair * L.nz * L.ny;
-  const dim3 grid((unsigned)((rows + LINES - 1) / LINES)), block(kFftThreads);
+  const dim3 grid((unsigned)((rows + LINES - 1) / LINES), bt.nb), block(kFftThreads);
   const C* tw = at<C>(ws, ANCHOR ? L.off_tw64[0] : L.off_tw32[0]);
   if (first_half) {
     TIMED(ANCHOR ? F_UPDFFT64 : F_UPDFFT32, s);
     hipLaunchKernelGGL((k_update_fftx<ANCHOR, N>), grid, block, 0, s, st,
                        at<float>(ws, L.off_tau), at<float>(ws, L.off_res), at<float>(ws, L.off_w),
                        at<float>(ws, L.off_tref), at<float>(ws, L.off_dg),
-                       at<void>(ws, L.off_spec), L.ny, L.nz, L.nv, L.npair, L.M, kind, order, tw);
+                       at<void>(ws, L.off_spec), L.ny, L.nz, L.nv, L.npair, L.M, kind, order, tw,
+                       bt.stride);
   } else {
     {
       TIMED(ANCHOR ? F_FFTRES64 : F_FFTRES32, s);
@@ -569,27 +585,27 @@ void launch_fused_n(const Layout& L, void* ws, const rism3d_opts* op, bool first
                          at<float>(ws, L.off_tau), at<float>(ws, L.off_res),
                          at<float>(ws, L.off_tref), at<float>(ws, L.off_rref),
                          at<float>(ws, L.off_dg), L.ny, L.nz, L.nv, L.npair, L.M, kind, order, tw,
-                         at<double>(ws, L.off_part));
+                         at<double>(ws, L.off_part), bt.stride);
     }
     TIMED(F_CONTROL, s);
     const double inv_count = 1.0 / ((double)L.N * (double)L.nv);
-    hipLaunchKernelGGL(k_control, dim3(1), dim3(kRedThreads), 0, s, st,
+    hipLaunchKernelGGL(k_control, dim3(1, bt.nb), dim3(kRedThreads), 0, s, st,
                        at<double>(ws, L.off_part), (int)grid.x, L.M, inv_count, op->tol,
-                       op->max_iter, (float)op->mdiis_eta, op->eta_dynamic);
+                       op->max_iter, (float)op->mdiis_eta, op->eta_dynamic, bt.stride);
   }
 }
 
 template <bool ANCHOR>
 void launch_fused(const Layout& L, void* ws, const rism3d_opts* op, bool first_half,
-                  hipStream_t s) {
+                  hipStream_t s, Batch bt) {
   switch (L.nx) {
-    case 32: launch_fused_n<ANCHOR, 32>(L, ws, op, first_half, s); break;
-    case 64: launch_fused_n<ANCHOR, 64>(L, ws, op, first_half, s); break;
-    case 96: launch_fused_n<ANCHOR, 96>(L, ws, op, first_half, s); break;
-    case 128: launch_fused_n<ANCHOR, 128>(L, ws, op, first_half, s); break;
-    case 192: launch_fused_n<ANCHOR, 192>(L, ws, op, first_half, s); break;
-    case 256: launch_fused_n<ANCHOR, 256>(L, ws, op, first_half, s); break;
-    default: launch_fused_n<ANCHOR, 512>(L, ws, op, first_half, s); break;
+    case 32: launch_fused_n<ANCHOR, 32>(L, ws, op, first_half, s, bt); break;
+    case 64: launch_fused_n<ANCHOR, 64>(L, ws, op, first_half, s, bt); break;
+    case 96: launch_fused_n<ANCHOR, 96>(L, ws, op, first_half, s, bt); break;
+    case 128: launch_fused_n<ANCHOR, 128>(L, ws, op, first_half, s, bt); break;
+    case 192: launch_fused_n<ANCHOR, 192>(L, ws, op, first_half, s, bt); break;
+    case 256: launch_fused_n<ANCHOR, 256>(L, ws, op, first_half, s, bt); break;
+    default: launch_fused_n<ANCHOR, 512>(L, ws, op, first_half, s, bt); break;
   }
 }
 
@@ -597,14 +613,14 @@ void launch_fused(const Layout& L, void* ws, const rism3d_opts* op, bool first_h
 // closure, forward FFT, contraction, inverse FFT, residual + Gram row, control.
 // anchor: FP64 evaluation that re-bases the FP32 increments.
 void launch_iteration(const Layout& L, void* ws, const rism3d_opts* op, float inv_dkt,
-                      bool anchor, hipStream_t s) {
+                      bool anchor, hipStream_t s, Batch bt = {}) {
   IterState* st = at<IterState>(ws, L.off_state);
   const int* done = &st->done;
   const int kind = (int)op->closure;
   const int order = op->closure == RISM3D_PSE ? op->pse_order : 1;
   if (fixed_fft_size(L.nx)) {
-    if (anchor) launch_fused<true>(L, ws, op, true, s);
-    else launch_fused<false>(L, ws, op, true, s);
+    if (anchor) launch_fused<true>(L, ws, op, true, s, bt);
+    else launch_fused<false>(L, ws, op, true, s, bt);
     if (zcz_supported(L)) {
       // y pass, then z + contraction + z fused, then inverse y pass
       const float2* tw32[3] = {at<float2>(ws, L.off_tw32[0]), at<float2>(ws, L.off_tw32[1]),
@@ -612,13 +628,13 @@ void launch_iteration(const Layout& L, void* ws, const rism3d_opts* op, float in
       const double2* tw64[3] = {at<double2>(ws, L.off_tw64[0]), at<double2>(ws, L.off_tw64[1]),
                                 at<double2>(ws, L.off_tw64[2])};
       if (anchor) {
-        launch_axis(L, at<double2>(ws, L.off_spec), tw64, 1, 1, done, s);
-        launch_zcz<double2>(L, ws, inv_dkt, done, s);
-        launch_axis(L, at<double2>(ws, L.off_spec), tw64, 1, 0, done, s);
+        launch_axis(L, at<double2>(ws, L.off_spec), tw64, 1, 1, done, s, bt);
+        launch_zcz<double2>(L, ws, inv_dkt, done, s, bt);
+        launch_axis(L, at<double2>(ws, L.off_spec), tw64, 1, 0, done, s, bt);
       } else {
-        launch_axis(L, at<float2>(ws, L.off_spec), tw32, 1, 1, done, s);
-        launch_zcz<float2>(L, ws, inv_dkt, done, s);
-        launch_axis(L, at<float2>(ws, L.off_spec), tw32, 1, 0, done, s);
+        launch_axis(L, at<float2>(ws, L.off_spec), tw32, 1, 1, done, s, bt);
+        launch_zcz<float2>(L, ws, inv_dkt, done, s, bt);
+        launch_axis(L, at<float2>(ws, L.off_spec), tw32, 1, 0, done, s, bt);
       }
     } else {
       if (anchor) launch_fft3<double2>(L, ws, 1, done, s, true);
@@ -627,8 +643,8 @@ void launch_iteration(const Layout& L, void* ws, const rism3d_opts* op, float in
       if (anchor) launch_fft3<double2>(L, ws, 0, done, s, true);
       else launch_fft3<float2>(L, ws, 0, done, s, true);
     }
-    if (anchor) launch_fused<true>(L, ws, op, false, s);
-    else launch_fused<false>(L, ws, op, false, s);
+    if (anchor) launch_fused<true>(L, ws, op, false, s, bt);
+    else launch_fused<false>(L, ws, op, false, s, bt);
     return;
   }
   const bool v4 = (L.N % 4) == 0;
@@ -671,7 +687,7 @@ void launch_iteration(const Layout& L, void* ws, const rism3d_opts* op, float in
     TIMED(F_CONTROL, s);
     hipLaunchKernelGGL(k_control, dim3(1), dim3(kRedThreads), 0, s, st, at<double>(ws, L.off_part),
                        (int)nblk, L.M, inv_count, op->tol, op->max_iter, (float)op->mdiis_eta,
-                       op->eta_dynamic);
+                       op->eta_dynamic, (size_t)0);
   }
 }
 
@@ -722,12 +738,12 @@ hipStream_t capture_stream() {
 }
 
 std::string graph_key(const Layout& L, const void* ws, const rism3d_opts* op, float inv_dkt,
-                      int every) {
+                      int every, Batch bt) {
   char buf[512];
-  snprintf(buf, sizeof(buf), "%p|%zu|%d,%d,%d,%d,%d,%d|%d,%d,%.17g,%d,%.17g,%d,%d|%a|%d",
+  snprintf(buf, sizeof(buf), "%p|%zu|%d,%d,%d,%d,%d,%d|%d,%d,%.17g,%d,%.17g,%d,%d|%a|%d|%d,%zu",
            ws, L.total, L.nx, L.ny, L.nz, L.nv, L.M, L.m_tab, (int)op->closure, op->pse_order,
            op->tol, op->max_iter, op->mdiis_eta, op->eta_dynamic, every, (double)inv_dkt,
-           g_timer.on ? g_timer.only : -2);
+           g_timer.on ? g_timer.only : -2, bt.nb, bt.stride);
   return buf;
 }
 
@@ -741,8 +757,8 @@ void drop_graph(GraphEntry* e) {
 }
 
 GraphEntry* graph_for(const Layout& L, void* ws, const rism3d_opts* op, float inv_dkt, int every,
-                      hipStream_t s) {
-  const std::string key = graph_key(L, ws, op, inv_dkt, every);
+                      hipStream_t s, Batch bt = {}) {
+  const std::string key = graph_key(L, ws, op, inv_dkt, every, bt);
   std::lock_guard<std::mutex> lock(g_graph_mu);
   for (size_t i = 0; i < g_graphs.size(); ++i) {
     if (g_graphs[i]->key == key) {
@@ -770,7 +786,7 @@ GraphEntry* graph_for(const Layout& L, void* ws, const rism3d_opts* op, float in
   g_capture_bad = false;
   for (int k = 0; k < every; ++k) {
     g_iter_tag = k;
-    launch_iteration(L, ws, op, inv_dkt, k == 0, cs);
+    launch_iteration(L, ws, op, inv_dkt, k == 0, cs, bt);
   }
   g_iter_tag = -1;
   g_capturing = false;
@@ -795,30 +811,9 @@ GraphEntry* graph_for(const Layout& L, void* ws, const rism3d_opts* op, float in
   return e;
 }
 
-}  // namespace
-
-extern "C" {
-
-void rism3d_use_graphs(int on) { g_use_graphs = on != 0; }
-
-void rism3d_release_graphs(void) {
-  std::lock_guard<std::mutex> lock(g_graph_mu);
-  for (GraphEntry* e : g_graphs) drop_graph(e);
-  g_graphs.clear();
-}
-
-size_t rism3d_workspace_bytes(const rism3d_problem* problem, const rism3d_opts* opts) {
-  Layout L;
-  if (make_layout(problem, opts, &L) != RISM3D_OK) return 0;
-  return L.total;
-}
-
-rism3d_status rism3d_potential(const rism3d_problem* pr, const rism3d_opts* op, void* ws,
-                               size_t ws_bytes, hipStream_t s) {
-  Layout L;
-  rism3d_status st = make_layout(pr, op, &L);
-  if (st != RISM3D_OK) return st;
-  if ((st = check_ws(L, ws, ws_bytes)) != RISM3D_OK) return st;
+// Potential, long-range spectrum, susceptibility and twiddle tables of one
+// problem into its workspace (the work of rism3d_potential after validation).
+rism3d_status prepare(const rism3d_problem* pr, const Layout& L, void* ws, hipStream_t s) {
   const double r0x = pr->center[0] - (pr->nx / 2) * pr->spacing;
   const double r0y = pr->center[1] - (pr->ny / 2) * pr->spacing;
   const double r0z = pr->center[2] - (pr->nz / 2) * pr->spacing;
@@ -863,6 +858,145 @@ rism3d_status rism3d_potential(const rism3d_problem* pr, const rism3d_opts* op, 
   LAUNCH_CHECK();
   return RISM3D_OK;
 }
+
+// Launches the SFE density sums of a solved workspace into its output slot
+// (read back with read_sfe after the stream synchronises).
+void launch_sfe(const rism3d_problem* pr, const rism3d_opts* op, const Layout& L, void* ws,
+                hipStream_t s) {
+  const SiteConsts sc = site_consts(pr, L.beta);
+  unsigned nblk = blocks_for(L.N, kRedThreads);
+  if (nblk > (unsigned)kRedBlocks) nblk = kRedBlocks;
+  {
+    TIMED(F_SFE, s);
+    hipLaunchKernelGGL(k_sfe_partial, dim3(nblk), dim3(kRedThreads), 0, s,
+                       at<IterState>(ws, L.off_state), at<float>(ws, L.off_tau),
+                       at<float>(ws, L.off_w), at<float>(ws, L.off_phi), L.N, L.nv,
+                       (int)op->closure, order_of(op), sc, at<double>(ws, L.off_part));
+  }
+  const double scale = L.dv / L.beta;   // k_B T dV
+  hipLaunchKernelGGL(k_sfe_reduce, dim3(1), dim3(kRedThreads), 0, s, at<double>(ws, L.off_part),
+                     (int)nblk, L.nv, scale, sc, at<double>(ws, L.off_out));
+}
+
+void fill_thermo(const double* res, int nv, rism3d_thermo_out* out) {
+  memset(out, 0, sizeof(*out));
+  out->sfe = res[kMaxSites];
+  for (int g = 0; g < nv; ++g) out->sfe_site[g] = res[g];
+}
+
+// ---------------------------------------------------------------------------
+// Batched solves.  Members are grouped by the iteration layout (grid, sites,
+// MDIIS depth, table length and spacing); a group whose axis lengths have the
+// fixed-size fused kernels runs as one batched launch per kernel (blockIdx.y =
+// member), other members as groups of one.  The batch workspace holds a state
+// table (one IterState copy per member, gathered after each chunk) followed by
+// the groups, member m of a group at off + m * stride.
+// ---------------------------------------------------------------------------
+struct BatchGroup {
+  Layout L;                  // layout of the first member, total = the stride
+  float inv_dkt = 0.0f;
+  bool batched = false;
+  size_t off = 0, stride = 0;
+  std::vector<int> members;  // indices into the problem array
+};
+
+__global__ void k_gather_states(const char* __restrict__ base, size_t stride, size_t off_state,
+                                const int* __restrict__ slots, IterState* __restrict__ table) {
+  const int m = blockIdx.x;
+  const int* src = reinterpret_cast<const int*>(base + (size_t)m * stride + off_state);
+  int* dst = reinterpret_cast<int*>(table + slots[m]);
+  for (int i = threadIdx.x; i < (int)(sizeof(IterState) / sizeof(int)); i += blockDim.x)
+    dst[i] = src[i];
+}
+
+bool batchable(const Layout& L) {
+  return fixed_fft_size(L.nx) && fixed_fft_size(L.ny) && zcz_supported(L);
+}
+
+bool same_iteration_layout(const Layout& a, const Layout& b) {
+  return a.nx == b.nx && a.ny == b.ny && a.nz == b.nz && a.nv == b.nv && a.M == b.M &&
+         a.m_tab == b.m_tab && a.off_out == b.off_out;
+}
+
+struct BatchPlan {
+  std::vector<BatchGroup> groups;
+  size_t off_table = 0;   // IterState[n]: member states gathered after each chunk
+  size_t off_index = 0;   // int[n]: problem index of each group member, group by group
+  size_t total = 0;
+};
+
+rism3d_status batch_plan(int n, const rism3d_problem* prs, const rism3d_opts* op,
+                         BatchPlan* plan) {
+  std::vector<BatchGroup>* groups = &plan->groups;
+  if (n < 1 || !prs || !op) return fail(RISM3D_E_ARG, "empty batch or null arguments");
+  groups->clear();
+  for (int i = 0; i < n; ++i) {
+    Layout L;
+    const rism3d_status st = make_layout(&prs[i], op, &L);
+    if (st != RISM3D_OK)
+      return fail(st, "batch member %d: %s", i, g_error.c_str());
+    const float inv_dkt = (float)(1.0 / prs[i].dk);
+    BatchGroup* hit = nullptr;
+    if (batchable(L))
+      for (BatchGroup& g : *groups)
+        if (g.batched && same_iteration_layout(g.L, L) && g.inv_dkt == inv_dkt &&
+            prs[g.members[0]].spacing == prs[i].spacing) {
+          hit = &g;
+          break;
+        }
+    if (hit) {
+      hit->members.push_back(i);
+      if (L.total > hit->L.total) hit->L.total = L.total;
+    } else {
+      BatchGroup g;
+      g.L = L;
+      g.inv_dkt = inv_dkt;
+      g.batched = batchable(L);
+      g.members.push_back(i);
+      groups->push_back(g);
+    }
+  }
+  size_t off = 0;
+  plan->off_table = off;
+  off = align_up(off + (size_t)n * sizeof(IterState));
+  plan->off_index = off;
+  off = align_up(off + (size_t)n * sizeof(int));
+  for (BatchGroup& g : *groups) {
+    g.stride = align_up(g.L.total);
+    g.off = off;
+    off += g.stride * g.members.size();
+  }
+  plan->total = off;
+  return RISM3D_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void rism3d_use_graphs(int on) { g_use_graphs = on != 0; }
+
+void rism3d_release_graphs(void) {
+  std::lock_guard<std::mutex> lock(g_graph_mu);
+  for (GraphEntry* e : g_graphs) drop_graph(e);
+  g_graphs.clear();
+}
+
+size_t rism3d_workspace_bytes(const rism3d_problem* problem, const rism3d_opts* opts) {
+  Layout L;
+  if (make_layout(problem, opts, &L) != RISM3D_OK) return 0;
+  return L.total;
+}
+
+rism3d_status rism3d_potential(const rism3d_problem* pr, const rism3d_opts* op, void* ws,
+                               size_t ws_bytes, hipStream_t s) {
+  Layout L;
+  rism3d_status st = make_layout(pr, op, &L);
+  if (st != RISM3D_OK) return st;
+  if ((st = check_ws(L, ws, ws_bytes)) != RISM3D_OK) return st;
+  return prepare(pr, L, ws, s);
+}
+
 
 rism3d_status rism3d_solve(const rism3d_problem* pr, const rism3d_opts* op, const float* tau0,
                            void* ws, size_t ws_bytes, float* g_out, rism3d_info* info,
@@ -953,26 +1087,173 @@ rism3d_status rism3d_thermo(const rism3d_problem* pr, const rism3d_opts* op, con
   HIP_TRY(hipStreamSynchronize(s));
   if (host.prepared != kPreparedMagic || host.final_slot < 0)
     return fail(RISM3D_E_WORKSPACE, "no solution in the workspace: call rism3d_solve first");
-  const SiteConsts sc = site_consts(pr, L.beta);
-  unsigned nblk = blocks_for(L.N, kRedThreads);
-  if (nblk > (unsigned)kRedBlocks) nblk = kRedBlocks;
-  {
-    TIMED(F_SFE, s);
-    hipLaunchKernelGGL(k_sfe_partial, dim3(nblk), dim3(kRedThreads), 0, s, dst,
-                       at<float>(ws, L.off_tau), at<float>(ws, L.off_w), at<float>(ws, L.off_phi),
-                       L.N, L.nv, (int)op->closure, order_of(op), sc, at<double>(ws, L.off_part));
-  }
-  const double scale = L.dv / L.beta;   // k_B T dV
-  hipLaunchKernelGGL(k_sfe_reduce, dim3(1), dim3(kRedThreads), 0, s, at<double>(ws, L.off_part),
-                     (int)nblk, L.nv, scale, sc, at<double>(ws, L.off_out));
+  launch_sfe(pr, op, L, ws, s);
   LAUNCH_CHECK();
   double res[kMaxSites + 1];
   HIP_TRY(hipMemcpyAsync(res, at<double>(ws, L.off_out), sizeof(res), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   if (g_timer.on) g_timer.harvest();
-  memset(out, 0, sizeof(*out));
-  out->sfe = res[kMaxSites];
-  for (int g = 0; g < L.nv; ++g) out->sfe_site[g] = res[g];
+  fill_thermo(res, L.nv, out);
+  g_error.clear();
+  return RISM3D_OK;
+}
+
+size_t rism3d_batch_workspace_bytes(int n, const rism3d_problem* problems,
+                                    const rism3d_opts* opts) {
+  BatchPlan plan;
+  if (batch_plan(n, problems, opts, &plan) != RISM3D_OK) return 0;
+  return plan.total;
+}
+
+rism3d_status rism3d_solve_batch(int n, const rism3d_problem* prs, const rism3d_opts* op,
+                                 const float* const* tau0, void* ws, size_t ws_bytes,
+                                 float* const* g_out, rism3d_info* info,
+                                 rism3d_thermo_out* thermo, hipStream_t s) {
+  BatchPlan plan;
+  rism3d_status st = batch_plan(n, prs, op, &plan);
+  if (st != RISM3D_OK) return st;
+  if (!ws) return fail(RISM3D_E_WORKSPACE, "null workspace");
+  if (((uintptr_t)ws) & 255) return fail(RISM3D_E_WORKSPACE, "workspace must be 256-byte aligned");
+  if (ws_bytes < plan.total)
+    return fail(RISM3D_E_WORKSPACE, "batch workspace holds %zu bytes, %zu needed", ws_bytes,
+                plan.total);
+  char* base = static_cast<char*>(ws);
+  auto member_ws = [&](const BatchGroup& g, size_t m) -> void* {
+    return base + g.off + m * g.stride;
+  };
+  // problem index of each group member, group by group
+  std::vector<int> index;
+  for (const BatchGroup& g : plan.groups) index.insert(index.end(), g.members.begin(), g.members.end());
+  HIP_TRY(hipMemcpyAsync(base + plan.off_index, index.data(), index.size() * sizeof(int),
+                         hipMemcpyHostToDevice, s));
+  // set-up and start of every member
+  for (const BatchGroup& g : plan.groups)
+    for (size_t m = 0; m < g.members.size(); ++m) {
+      const int i = g.members[m];
+      Layout L;
+      make_layout(&prs[i], op, &L);
+      void* w = member_ws(g, m);
+      if ((st = prepare(&prs[i], L, w, s)) != RISM3D_OK)
+        return fail(st, "batch member %d: %s", i, g_error.c_str());
+      const float* t0 = tau0 ? tau0[i] : nullptr;
+      hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1), 0, s, at<IterState>(w, L.off_state),
+                         (float)op->mdiis_eta, t0 ? 1 : 0);
+      hipLaunchKernelGGL(k_init_tau, dim3(blocks_for((size_t)L.nv * L.N, kElemThreads)),
+                         dim3(kElemThreads), 0, s, t0, at<float>(w, L.off_tau),
+                         (size_t)L.nv * L.N);
+      LAUNCH_CHECK();
+    }
+  const int every = op->anchor_every > 0 ? op->anchor_every : kDefaultAnchorEvery;
+  const size_t ng = plan.groups.size();
+  std::vector<GraphEntry*> graphs(ng, nullptr);
+  std::vector<Batch> batches(ng);
+  for (size_t k = 0; k < ng; ++k) {
+    const BatchGroup& g = plan.groups[k];
+    batches[k] = Batch{(int)g.members.size(), g.batched ? g.stride : 0};
+    if (g_use_graphs)
+      graphs[k] = graph_for(g.L, member_ws(g, 0), op, g.inv_dkt, every, s, batches[k]);
+  }
+  const int chunk_direct = op->check_every > 0 ? op->check_every : kDefaultCheckEvery;
+  std::vector<int> launched(ng, 0), iter_before(n, 0);
+  std::vector<char> finished(ng, 0);
+  std::vector<IterState> host(n);
+  IterState* table = at<IterState>(ws, plan.off_table);
+  const int* index_d = at<int>(ws, plan.off_index);
+  for (;;) {
+    size_t first = 0;
+    for (size_t k = 0; k < ng; ++k) {
+      const BatchGroup& g = plan.groups[k];
+      if (!finished[k]) {
+        if (graphs[k]) {
+          HIP_TRY(hipGraphLaunch(graphs[k]->exec, s));
+          launched[k] += every;
+        } else {
+          const int left = op->max_iter - launched[k];
+          const int todo = left < chunk_direct ? left : chunk_direct;
+          for (int j = 0; j < todo; ++j) {
+            g_iter_tag = j;
+            launch_iteration(g.L, member_ws(g, 0), op, g.inv_dkt,
+                             ((launched[k] + j) % every) == 0, s, batches[k]);
+          }
+          g_iter_tag = -1;
+          launched[k] += todo;
+        }
+        hipLaunchKernelGGL(k_gather_states, dim3((unsigned)g.members.size()), dim3(64), 0, s,
+                           static_cast<const char*>(member_ws(g, 0)), g.stride, g.L.off_state,
+                           index_d + first, table);
+      }
+      first += g.members.size();
+    }
+    LAUNCH_CHECK();
+    HIP_TRY(hipMemcpyAsync(host.data(), table, (size_t)n * sizeof(IterState),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    bool all = true;
+    for (size_t k = 0; k < ng; ++k) {
+      if (finished[k]) continue;
+      const BatchGroup& g = plan.groups[k];
+      bool done = true;
+      int executed = 0;
+      for (int i : g.members) {
+        done = done && host[i].done;
+        executed = std::max(executed, host[i].iter - iter_before[i]);
+        iter_before[i] = host[i].iter;
+      }
+      if (g_timer.on && graphs[k]) graphs[k]->harvest(executed);
+      if (done || launched[k] >= op->max_iter) finished[k] = 1;
+      all = all && finished[k];
+    }
+    if (g_timer.on) g_timer.harvest();
+    if (all) break;
+  }
+  // outputs, SFE and per-member status
+  rism3d_status worst = RISM3D_OK;
+  int worst_member = -1;
+  std::vector<double> sfe((size_t)n * (kMaxSites + 1), 0.0);
+  for (const BatchGroup& g : plan.groups)
+    for (size_t m = 0; m < g.members.size(); ++m) {
+      const int i = g.members[m];
+      Layout L;
+      make_layout(&prs[i], op, &L);
+      void* w = member_ws(g, m);
+      const IterState& h = host[i];
+      if (g_out && g_out[i])
+        hipLaunchKernelGGL(k_output, dim3(blocks_for((size_t)L.nv * L.N, kElemThreads)),
+                           dim3(kElemThreads), 0, s, at<IterState>(w, L.off_state),
+                           at<float>(w, L.off_tau), at<float>(w, L.off_w), L.N, L.nv,
+                           (int)op->closure, order_of(op), g_out[i], (float*)nullptr);
+      if (thermo && h.final_slot >= 0) {
+        launch_sfe(&prs[i], op, L, w, s);
+        HIP_TRY(hipMemcpyAsync(&sfe[(size_t)i * (kMaxSites + 1)], at<double>(w, L.off_out),
+                               (kMaxSites + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+      }
+      LAUNCH_CHECK();
+      rism3d_status ms = RISM3D_OK;
+      if (!h.done || h.status == RISM3D_E_NOCONV) ms = RISM3D_E_NOCONV;
+      if (h.status == RISM3D_E_NONFINITE) ms = RISM3D_E_NONFINITE;
+      if (info) {
+        info[i].iterations = h.iter;
+        info[i].rms = h.last_rms;
+        info[i].restarts = h.restarts;
+        info[i].warm_start_used = h.warm;
+      }
+      if (ms != RISM3D_OK && (worst == RISM3D_OK || ms == RISM3D_E_NONFINITE)) {
+        worst = ms;
+        worst_member = i;
+      }
+    }
+  HIP_TRY(hipStreamSynchronize(s));
+  if (g_timer.on) g_timer.harvest();
+  if (thermo)
+    for (int i = 0; i < n; ++i) {
+      if (host[i].final_slot >= 0) fill_thermo(&sfe[(size_t)i * (kMaxSites + 1)], prs[i].n_sites,
+                                               &thermo[i]);
+      else memset(&thermo[i], 0, sizeof(thermo[i]));
+    }
+  if (worst != RISM3D_OK)
+    return fail(worst, "batch member %d: %s after %d iterations (rms %g)", worst_member,
+                worst == RISM3D_E_NONFINITE ? "non-finite residual" : "no convergence",
+                host[worst_member].iter, host[worst_member].last_rms);
   g_error.clear();
   return RISM3D_OK;
 }

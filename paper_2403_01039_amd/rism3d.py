@@ -84,6 +84,10 @@ def _load():
         "rism3d_timing_reset": (None, []),
         "rism3d_timing_read": (ctypes.c_int, [ctypes.c_int, P(ctypes.c_char_p), P(ctypes.c_long),
                                               P(ctypes.c_double)]),
+        "rism3d_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_void_p, P(Opts)]),
+        "rism3d_solve_batch": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, P(Opts), ctypes.c_void_p,
+                                              ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
         "rism3d_timing_select": (ctypes.c_int, [ctypes.c_char_p]),
         "rism3d_use_graphs": (None, [ctypes.c_int]),
         "rism3d_release_graphs": (None, []),
@@ -102,7 +106,8 @@ EXPORTED = ("rism3d_workspace_bytes", "rism3d_potential", "rism3d_solve", "rism3
             "rism3d_get_tau", "rism3d_map", "rism3d_get_potential",
             "rism3d_transform_workspace_bytes", "rism3d_transform", "rism3d_timing_enable",
             "rism3d_timing_reset", "rism3d_timing_read", "rism3d_use_graphs",
-            "rism3d_release_graphs", "rism3d_timing_select", "rism3d_last_error", "rism3d_constants")
+            "rism3d_release_graphs", "rism3d_timing_select",
+            "rism3d_batch_workspace_bytes", "rism3d_solve_batch", "rism3d_last_error", "rism3d_constants")
 
 
 def last_error() -> str:
@@ -279,6 +284,48 @@ def rism3d_transform(data: torch.Tensor, forward: bool, ws: Optional[torch.Tenso
     _check(LIB.rism3d_transform(nx, ny, nz, count, _ptr(data), int(bool(forward)), _ptr(ws),
                                 ws.numel(), _stream(stream)))
     return data
+
+
+def _problem_array(dps):
+    arr = (Problem * len(dps))()
+    for i, dp in enumerate(dps):
+        arr[i] = dp.struct
+    return arr
+
+
+def rism3d_batch_workspace_bytes(dps, opts: Opts) -> int:
+    arr = _problem_array(dps)
+    n = LIB.rism3d_batch_workspace_bytes(len(dps), ctypes.cast(arr, ctypes.c_void_p),
+                                         ctypes.byref(opts))
+    if n == 0:
+        raise RismError(1, last_error())
+    return n
+
+
+def rism3d_solve_batch(dps, opts: Opts, ws: torch.Tensor, tau0=None, g_out=None, stream=None,
+                       allow_noconv=False, thermo=True):
+    """Batched potential + solve (+ SFE) of several problems; returns the list of
+    Info and the list of (sfe, per-site sfe) or None."""
+    n = len(dps)
+    arr = _problem_array(dps)
+    ptrs = lambda ts: (None if ts is None else
+                       (ctypes.c_void_p * n)(*[_ptr(t) if t is not None else None for t in ts]))
+    tau_arr, g_arr = ptrs(tau0), ptrs(g_out)
+    infos = (Info * n)()
+    th = (ThermoOut * n)() if thermo else None
+    status = LIB.rism3d_solve_batch(n, ctypes.cast(arr, ctypes.c_void_p), ctypes.byref(opts),
+                                    tau_arr and ctypes.cast(tau_arr, ctypes.c_void_p), _ptr(ws),
+                                    ws.numel(), g_arr and ctypes.cast(g_arr, ctypes.c_void_p),
+                                    ctypes.cast(infos, ctypes.c_void_p),
+                                    th and ctypes.cast(th, ctypes.c_void_p), _stream(stream))
+    _check(status, allow=(3, 4) if allow_noconv else ())
+    out_info = list(infos)
+    for inf in out_info:
+        inf.status = status
+    sfe = None
+    if thermo:
+        sfe = [(t.sfe, np.array(t.sfe_site[:dp.shape[0]])) for t, dp in zip(th, dps)]
+    return out_info, sfe
 
 
 # --- convenience -------------------------------------------------------------

@@ -121,3 +121,20 @@ def test_null_workspace_is_rejected_without_device_work(R):
 def test_transform_sizes(R):
     assert R.LIB.rism3d_transform_workspace_bytes(7, 8, 8) == 0
     assert R.LIB.rism3d_transform_workspace_bytes(96, 20, 18) > 0
+
+
+def test_batch_workspace_plan(R):
+    """Two problems on one grid: the batch workspace holds both member
+    workspaces plus a state table; an invalid member is named."""
+    p, keep = _fake_problem(R, n=(64, 24, 32))
+    one = R.LIB.rism3d_workspace_bytes(ctypes.byref(p), ctypes.byref(_opts(R)))
+    arr = (R.Problem * 2)(p, p)
+    two = R.LIB.rism3d_batch_workspace_bytes(2, ctypes.cast(arr, ctypes.c_void_p),
+                                             ctypes.byref(_opts(R)))
+    assert 2 * one < two <= 2 * one + 2 * 256 + 2 * 4096 + 2 * 256
+    arr[1].nx = 7
+    assert R.LIB.rism3d_batch_workspace_bytes(2, ctypes.cast(arr, ctypes.c_void_p),
+                                              ctypes.byref(_opts(R))) == 0
+    assert "batch member 1" in R.last_error()
+    assert R.LIB.rism3d_batch_workspace_bytes(0, ctypes.cast(arr, ctypes.c_void_p),
+                                              ctypes.byref(_opts(R))) == 0

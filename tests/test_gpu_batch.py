@@ -1,0 +1,102 @@
+"""Batched solves (many solutes, uneven grids) through rism3d_solve_batch.
+
+Every member of a batch runs the same kernels as its single solve, with the
+member selected by the launch's second grid dimension, and every reduction
+has a fixed order; so each member's g, iteration count and SFE must equal
+those of its single solve bit for bit.  The single-solve path is itself held
+to the oracle by the parity tests."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2403_01039_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_2403_01039_amd import rism3d
+    return rism3d
+
+
+def _single(R, prob, opts):
+    chi, dk = inputs.solvent_table_for(prob.solvent)
+    dp = R.DeviceProblem(prob, chi, dk)
+    s = R.Solver(dp, opts)
+    s.potential()
+    g = torch.empty(dp.shape, dtype=torch.float32, device="cuda")
+    info = s.solve(g_out=g)
+    sfe, site = s.thermo()
+    return g, info, sfe, site
+
+
+def _batch(R, probs, opts):
+    dps = []
+    for p in probs:
+        chi, dk = inputs.solvent_table_for(p.solvent)
+        dps.append(R.DeviceProblem(p, chi, dk))
+    nbytes = R.rism3d_batch_workspace_bytes(dps, opts)
+    ws = R.alloc_workspace(nbytes)
+    gs = [torch.empty(dp.shape, dtype=torch.float32, device="cuda") for dp in dps]
+    infos, sfe = R.rism3d_solve_batch(dps, opts, ws, g_out=gs)
+    torch.cuda.synchronize()
+    return gs, infos, sfe
+
+
+def _compare(R, probs, opts, members):
+    gs, infos, sfe = _batch(R, probs, opts)
+    for i in members:
+        g1, info1, sfe1, site1 = _single(R, probs[i], opts)
+        print(f"  member {i} {probs[i].grid.nx}x{probs[i].grid.ny}x{probs[i].grid.nz} "
+              f"atoms {probs[i].solute.n_atoms}: it {infos[i].iterations} (single "
+              f"{info1.iterations}) sfe {sfe[i][0]:.6f} (single {sfe1:.6f})", flush=True)
+        assert infos[i].iterations == info1.iterations
+        assert infos[i].rms == info1.rms
+        assert torch.equal(gs[i], g1)
+        assert sfe[i][0] == sfe1
+        assert np.array_equal(sfe[i][1], site1)
+    return infos
+
+
+@pytest.mark.parametrize("graphs", [True, False])
+def test_mixed_batch_equals_single_solves(R, graphs):
+    """Two members share a batched group (same grid, different solutes), one
+    has its own batched grid, one grid has no fused kernels (a group of one)."""
+    print(f"mixed batch, graphs={graphs}", flush=True)
+    R.use_graphs(graphs)
+    try:
+        probs = [inputs.small_problem(21, n_atoms=6, shape=(64, 24, 32), radius=2.5),
+                 inputs.small_problem(22, n_atoms=10, shape=(64, 24, 32), radius=3.0),
+                 inputs.small_problem(23, n_atoms=8, shape=(96, 20, 32), radius=2.5),
+                 inputs.small_problem(24, n_atoms=5, shape=(24, 20, 18), radius=2.5)]
+        opts = R.make_opts(probs[0].options)
+        _compare(R, probs, opts, range(len(probs)))
+    finally:
+        R.use_graphs(True)
+
+
+def test_uneven_batch_64_solutes(R):
+    """The 64-solute uneven batch (20-300 atoms, 96^3 / 128^3 grids, water):
+    every member converges; sampled members of both grids equal their single
+    solves bit for bit."""
+    probs = inputs.batch_uneven_problems()
+    sizes = [p.grid.nx for p in probs]
+    print(f"uneven batch: {sizes.count(96)} x 96^3, {sizes.count(128)} x 128^3", flush=True)
+    opts = R.make_opts(probs[0].options)
+    first96 = sizes.index(96)
+    first128 = sizes.index(128)
+    infos = _compare(R, probs, opts, [first96, first128, len(probs) - 1])
+    assert all(inf.rms < 1e-6 for inf in infos)
+
+
+def test_batch_nonconvergence_reports_member(R):
+    probs = [inputs.small_problem(31, n_atoms=6, shape=(64, 24, 32), radius=2.5),
+             inputs.small_problem(32, n_atoms=6, shape=(64, 24, 32), radius=2.5)]
+    opts = R.make_opts(probs[0].options, max_iter=5)
+    dps = [R.DeviceProblem(p, *inputs.solvent_table_for(p.solvent)) for p in probs]
+    ws = R.alloc_workspace(R.rism3d_batch_workspace_bytes(dps, opts))
+    infos, sfe = R.rism3d_solve_batch(dps, opts, ws, allow_noconv=True)
+    assert infos[0].status == 3
+    assert all(inf.iterations == 5 for inf in infos)
+    assert "batch member" in R.last_error()
