@@ -145,4 +145,22 @@ __device__ __forceinline__ T* member_ptr(T* p, size_t bstride) {
            : p;
 }
 
+// Row width of the susceptibility tables: the nv*nv values of one k-sample,
+// padded to whole 16-byte vectors.
+template <typename S>
+__host__ __device__ constexpr int chi_row(int nv) {
+  return sizeof(S) == 4 ? ((nv * nv + 3) & ~3) : ((nv * nv + 1) & ~1);
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip (block b
+// runs on XCD b % 8).  xcd_tile maps block b to a tile index such that each
+// XCD takes one contiguous run of tiles, in order; neighbouring tiles that
+// share 128-byte lines then meet in the same L2.  A bijection on [0, G).
+__device__ __forceinline__ int xcd_tile(int b, int G) {
+  constexpr int X = 8;
+  const int x = b % X, i = b / X;
+  const int q = G / X, r = G % X;
+  return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
 }  // namespace rism

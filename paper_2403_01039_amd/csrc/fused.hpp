@@ -106,9 +106,29 @@ __global__ __launch_bounds__(kFftThreads) void k_fftx_residual(
   const int dest = st->dest;
   const unsigned mask = other_slots(st, M, dest);
   const C* spec = static_cast<const C*>(spec_v) + row0 * N;
-  for (int f = threadIdx.x; f < nl * N; f += kFftThreads) {
-    const int b = f / N, i = f - b * N;
-    buf[Lds<N>::at(b, i)] = spec[f];
+  if constexpr (ANCHOR) {
+    for (int f = threadIdx.x; f < nl * N; f += kFftThreads) {
+      const int b = f / N, i = f - b * N;
+      buf[Lds<N>::at(b, i)] = spec[f];
+    }
+  } else {
+    // every load of the tile in flight before the first LDS store (the FP64
+    // variant keeps the plain loop: staging its tile would spill)
+    constexpr int EPT = (LINES * N + kFftThreads - 1) / kFftThreads;
+    C v[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int f = threadIdx.x + e * kFftThreads;
+      if (f < nl * N) v[e] = spec[f];
+    }
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int f = threadIdx.x + e * kFftThreads;
+      if (f < nl * N) {
+        const int b = f / N, i = f - b * N;
+        buf[Lds<N>::at(b, i)] = v[e];
+      }
+    }
   }
   __syncthreads();
   passes_from<0, 1, N, LINES>(buf, nl, tw2, S(1));
@@ -177,8 +197,9 @@ __global__ __launch_bounds__(kFftThreads) void k_zcz(
   __shared__ C tw2[2 * NZ];
   for (int i = threadIdx.x; i < 2 * NZ; i += kFftThreads) tw2[i] = tw2_g[i];
   const int tiles_x = (nx + B - 1) / B;
-  const int jy = blockIdx.x / tiles_x;                 // 0 .. ny/2 - 1
-  const int x0 = (blockIdx.x - jy * tiles_x) * B;
+  const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+  const int jy = tile / tiles_x;                       // 0 .. ny/2 - 1
+  const int x0 = (tile - jy * tiles_x) * B;
   const int nb = (nx - x0) < B ? (nx - x0) : B;
   const int jy2 = ny - 1 - jy;
   const size_t N = (size_t)nx * ny * NZ;
@@ -189,15 +210,34 @@ __global__ __launch_bounds__(kFftThreads) void k_zcz(
     return (size_t)p * N + (size_t)z * zs + (size_t)(side ? jy2 : jy) * nx + x;
   };
   const int total = 2 * P * nb * NZ;
-  __syncthreads();
-  for (int f = threadIdx.x; f < total; f += kFftThreads) {
-    const int b = f % nb;
-    const int r = f / nb;                // (side, p, z) with z fastest after b
-    const int z = r % NZ;
-    const int sp = r / NZ;               // side * P + p
-    const int side = sp / P, p = sp - side * P;
-    const C v = spec[addr(side, p, b, z)];
-    buf[Lds<NZ>::at(sp * B + b, z)] = cmul(v, tw2[z]);
+  {
+    // every load of the tile in flight before the first LDS store
+    constexpr int EPT = (2 * P * B * NZ + kFftThreads - 1) / kFftThreads;
+    C v[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int f = threadIdx.x + e * kFftThreads;
+      if (f < total) {
+        const int b = f % nb;
+        const int r = f / nb;              // (side, p, z) with z fastest after b
+        const int z = r % NZ;
+        const int sp = r / NZ;             // side * P + p
+        const int side = sp / P, p = sp - side * P;
+        v[e] = spec[addr(side, p, b, z)];
+      }
+    }
+    __syncthreads();   // twiddles visible
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int f = threadIdx.x + e * kFftThreads;
+      if (f < total) {
+        const int b = f % nb;
+        const int r = f / nb;
+        const int z = r % NZ;
+        const int sp = r / NZ;
+        buf[Lds<NZ>::at(sp * B + b, z)] = cmul(v[e], tw2[z]);
+      }
+    }
   }
   __syncthreads();
   // forward z passes over all 2 P B lines (unused tail lines carry stale data and are not stored)
@@ -237,25 +277,8 @@ __global__ __launch_bounds__(kFftThreads) void k_zcz(
       const size_t Lb = N - 1 - L;
       Fk = L < (N + 1) / 2 ? F[L] : cconj(F[Lb]);
     }
-    const S* c0 = chi + (size_t)m * NV * NV;
-    const S* c1 = c0 + NV * NV;
     C H[NV];
-#pragma unroll
-    for (int g = 0; g < NV; ++g) {
-      C acc = make_c(S(0), S(0));
-      if (WITHF) {
-        const S* q0 = qtab + (size_t)m * NV;
-        const S Q = q0[g] + fr * (q0[NV + g] - q0[g]);
-        acc = make_c(-Fk.x * Q, -Fk.y * Q);
-      }
-#pragma unroll
-      for (int gp = 0; gp < NV; ++gp) {
-        const S c = c0[gp * NV + g] + fr * (c1[gp * NV + g] - c0[gp * NV + g]);
-        acc.x += X[gp].x * c;
-        acc.y += X[gp].y * c;
-      }
-      H[g] = acc;
-    }
+    contract_point<NV, C, WITHF>(X, Fk, m, fr, chi, qtab, H);
 #pragma unroll
     for (int p = 0; p < P; ++p) {
       const C a = H[2 * p];

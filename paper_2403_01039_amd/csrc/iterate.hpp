@@ -238,6 +238,53 @@ __device__ inline float kappa_f(int j, int n, float dk) {
   return (2 * j < n) ? (j + 0.5f) * dk : (j + 0.5f - n) * dk;
 }
 
+// The contraction of Eq 13 at one k-point with the analytic long-range term
+// of Eq 32: H_g = sum_g' X_g' chi_g'g(|k|) - F(k) Q_g(|k|), chi and Q linear
+// in |k| between table samples m and m+1 (weight fr).  A table row holds the
+// NV*NV values of one sample padded to whole 16-byte vectors (chi_row), so a
+// row is fetched with NV*NV/4 (FP32) or NV*NV/2 (FP64) vector loads.
+__device__ __forceinline__ void unpack_vec(float* d, const float4& v) {
+  d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+}
+__device__ __forceinline__ void unpack_vec(double* d, const double2& v) {
+  d[0] = v.x; d[1] = v.y;
+}
+
+template <int NV, typename C, bool WITHF>
+__device__ __forceinline__ void contract_point(const C (&X)[NV], C Fk, int m,
+                                               typename ScalarOf<C>::type fr,
+                                               const typename ScalarOf<C>::type* __restrict__ chi,
+                                               const typename ScalarOf<C>::type* __restrict__ qtab,
+                                               C (&H)[NV]) {
+  using S = typename ScalarOf<C>::type;
+  using V = typename std::conditional<sizeof(S) == 4, float4, double2>::type;
+  constexpr int RW = chi_row<S>(NV);
+  constexpr int VW = (int)(sizeof(V) / sizeof(S));
+  S r0[RW], r1[RW];
+  const V* v0 = reinterpret_cast<const V*>(chi + (size_t)m * RW);
+#pragma unroll
+  for (int i = 0; i < RW / VW; ++i) {
+    unpack_vec(&r0[i * VW], v0[i]);
+    unpack_vec(&r1[i * VW], v0[RW / VW + i]);
+  }
+#pragma unroll
+  for (int g = 0; g < NV; ++g) {
+    C acc = make_c(S(0), S(0));
+    if (WITHF) {
+      const S* q0 = qtab + (size_t)m * NV;
+      const S Q = q0[g] + fr * (q0[NV + g] - q0[g]);
+      acc = make_c(-Fk.x * Q, -Fk.y * Q);
+    }
+#pragma unroll
+    for (int gp = 0; gp < NV; ++gp) {
+      const S c = r0[gp * NV + g] + fr * (r1[gp * NV + g] - r0[gp * NV + g]);
+      acc.x += X[gp].x * c;
+      acc.y += X[gp].y * c;
+    }
+    H[g] = acc;
+  }
+}
+
 template <int NV, typename C, bool WITHF>
 __global__ __launch_bounds__(kElemThreads) void k_contract(
     C* __restrict__ spec, int nx, int ny, int nz, float dkx, float dky, float dkz,
@@ -278,25 +325,8 @@ __global__ __launch_bounds__(kElemThreads) void k_contract(
   }
   C Fk = make_c(S(0), S(0));
   if (WITHF) Fk = F[L];
-  const S* c0 = chi + (size_t)m * NV * NV;
-  const S* c1 = c0 + NV * NV;
   C H[NV];
-#pragma unroll
-  for (int g = 0; g < NV; ++g) {
-    C acc = make_c(S(0), S(0));
-    if (WITHF) {
-      const S* q0 = qtab + (size_t)m * NV;
-      const S Q = q0[g] + fr * (q0[NV + g] - q0[g]);
-      acc = make_c(-Fk.x * Q, -Fk.y * Q);
-    }
-#pragma unroll
-    for (int gp = 0; gp < NV; ++gp) {
-      const S c = c0[gp * NV + g] + fr * (c1[gp * NV + g] - c0[gp * NV + g]);
-      acc.x += X[gp].x * c;
-      acc.y += X[gp].y * c;
-    }
-    H[g] = acc;
-  }
+  contract_point<NV, C, WITHF>(X, Fk, m, fr, chi, qtab, H);
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
     const C a = H[2 * p];

@@ -295,8 +295,8 @@ rism3d_status make_layout(const rism3d_problem* pr, const rism3d_opts* op, Layou
     if (b > part_blocks) part_blocks = b;
   }
   L->off_part = take(part_blocks * part_q * sizeof(double));
-  L->off_chi32 = take((size_t)L->m_tab * nv * nv * sizeof(float));
-  L->off_chi64 = take((size_t)L->m_tab * nv * nv * sizeof(double));
+  L->off_chi32 = take((size_t)L->m_tab * chi_row<float>((int)nv) * sizeof(float));
+  L->off_chi64 = take((size_t)L->m_tab * chi_row<double>((int)nv) * sizeof(double));
   L->off_q64 = take((size_t)L->m_tab * nv * sizeof(double));
   const int dims[3] = {pr->nx, pr->ny, pr->nz};
   for (int a = 0; a < 3; ++a) {

@@ -165,12 +165,17 @@ __global__ void k_chi_tables(const double* __restrict__ chi, int nv, int n_k, in
   if (t >= m_tab * nv) return;
   const int m = t / nv;
   const int b = t - m * nv;
+  const int rw32 = chi_row<float>(nv), rw64 = chi_row<double>(nv);
   double qs = 0.0;
   for (int a = 0; a < nv; ++a) {
     const double v = chi[((size_t)a * nv + b) * n_k + m];
-    chi32[((size_t)m * nv + a) * nv + b] = (float)(v * inv_n);
-    chi64[((size_t)m * nv + a) * nv + b] = v * inv_n;
+    chi32[(size_t)m * rw32 + a * nv + b] = (float)(v * inv_n);
+    chi64[(size_t)m * rw64 + a * nv + b] = v * inv_n;
     qs += sc.q64[a] * v;
+  }
+  if (b == 0) {   // row padding (never read into the arithmetic)
+    for (int i = nv * nv; i < rw32; ++i) chi32[(size_t)m * rw32 + i] = 0.0f;
+    for (int i = nv * nv; i < rw64; ++i) chi64[(size_t)m * rw64 + i] = 0.0;
   }
   q64[(size_t)m * nv + b] = qs * inv_n;
 }
