@@ -330,3 +330,36 @@ def solvent_table_for(solvent: Solvent):
     if names == saline_solvent().site_names():
         return solvent_table("saline")
     raise KeyError(f"no stored susceptibility table for sites {names}")
+
+
+# ---------------------------------------------------------------------------
+# Warm-start network parameters (seeded initial values; both sides take them
+# as inputs)
+# ---------------------------------------------------------------------------
+
+def unet_init_params(layers, seed: int, slope: float = 0.1, scale: float = 1.0) -> np.ndarray:
+    """Flat FP32 parameter vector for the convolution list ``layers`` =
+    [(name, C_in, C_out), ...]: per layer W[C_out, 27, C_in] then b[C_out].
+    He-normal weights for a leaky slope (fan-in 27 C_in) times ``scale``, zero
+    biases, and a zero output layer (named "out")."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for name, ci, co in layers:
+        if name == "out":
+            W = np.zeros((co, 27, ci))
+        else:
+            std = scale * np.sqrt(2.0 / (1.0 + slope ** 2) / (27 * ci))
+            W = rng.standard_normal((co, 27, ci)) * std
+        parts += [W.ravel(), np.zeros(co)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def unet_random_params(layers, seed: int, scale: float = 0.5) -> np.ndarray:
+    """Random parameters for gradient checks: every layer (the output layer
+    and the biases too) drawn N(0, scale^2 / (27 C_in))."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for name, ci, co in layers:
+        std = scale / np.sqrt(27 * ci)
+        parts += [rng.standard_normal(co * 27 * ci) * std, rng.standard_normal(co) * std]
+    return np.concatenate(parts).astype(np.float32)
