@@ -220,6 +220,84 @@ size_t rism3d_transform_workspace_bytes(int nx, int ny, int nz);
 rism3d_status rism3d_transform(int nx, int ny, int nz, int count, void* d_data, int forward,
                                void* d_ws, size_t ws_bytes, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Learned warm start (not in the paper, which starts every solve at t = f):
+ * a 3D convolutional encoder-decoder maps the solute potential of each
+ * solvent site to an initial short-range direct correlation c0; one
+ * Ornstein-Zernike half-step (Eq 32, Eq 13 and the inverse transform of
+ * "Numerical procedure") turns c0 into the starting tau0 = h0 - c0.  The
+ * warm start changes only the starting point: the fixed point and its
+ * tolerance are those of the plain solve, and rism3d_solve repeats a solve
+ * from tau0 = 0 when the iteration from a caller's tau0 ends non-finite.
+ *
+ * Network: `levels` levels with base * 2^l channels, 3x3x3 convolutions
+ * (zero padding), leaky activations of slope `slope`, 2x2x2 average pooling,
+ * nearest upsampling, skip concatenation (upsampled channels first):
+ *   encoder l: a_l = act(conv(in_l)), e_l = act(conv(a_l)), in_0 = input,
+ *              in_{l+1} = pool(e_l);
+ *   decoder l = levels-2 .. 0: da_l = act(conv([up(d_{l+1}), e_l])),
+ *              d_l = act(conv(da_l)), d_{levels-1} = e_{levels-1};
+ *   output = conv(d_0).
+ * Parameters: one FP32 vector, per convolution in the order enc0a, enc0b,
+ * ..., dec{levels-2}a, dec{levels-2}b, ..., dec0a, dec0b, out: W[C_out][27][C_in]
+ * (tap (dz * 3 + dy) * 3 + dx for offsets (dz-1, dy-1, dx-1)) then b[C_out].
+ * The kernels run in BF16 on the matrix cores with FP32 accumulation; the
+ * parameters, gradients and Adam moments stay FP32.  Grid axes must be
+ * multiples of 2^(levels-1); base a multiple of 16 with base * 2^(levels-1)
+ * <= 128.  Fields are FP32 site-major [channel][nz][ny][nx] (device).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int levels;        /* 4 */
+  int base;          /* 16 */
+  int in_channels;   /* solvent sites */
+  int out_channels;  /* solvent sites */
+  float slope;       /* 0.1 */
+} rism3d_unet_config;
+
+/* Number of FP32 parameters (0 for an invalid configuration). */
+size_t rism3d_unet_param_count(const rism3d_unet_config* cfg);
+/* Device workspace bytes for inference (training = 0) or for
+ * rism3d_unet_gradient (training != 0) on an nx x ny x nz grid; 0 if invalid. */
+size_t rism3d_unet_workspace_bytes(const rism3d_unet_config* cfg, int nx, int ny, int nz,
+                                   int training);
+/* d_output[out_channels][N] = network(d_params, d_input[in_channels][N]). */
+rism3d_status rism3d_unet_forward(const rism3d_unet_config* cfg, int nx, int ny, int nz,
+                                  const float* d_params, const float* d_input, float* d_output,
+                                  void* d_ws, size_t ws_bytes, hipStream_t stream);
+/* Mean squared error of the network output against d_target[out_channels][N]
+ * (mean over channels and voxels) and its gradient: d_grad (device,
+ * param_count floats) is overwritten; d_loss (device double, may be NULL)
+ * receives the loss. */
+rism3d_status rism3d_unet_gradient(const rism3d_unet_config* cfg, int nx, int ny, int nz,
+                                   const float* d_params, const float* d_input,
+                                   const float* d_target, float* d_grad, double* d_loss,
+                                   void* d_ws, size_t ws_bytes, hipStream_t stream);
+/* One Adam step (Kingma & Ba, bias-corrected, step >= 1) on n parameters. */
+rism3d_status rism3d_unet_adam(size_t n, float* d_params, float* d_m, float* d_v,
+                               const float* d_grad, int step, float lr, float beta1, float beta2,
+                               float eps, hipStream_t stream);
+/* Network input of a prepared workspace: symlog(beta u_g) = sign log(1 + |beta u_g|)
+ * of the capped potential, d_x[n_sites][N]. */
+rism3d_status rism3d_net_input(const rism3d_problem* problem, const rism3d_opts* opts,
+                               const void* d_ws, size_t ws_bytes, float* d_x, hipStream_t stream);
+/* Training target of a solved workspace: c_sr = g - 1 - tau of the returned
+ * iterate (Eq 31 in tau-form), d_c[n_sites][N]. */
+rism3d_status rism3d_csr(const rism3d_problem* problem, const rism3d_opts* opts,
+                         const void* d_ws, size_t ws_bytes, float* d_c, hipStream_t stream);
+/* tau0 = h0 - s c0 with h0 from c_scale * d_c0 by one Ornstein-Zernike
+ * half-step (FP64 transforms and contraction); needs a prepared workspace
+ * (rism3d_potential) and uses its spectrum buffer. */
+rism3d_status rism3d_oz_half_step(const rism3d_problem* problem, const rism3d_opts* opts,
+                                  const float* d_c0, float c_scale, void* d_ws, size_t ws_bytes,
+                                  float* d_tau0, hipStream_t stream);
+/* The whole warm start on a prepared workspace: network input, inference
+ * (network workspace d_net_ws of rism3d_unet_workspace_bytes(.., 0) bytes),
+ * c0 = c_scale * output, half-step; writes d_tau0[n_sites][N] for rism3d_solve. */
+rism3d_status rism3d_warmstart(const rism3d_problem* problem, const rism3d_opts* opts,
+                               const rism3d_unet_config* cfg, const float* d_params, float c_scale,
+                               void* d_ws, size_t ws_bytes, void* d_net_ws, size_t net_ws_bytes,
+                               float* d_tau0, hipStream_t stream);
+
 /* Kernel timing, for profiling (thread-local switch).  While enabled, calls on
  * this thread record a pair of HIP events on the call's stream around every
  * kernel launch and add the elapsed time to a per-family total when the call

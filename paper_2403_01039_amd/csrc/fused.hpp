@@ -187,7 +187,7 @@ __global__ __launch_bounds__(kFftThreads) void k_zcz(
   constexpr int B = zcz_cols<C, NZ, NV>();
   constexpr int LINES = 2 * P * B;     // line l = (side * P + p) * B + b
   done = member_ptr(done, bstride);
-  if (*done) return;
+  if (done && *done) return;
   spec = member_ptr(spec, bstride);
   tw2_g = member_ptr(tw2_g, bstride);
   F = member_ptr(F, bstride);

@@ -292,7 +292,7 @@ __global__ __launch_bounds__(kElemThreads) void k_contract(
     const typename ScalarOf<C>::type* __restrict__ qtab, float inv_dkt, int m_tab,
     const int* __restrict__ done) {
   using S = typename ScalarOf<C>::type;
-  if (*done) return;
+  if (done && *done) return;
   constexpr int NP = (NV + 1) / 2;
   const size_t N = (size_t)nx * ny * nz;
   const size_t half = (N + 1) / 2;

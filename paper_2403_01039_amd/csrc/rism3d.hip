@@ -20,6 +20,7 @@
 #include "iterate.hpp"
 #include "fused.hpp"
 #include "setup.hpp"
+#include "unet.hpp"
 
 using namespace rism;
 
@@ -59,7 +60,7 @@ enum Family {
   F_UPDATE32, F_UPDATE64, F_FFTX32, F_FFTY32, F_FFTZ32, F_FFTX64, F_FFTY64, F_FFTZ64,
   F_CONTRACT32, F_CONTRACT64, F_RESIDUAL32, F_RESIDUAL64, F_CONTROL, F_UPDFFT32, F_UPDFFT64,
   F_FFTRES32, F_FFTRES64, F_ZCZ32, F_ZCZ64, F_POTENTIAL, F_FTILDE, F_SETUP, F_OUTPUT, F_SFE,
-  F_COUNT
+  F_NET_FWD, F_NET_GRAD, F_HALFSTEP, F_COUNT
 };
 const char* const kFamilyNames[F_COUNT] = {
     "update_closure_f32", "update_closure_f64", "fft_x_f32", "fft_y_f32", "fft_z_f32",
@@ -67,7 +68,7 @@ const char* const kFamilyNames[F_COUNT] = {
     "residual_gram_f64", "mdiis_control", "update_fftx_f32", "update_fftx_f64",
     "fftx_residual_f32", "fftx_residual_f64", "zfft_contract_f32", "zfft_contract_f64",
     "potential", "long_range_spectrum",
-    "setup_tables", "output", "free_energy"};
+    "setup_tables", "output", "free_energy", "unet_forward", "unet_gradient", "oz_half_step"};
 
 struct Timer {
   bool on = false;
@@ -748,10 +749,10 @@ std::string graph_key(const Layout& L, const void* ws, const rism3d_opts* op, fl
 }
 
 void drop_graph(GraphEntry* e) {
-  if (e->exec) hipGraphExecDestroy(e->exec);
+  if (e->exec) (void)hipGraphExecDestroy(e->exec);
   for (const Timer::Pending& p : e->timing) {
-    hipEventDestroy(p.a);
-    hipEventDestroy(p.b);
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
   }
   delete e;
 }
@@ -797,12 +798,12 @@ GraphEntry* graph_for(const Layout& L, void* ws, const rism3d_opts* op, float in
   g_timer.pending.swap(before);
   if (ec != hipSuccess || !graph || g_capture_bad ||
       hipGraphInstantiate(&e->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
-    if (graph) hipGraphDestroy(graph);
+    if (graph) (void)hipGraphDestroy(graph);
     (void)hipGetLastError();
     drop_graph(e);
     return nullptr;
   }
-  hipGraphDestroy(graph);
+  (void)hipGraphDestroy(graph);
   if (g_graphs.size() >= kMaxGraphs) {
     drop_graph(g_graphs.front());
     g_graphs.erase(g_graphs.begin());
@@ -970,6 +971,58 @@ rism3d_status batch_plan(int n, const rism3d_problem* prs, const rism3d_opts* op
   return RISM3D_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Warm start: network input and training target from a solver workspace, and
+// the Ornstein-Zernike half-step that turns a predicted c_sr into tau0.
+// ---------------------------------------------------------------------------
+#include "unet_host.hpp"
+
+// x[g][n] = symlog(beta u_g(n)) with the capped beta u = w + f, f_g = beta C q_g phi.
+__global__ void k_net_input(const float* __restrict__ w, const float* __restrict__ phi, size_t N,
+                            int nv, SiteConsts sc, float* __restrict__ x) {
+  const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (size_t)nv * N) return;
+  const int g = (int)(id / N);
+  const double bu = (double)w[id] + sc.coul64[g] * (double)phi[id - (size_t)g * N];
+  x[id] = (float)(bu < 0.0 ? -log1p(-bu) : log1p(bu));
+}
+
+// c_sr = g - 1 - tau of the accepted iterate (FP64 closure).
+__global__ void k_csr_out(const IterState* __restrict__ st, const float* __restrict__ tau_hist,
+                          const float* __restrict__ w, size_t N, int nv, int kind, int order,
+                          float* __restrict__ c) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)nv * N) return;
+  const int slot = st->final_slot;
+  if (slot < 0) return;
+  const double tau = (double)tau_hist[(size_t)slot * nv * N + idx];
+  c[idx] = (float)(closure_g(-(double)w[idx] + tau, kind, order) - 1.0 - tau);
+}
+
+// Packed FP64 pairs of the scaled prediction: spec[p][n] = s (c_{2p} + i c_{2p+1}).
+__global__ void k_pack_c64(const float* __restrict__ c, size_t N, int nv, double scale,
+                           double2* __restrict__ spec) {
+  const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int np = (nv + 1) / 2;
+  if (id >= (size_t)np * N) return;
+  const int p = (int)(id / N);
+  const size_t n = id - (size_t)p * N;
+  const double re = scale * (double)c[(size_t)(2 * p) * N + n];
+  const double im = 2 * p + 1 < nv ? scale * (double)c[(size_t)(2 * p + 1) * N + n] : 0.0;
+  spec[id] = make_double2(re, im);
+}
+
+// tau0 = h - c0 with h unpacked from the inverse-transformed pairs.
+__global__ void k_tau_from_h(const double2* __restrict__ spec, const float* __restrict__ c,
+                             size_t N, int nv, double scale, float* __restrict__ tau0) {
+  const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (size_t)nv * N) return;
+  const int g = (int)(id / N);
+  const size_t n = id - (size_t)g * N;
+  const double2 h = spec[(size_t)(g / 2) * N + n];
+  tau0[id] = (float)(((g & 1) ? h.y : h.x) - scale * (double)c[id]);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1011,13 +1064,17 @@ rism3d_status rism3d_solve(const rism3d_problem* pr, const rism3d_opts* op, cons
   HIP_TRY(hipStreamSynchronize(s));
   if (host.prepared != kPreparedMagic)
     return fail(RISM3D_E_WORKSPACE, "workspace not prepared: call rism3d_potential first");
+  const float inv_dkt = (float)(1.0 / pr->dk);
+  // A caller's starting tau is only a starting point: if the iteration from
+  // it ends on a non-finite residual, the solve is repeated from tau0 = 0.
+  for (int attempt = 0; attempt < 2; ++attempt) {
+  const float* t0 = attempt == 0 ? tau0 : nullptr;
   hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1), 0, s, dst, (float)op->mdiis_eta,
-                     tau0 ? 1 : 0);
+                     t0 ? 1 : 0);
   hipLaunchKernelGGL(k_init_tau, dim3(blocks_for((size_t)L.nv * L.N, kElemThreads)),
-                     dim3(kElemThreads), 0, s, tau0, at<float>(ws, L.off_tau),
+                     dim3(kElemThreads), 0, s, t0, at<float>(ws, L.off_tau),
                      (size_t)L.nv * L.N);
   LAUNCH_CHECK();
-  const float inv_dkt = (float)(1.0 / pr->dk);
   const int every = op->anchor_every > 0 ? op->anchor_every : kDefaultAnchorEvery;
   // One anchor period (an FP64 anchor evaluation + every-1 FP32 increments) is
   // captured once into a HIP graph per workspace and options, then replayed;
@@ -1049,6 +1106,8 @@ rism3d_status rism3d_solve(const rism3d_problem* pr, const rism3d_opts* op, cons
     }
     iter_before = host.iter;
     if (host.done || launched >= op->max_iter) break;
+  }
+  if (!(t0 && host.status == RISM3D_E_NONFINITE)) break;
   }
   if (g_out) {
     hipLaunchKernelGGL(k_output, dim3(blocks_for((size_t)L.nv * L.N, kElemThreads)),
@@ -1392,6 +1451,156 @@ int rism3d_timing_read(int family, const char** name, long* launches, double* to
     if (total_ms) *total_ms = g_timer.ms[family];
   }
   return F_COUNT;
+}
+
+// ---------------------------------------------------------------------------
+// Warm-start network
+// ---------------------------------------------------------------------------
+size_t rism3d_unet_param_count(const rism3d_unet_config* cfg) {
+  NetPlan P;
+  if (net_plan(cfg, 1 << (cfg ? cfg->levels - 1 : 0), 1 << (cfg ? cfg->levels - 1 : 0),
+               1 << (cfg ? cfg->levels - 1 : 0), &P) != RISM3D_OK)
+    return 0;
+  return P.n_params;
+}
+
+size_t rism3d_unet_workspace_bytes(const rism3d_unet_config* cfg, int nx, int ny, int nz,
+                                   int training) {
+  NetPlan P;
+  if (net_plan(cfg, nx, ny, nz, &P) != RISM3D_OK) return 0;
+  return training ? P.total_train : P.total_infer;
+}
+
+rism3d_status rism3d_unet_forward(const rism3d_unet_config* cfg, int nx, int ny, int nz,
+                                  const float* d_params, const float* d_input, float* d_output,
+                                  void* d_ws, size_t ws_bytes, hipStream_t s) {
+  NetPlan P;
+  rism3d_status st = net_plan(cfg, nx, ny, nz, &P);
+  if (st != RISM3D_OK) return st;
+  if (!d_params || !d_input || !d_output) return fail(RISM3D_E_ARG, "null network buffer");
+  if (!d_ws || ((uintptr_t)d_ws & 255)) return fail(RISM3D_E_WORKSPACE, "workspace must be 256-byte aligned");
+  if (ws_bytes < P.total_infer)
+    return fail(RISM3D_E_WORKSPACE, "network workspace holds %zu bytes, %zu needed", ws_bytes,
+                P.total_infer);
+  {
+    TIMED(F_NET_FWD, s);
+    net_pack(P, d_params, d_ws, false, s);
+    net_forward(P, d_params, d_input, d_output, d_ws, s);
+  }
+  LAUNCH_CHECK();
+  return RISM3D_OK;
+}
+
+rism3d_status rism3d_unet_gradient(const rism3d_unet_config* cfg, int nx, int ny, int nz,
+                                   const float* d_params, const float* d_input,
+                                   const float* d_target, float* d_grad, double* d_loss,
+                                   void* d_ws, size_t ws_bytes, hipStream_t s) {
+  NetPlan P;
+  rism3d_status st = net_plan(cfg, nx, ny, nz, &P);
+  if (st != RISM3D_OK) return st;
+  if (!d_params || !d_input || !d_target || !d_grad) return fail(RISM3D_E_ARG, "null network buffer");
+  if (!d_ws || ((uintptr_t)d_ws & 255)) return fail(RISM3D_E_WORKSPACE, "workspace must be 256-byte aligned");
+  if (ws_bytes < P.total_train)
+    return fail(RISM3D_E_WORKSPACE, "network workspace holds %zu bytes, %zu needed", ws_bytes,
+                P.total_train);
+  {
+    TIMED(F_NET_GRAD, s);
+    net_pack(P, d_params, d_ws, true, s);
+    net_gradient(P, d_params, d_input, d_target, d_grad, d_ws, s);
+  }
+  if (d_loss)
+    HIP_TRY(hipMemcpyAsync(d_loss, wsp<double>(d_ws, P.loss), sizeof(double),
+                           hipMemcpyDeviceToDevice, s));
+  LAUNCH_CHECK();
+  return RISM3D_OK;
+}
+
+rism3d_status rism3d_unet_adam(size_t n, float* d_params, float* d_m, float* d_v,
+                               const float* d_grad, int step, float lr, float beta1, float beta2,
+                               float eps, hipStream_t s) {
+  if (!d_params || !d_m || !d_v || !d_grad || n == 0) return fail(RISM3D_E_ARG, "null Adam buffer");
+  if (step < 1 || !(lr > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) ||
+      !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+    return fail(RISM3D_E_ARG, "invalid Adam hyper-parameters");
+  const float c1 = (float)(1.0 - pow((double)beta1, step));
+  const float c2 = (float)(1.0 - pow((double)beta2, step));
+  hipLaunchKernelGGL(net::k_adam, dim3(net_blocks(n, 256)), dim3(256), 0, s, d_params, d_m, d_v,
+                     d_grad, n, lr, beta1, beta2, eps, c1, c2);
+  LAUNCH_CHECK();
+  return RISM3D_OK;
+}
+
+rism3d_status rism3d_net_input(const rism3d_problem* pr, const rism3d_opts* op, const void* ws_c,
+                               size_t ws_bytes, float* d_x, hipStream_t s) {
+  Layout L;
+  rism3d_status st = make_layout(pr, op, &L);
+  if (st != RISM3D_OK) return st;
+  if ((st = check_ws(L, ws_c, ws_bytes)) != RISM3D_OK) return st;
+  if (!d_x) return fail(RISM3D_E_ARG, "null output");
+  const SiteConsts sc = site_consts(pr, L.beta);
+  hipLaunchKernelGGL(k_net_input, dim3(blocks_for((size_t)L.nv * L.N, kElemThreads)),
+                     dim3(kElemThreads), 0, s, at<float>(ws_c, L.off_w), at<float>(ws_c, L.off_phi),
+                     L.N, L.nv, sc, d_x);
+  LAUNCH_CHECK();
+  return RISM3D_OK;
+}
+
+rism3d_status rism3d_csr(const rism3d_problem* pr, const rism3d_opts* op, const void* ws_c,
+                         size_t ws_bytes, float* d_c, hipStream_t s) {
+  Layout L;
+  rism3d_status st = make_layout(pr, op, &L);
+  if (st != RISM3D_OK) return st;
+  if ((st = check_ws(L, ws_c, ws_bytes)) != RISM3D_OK) return st;
+  if (!d_c) return fail(RISM3D_E_ARG, "null output");
+  hipLaunchKernelGGL(k_csr_out, dim3(blocks_for((size_t)L.nv * L.N, kElemThreads)),
+                     dim3(kElemThreads), 0, s, at<IterState>(ws_c, L.off_state),
+                     at<float>(ws_c, L.off_tau), at<float>(ws_c, L.off_w), L.N, L.nv,
+                     (int)op->closure, order_of(op), d_c);
+  LAUNCH_CHECK();
+  return RISM3D_OK;
+}
+
+rism3d_status rism3d_oz_half_step(const rism3d_problem* pr, const rism3d_opts* op,
+                                  const float* d_c0, float c_scale, void* ws, size_t ws_bytes,
+                                  float* d_tau0, hipStream_t s) {
+  Layout L;
+  rism3d_status st = make_layout(pr, op, &L);
+  if (st != RISM3D_OK) return st;
+  if ((st = check_ws(L, ws, ws_bytes)) != RISM3D_OK) return st;
+  if (!d_c0 || !d_tau0) return fail(RISM3D_E_ARG, "null buffer");
+  TIMED(F_HALFSTEP, s);
+  hipLaunchKernelGGL(k_pack_c64, dim3(blocks_for((size_t)L.npair * L.N, kElemThreads)),
+                     dim3(kElemThreads), 0, s, d_c0, L.N, L.nv, (double)c_scale,
+                     at<double2>(ws, L.off_spec));
+  launch_fft3<double2>(L, ws, 1, nullptr, s);
+  launch_contract(L, ws, true, (float)(1.0 / pr->dk), nullptr, s);
+  launch_fft3<double2>(L, ws, 0, nullptr, s);
+  hipLaunchKernelGGL(k_tau_from_h, dim3(blocks_for((size_t)L.nv * L.N, kElemThreads)),
+                     dim3(kElemThreads), 0, s, at<double2>(ws, L.off_spec), d_c0, L.N, L.nv,
+                     (double)c_scale, d_tau0);
+  LAUNCH_CHECK();
+  return RISM3D_OK;
+}
+
+rism3d_status rism3d_warmstart(const rism3d_problem* pr, const rism3d_opts* op,
+                               const rism3d_unet_config* cfg, const float* d_params, float c_scale,
+                               void* ws, size_t ws_bytes, void* d_net_ws, size_t net_ws_bytes,
+                               float* d_tau0, hipStream_t s) {
+  Layout L;
+  rism3d_status st = make_layout(pr, op, &L);
+  if (st != RISM3D_OK) return st;
+  if ((st = check_ws(L, ws, ws_bytes)) != RISM3D_OK) return st;
+  if (!cfg || cfg->in_channels != L.nv || cfg->out_channels != L.nv)
+    return fail(RISM3D_E_ARG, "network channels must equal the number of solvent sites");
+  // the network input and its prediction use two per-site grids of the
+  // workspace that the next solve overwrites (reference tau and residual)
+  float* x = at<float>(ws, L.off_tref);
+  float* c0 = at<float>(ws, L.off_rref);
+  if ((st = rism3d_net_input(pr, op, ws, ws_bytes, x, s)) != RISM3D_OK) return st;
+  if ((st = rism3d_unet_forward(cfg, L.nx, L.ny, L.nz, d_params, x, c0, d_net_ws, net_ws_bytes,
+                                s)) != RISM3D_OK)
+    return st;
+  return rism3d_oz_half_step(pr, op, c0, c_scale, ws, ws_bytes, d_tau0, s);
 }
 
 const char* rism3d_last_error(void) { return g_error.c_str(); }

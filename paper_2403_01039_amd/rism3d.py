@@ -63,6 +63,11 @@ class ThermoOut(ctypes.Structure):
     _fields_ = [("sfe", ctypes.c_double), ("sfe_site", ctypes.c_double * MAX_SITES)]
 
 
+class UnetConfig(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int), ("base", ctypes.c_int), ("in_channels", ctypes.c_int),
+                ("out_channels", ctypes.c_int), ("slope", ctypes.c_float)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
@@ -89,6 +94,21 @@ def _load():
                                               ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
         "rism3d_timing_select": (ctypes.c_int, [ctypes.c_char_p]),
+        "rism3d_unet_param_count": (sz, [P(UnetConfig)]),
+        "rism3d_unet_workspace_bytes": (sz, [P(UnetConfig), ctypes.c_int, ctypes.c_int,
+                                             ctypes.c_int, ctypes.c_int]),
+        "rism3d_unet_forward": (ctypes.c_int, [P(UnetConfig), ctypes.c_int, ctypes.c_int,
+                                               ctypes.c_int, vp, vp, vp, vp, sz, st]),
+        "rism3d_unet_gradient": (ctypes.c_int, [P(UnetConfig), ctypes.c_int, ctypes.c_int,
+                                                ctypes.c_int, vp, vp, vp, vp, vp, vp, sz, st]),
+        "rism3d_unet_adam": (ctypes.c_int, [sz, vp, vp, vp, vp, ctypes.c_int, ctypes.c_float,
+                                            ctypes.c_float, ctypes.c_float, ctypes.c_float, st]),
+        "rism3d_net_input": (ctypes.c_int, [P(Problem), P(Opts), vp, sz, vp, st]),
+        "rism3d_csr": (ctypes.c_int, [P(Problem), P(Opts), vp, sz, vp, st]),
+        "rism3d_oz_half_step": (ctypes.c_int, [P(Problem), P(Opts), vp, ctypes.c_float, vp, sz,
+                                               vp, st]),
+        "rism3d_warmstart": (ctypes.c_int, [P(Problem), P(Opts), P(UnetConfig), vp,
+                                            ctypes.c_float, vp, sz, vp, sz, vp, st]),
         "rism3d_use_graphs": (None, [ctypes.c_int]),
         "rism3d_release_graphs": (None, []),
         "rism3d_last_error": (ctypes.c_char_p, []),
@@ -107,7 +127,10 @@ EXPORTED = ("rism3d_workspace_bytes", "rism3d_potential", "rism3d_solve", "rism3
             "rism3d_transform_workspace_bytes", "rism3d_transform", "rism3d_timing_enable",
             "rism3d_timing_reset", "rism3d_timing_read", "rism3d_use_graphs",
             "rism3d_release_graphs", "rism3d_timing_select",
-            "rism3d_batch_workspace_bytes", "rism3d_solve_batch", "rism3d_last_error", "rism3d_constants")
+            "rism3d_batch_workspace_bytes", "rism3d_solve_batch", "rism3d_unet_param_count",
+            "rism3d_unet_workspace_bytes", "rism3d_unet_forward", "rism3d_unet_gradient",
+            "rism3d_unet_adam", "rism3d_net_input", "rism3d_csr", "rism3d_oz_half_step",
+            "rism3d_warmstart", "rism3d_last_error", "rism3d_constants")
 
 
 def last_error() -> str:
@@ -326,6 +349,92 @@ def rism3d_solve_batch(dps, opts: Opts, ws: torch.Tensor, tau0=None, g_out=None,
     if thermo:
         sfe = [(t.sfe, np.array(t.sfe_site[:dp.shape[0]])) for t, dp in zip(th, dps)]
     return out_info, sfe
+
+
+# --- warm-start network ------------------------------------------------------
+
+
+def unet_config(in_channels: int, out_channels: int, levels: int = 4, base: int = 16,
+                slope: float = 0.1) -> UnetConfig:
+    c = UnetConfig()
+    c.levels, c.base, c.in_channels, c.out_channels, c.slope = (
+        levels, base, in_channels, out_channels, slope)
+    return c
+
+
+def unet_layers(cfg: UnetConfig):
+    """(name, C_in, C_out) of every convolution, in parameter order."""
+    ch = lambda l: cfg.base << l
+    out = []
+    for l in range(cfg.levels):
+        out += [(f"enc{l}a", cfg.in_channels if l == 0 else ch(l - 1), ch(l)),
+                (f"enc{l}b", ch(l), ch(l))]
+    for l in range(cfg.levels - 2, -1, -1):
+        out += [(f"dec{l}a", ch(l + 1) + ch(l), ch(l)), (f"dec{l}b", ch(l), ch(l))]
+    return out + [("out", ch(0), cfg.out_channels)]
+
+
+def unet_param_count(cfg: UnetConfig) -> int:
+    n = LIB.rism3d_unet_param_count(ctypes.byref(cfg))
+    if n == 0:
+        raise RismError(1, last_error())
+    return n
+
+
+def unet_workspace_bytes(cfg: UnetConfig, shape, training: bool) -> int:
+    nz, ny, nx = shape
+    n = LIB.rism3d_unet_workspace_bytes(ctypes.byref(cfg), nx, ny, nz, int(bool(training)))
+    if n == 0:
+        raise RismError(1, last_error())
+    return n
+
+
+def unet_forward(cfg, params: torch.Tensor, x: torch.Tensor, out: torch.Tensor, ws, stream=None):
+    nz, ny, nx = x.shape[1:]
+    _check(LIB.rism3d_unet_forward(ctypes.byref(cfg), nx, ny, nz, _ptr(params), _ptr(x),
+                                   _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
+    return out
+
+
+def unet_gradient(cfg, params, x, target, grad, ws, loss: Optional[torch.Tensor] = None,
+                  stream=None):
+    nz, ny, nx = x.shape[1:]
+    _check(LIB.rism3d_unet_gradient(ctypes.byref(cfg), nx, ny, nz, _ptr(params), _ptr(x),
+                                    _ptr(target), _ptr(grad), _ptr(loss), _ptr(ws), ws.numel(),
+                                    _stream(stream)))
+    return grad
+
+
+def unet_adam(params, m, v, grad, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8,
+              stream=None):
+    _check(LIB.rism3d_unet_adam(params.numel(), _ptr(params), _ptr(m), _ptr(v), _ptr(grad),
+                                int(step), lr, beta1, beta2, eps, _stream(stream)))
+
+
+def rism3d_net_input(dp, opts, ws, x, stream=None):
+    _check(LIB.rism3d_net_input(ctypes.byref(dp.struct), ctypes.byref(opts), _ptr(ws),
+                                ws.numel(), _ptr(x), _stream(stream)))
+    return x
+
+
+def rism3d_csr(dp, opts, ws, c, stream=None):
+    _check(LIB.rism3d_csr(ctypes.byref(dp.struct), ctypes.byref(opts), _ptr(ws), ws.numel(),
+                          _ptr(c), _stream(stream)))
+    return c
+
+
+def rism3d_oz_half_step(dp, opts, ws, c0, tau0, c_scale: float = 1.0, stream=None):
+    _check(LIB.rism3d_oz_half_step(ctypes.byref(dp.struct), ctypes.byref(opts), _ptr(c0),
+                                   float(c_scale), _ptr(ws), ws.numel(), _ptr(tau0),
+                                   _stream(stream)))
+    return tau0
+
+
+def rism3d_warmstart(dp, opts, cfg, params, ws, net_ws, tau0, c_scale: float = 1.0, stream=None):
+    _check(LIB.rism3d_warmstart(ctypes.byref(dp.struct), ctypes.byref(opts), ctypes.byref(cfg),
+                                _ptr(params), float(c_scale), _ptr(ws), ws.numel(), _ptr(net_ws),
+                                net_ws.numel(), _ptr(tau0), _stream(stream)))
+    return tau0
 
 
 # --- convenience -------------------------------------------------------------
