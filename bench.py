@@ -185,12 +185,60 @@ def summarize_counters(fetch_csv: str, write_csv: str, copy_bytes: int, out_path
     print(json.dumps(out, indent=1))
 
 
+def warm_start_comparison(R, inputs, n_seeds: int):
+    """Plain vs warm-started solves on held-out seeds of the warm-start
+    workload (200-atom solutes in water, 128^3 at 0.5 A, KH, MDIIS 5, rms
+    1e-6).  One solve = potential + [network inference + OZ half-step] +
+    iterations + SFE; inputs resident on the device."""
+    import numpy as np
+    import torch
+    if not os.path.exists(R.WEIGHTS_PATH):
+        return {"error": "no trained warm-start weights"}
+    net = R.WarmStart()
+    chi, dk = inputs.solvent_table("water")
+    seeds = list(range(20000, 20000 + n_seeds))
+    probs = [inputs.warmstart_problem(s) for s in seeds]
+    dps = [R.DeviceProblem(p, chi, dk) for p in probs]
+    opts = R.make_opts(probs[0].options)
+    ws = R.alloc_workspace(max(R.rism3d_workspace_bytes(dp, opts) for dp in dps))
+    tau0 = torch.empty(dps[0].shape, dtype=torch.float32, device="cuda")
+
+    def plain(dp):
+        R.rism3d_potential(dp, opts, ws)
+        info = R.rism3d_solve(dp, opts, ws)
+        R.rism3d_thermo(dp, opts, ws)
+        return info
+
+    def warm(dp):
+        R.rism3d_potential(dp, opts, ws)
+        net.tau0(dp, opts, ws, tau0)
+        info = R.rism3d_solve(dp, opts, ws, tau0)
+        R.rism3d_thermo(dp, opts, ws)
+        return info
+
+    plain(dps[0]); warm(dps[0])          # warm-up (graph capture, workspaces)
+    out = {}
+    for name, fn in (("plain", plain), ("warm", warm)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its = [fn(dp).iterations for dp in dps]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[name] = {"solves_per_s": len(dps) / el, "iterations_mean": float(np.mean(its))}
+    out["speedup"] = out["warm"]["solves_per_s"] / out["plain"]["solves_per_s"]
+    out["workload"] = (f"warm_start: held-out seeds {seeds[0]}..{seeds[-1]}, 200-atom solutes in "
+                       f"water (3 sites), 128^3 at 0.5 A, KH, MDIIS 5, rms 1e-6")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--warm-seeds", type=int, default=8,
+                    help="held-out seeds of the plain vs warm-start comparison (0: skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (the reference "
                          "dispatch for scaling HBM counters)")
@@ -317,6 +365,8 @@ def main():
                      "bytes_per_launch": timed["bytes_per_launch"]},
         "kernels_first_warmup_step": kernels,
     }
+    if args.warm_seeds > 0:
+        out["warm_start"] = warm_start_comparison(R, inputs, args.warm_seeds)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, chi, dk, int(round(it_mean)))
     print(json.dumps(out), flush=True)

@@ -272,10 +272,15 @@ rism3d_status rism3d_unet_gradient(const rism3d_unet_config* cfg, int nx, int ny
                                    const float* d_params, const float* d_input,
                                    const float* d_target, float* d_grad, double* d_loss,
                                    void* d_ws, size_t ws_bytes, hipStream_t stream);
-/* One Adam step (Kingma & Ba, bias-corrected, step >= 1) on n parameters. */
+/* One Adam step (Kingma & Ba, bias-corrected, step >= 1) on n parameters.
+ * clip_norm > 0 first scales the gradient by min(1, clip_norm / |g|) (global
+ * L2 norm, FP64 fixed-order sum); it then needs d_scratch, a device buffer of
+ * rism3d_unet_adam_scratch_bytes() bytes, whose last two doubles receive |g|
+ * and the applied scale.  clip_norm = 0: no clipping, d_scratch may be NULL. */
+size_t rism3d_unet_adam_scratch_bytes(void);
 rism3d_status rism3d_unet_adam(size_t n, float* d_params, float* d_m, float* d_v,
                                const float* d_grad, int step, float lr, float beta1, float beta2,
-                               float eps, hipStream_t stream);
+                               float eps, float clip_norm, double* d_scratch, hipStream_t stream);
 /* Network input of a prepared workspace: symlog(beta u_g) = sign log(1 + |beta u_g|)
  * of the capped potential, d_x[n_sites][N]. */
 rism3d_status rism3d_net_input(const rism3d_problem* problem, const rism3d_opts* opts,

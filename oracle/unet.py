@@ -24,7 +24,8 @@ gradients and its optimiser, written as directly as numpy allows:
   parameters in that order (enc0a, enc0b, ..., dec_{L-2}a, dec_{L-2}b, ...,
   dec0a, dec0b, out), each W[C_out, 27, C_in] then b[C_out];
 * loss = mean over voxels and output channels of (output - target)^2;
-* Adam (Kingma & Ba 2015) with bias correction.
+* Adam (Kingma & Ba 2015) with bias correction, optionally after scaling the
+  gradient to a global L2 norm of at most `clip`.
 """
 from __future__ import annotations
 
@@ -243,8 +244,14 @@ class Adam:
     beta2: float = 0.999
     eps: float = 1e-8
 
+    clip: float = 0.0        # > 0: scale the gradient to global L2 norm <= clip first
+
     def step(self, theta, grad, m, v, t: int):
         """One update at step t >= 1; returns (theta, m, v)."""
+        if self.clip > 0.0:
+            norm = float(np.sqrt(np.sum(grad * grad)))
+            if norm > self.clip:
+                grad = grad * (self.clip / norm)
         m = self.beta1 * m + (1.0 - self.beta1) * grad
         v = self.beta2 * v + (1.0 - self.beta2) * grad * grad
         mhat = m / (1.0 - self.beta1 ** t)

@@ -1515,17 +1515,29 @@ rism3d_status rism3d_unet_gradient(const rism3d_unet_config* cfg, int nx, int ny
   return RISM3D_OK;
 }
 
+size_t rism3d_unet_adam_scratch_bytes(void) {
+  return (size_t)(net::kNormBlocks + 2) * sizeof(double);
+}
+
 rism3d_status rism3d_unet_adam(size_t n, float* d_params, float* d_m, float* d_v,
                                const float* d_grad, int step, float lr, float beta1, float beta2,
-                               float eps, hipStream_t s) {
+                               float eps, float clip_norm, double* d_scratch, hipStream_t s) {
   if (!d_params || !d_m || !d_v || !d_grad || n == 0) return fail(RISM3D_E_ARG, "null Adam buffer");
   if (step < 1 || !(lr > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) ||
-      !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+      !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f) || !(clip_norm >= 0.0f))
     return fail(RISM3D_E_ARG, "invalid Adam hyper-parameters");
+  if (clip_norm > 0.0f && !d_scratch) return fail(RISM3D_E_ARG, "clipping needs the scratch buffer");
   const float c1 = (float)(1.0 - pow((double)beta1, step));
   const float c2 = (float)(1.0 - pow((double)beta2, step));
+  const double* scale = nullptr;
+  if (clip_norm > 0.0f) {
+    hipLaunchKernelGGL(net::k_sumsq, dim3(net::kNormBlocks), dim3(256), 0, s, d_grad, n, d_scratch);
+    hipLaunchKernelGGL(net::k_clip_scale, dim3(1), dim3(64), 0, s, d_scratch, net::kNormBlocks,
+                       (double)clip_norm);
+    scale = d_scratch + net::kNormBlocks + 1;
+  }
   hipLaunchKernelGGL(net::k_adam, dim3(net_blocks(n, 256)), dim3(256), 0, s, d_params, d_m, d_v,
-                     d_grad, n, lr, beta1, beta2, eps, c1, c2);
+                     d_grad, n, lr, beta1, beta2, eps, c1, c2, scale);
   LAUNCH_CHECK();
   return RISM3D_OK;
 }

@@ -440,13 +440,40 @@ __global__ void k_pack_weights(const float* __restrict__ W, int cout, int cin, i
   }
 }
 
-// Adam with bias correction, FP32 master parameters.
+// Global gradient norm for clipping: per-block FP64 sums of squares (fixed
+// block count and order), then one block forms scale = min(1, clip / |g|).
+constexpr int kNormBlocks = 256;
+
+__global__ __launch_bounds__(256) void k_sumsq(const float* __restrict__ g, size_t n,
+                                               double* __restrict__ partials) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < n;
+       id += (size_t)gridDim.x * blockDim.x)
+    s += (double)g[id] * (double)g[id];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) partials[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void k_clip_scale(double* __restrict__ partials, int nb, double clip) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < nb; ++i) s += partials[i];
+  const double norm = sqrt(s);
+  partials[nb] = norm;                                   // |g| before clipping
+  partials[nb + 1] = norm > clip ? clip / norm : 1.0;    // scale applied to g
+}
+
+// Adam with bias correction, FP32 master parameters; the gradient is first
+// multiplied by *scale when scale is not null (global-norm clipping).
 __global__ void k_adam(float* __restrict__ theta, float* __restrict__ m, float* __restrict__ v,
                        const float* __restrict__ grad, size_t n, float lr, float b1, float b2,
-                       float eps, float c1, float c2) {
+                       float eps, float c1, float c2, const double* __restrict__ scale) {
   const size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= n) return;
-  const float gr = grad[id];
+  const float gr = scale ? (float)((double)grad[id] * *scale) : grad[id];
   const float mm = b1 * m[id] + (1.0f - b1) * gr;
   const float vv = b2 * v[id] + (1.0f - b2) * gr * gr;
   m[id] = mm;

@@ -101,8 +101,10 @@ def _load():
                                                ctypes.c_int, vp, vp, vp, vp, sz, st]),
         "rism3d_unet_gradient": (ctypes.c_int, [P(UnetConfig), ctypes.c_int, ctypes.c_int,
                                                 ctypes.c_int, vp, vp, vp, vp, vp, vp, sz, st]),
+        "rism3d_unet_adam_scratch_bytes": (sz, []),
         "rism3d_unet_adam": (ctypes.c_int, [sz, vp, vp, vp, vp, ctypes.c_int, ctypes.c_float,
-                                            ctypes.c_float, ctypes.c_float, ctypes.c_float, st]),
+                                            ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                            ctypes.c_float, vp, st]),
         "rism3d_net_input": (ctypes.c_int, [P(Problem), P(Opts), vp, sz, vp, st]),
         "rism3d_csr": (ctypes.c_int, [P(Problem), P(Opts), vp, sz, vp, st]),
         "rism3d_oz_half_step": (ctypes.c_int, [P(Problem), P(Opts), vp, ctypes.c_float, vp, sz,
@@ -129,7 +131,7 @@ EXPORTED = ("rism3d_workspace_bytes", "rism3d_potential", "rism3d_solve", "rism3
             "rism3d_release_graphs", "rism3d_timing_select",
             "rism3d_batch_workspace_bytes", "rism3d_solve_batch", "rism3d_unet_param_count",
             "rism3d_unet_workspace_bytes", "rism3d_unet_forward", "rism3d_unet_gradient",
-            "rism3d_unet_adam", "rism3d_net_input", "rism3d_csr", "rism3d_oz_half_step",
+            "rism3d_unet_adam", "rism3d_unet_adam_scratch_bytes", "rism3d_net_input", "rism3d_csr", "rism3d_oz_half_step",
             "rism3d_warmstart", "rism3d_last_error", "rism3d_constants")
 
 
@@ -405,10 +407,18 @@ def unet_gradient(cfg, params, x, target, grad, ws, loss: Optional[torch.Tensor]
     return grad
 
 
+def unet_adam_scratch(device="cuda") -> torch.Tensor:
+    return torch.zeros(LIB.rism3d_unet_adam_scratch_bytes() // 8, dtype=torch.float64,
+                       device=device)
+
+
 def unet_adam(params, m, v, grad, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8,
-              stream=None):
+              clip_norm: float = 0.0, scratch: Optional[torch.Tensor] = None, stream=None):
+    """One Adam step; clip_norm > 0 clips the global gradient norm (scratch from
+    unet_adam_scratch(); its last two entries receive |g| and the scale)."""
     _check(LIB.rism3d_unet_adam(params.numel(), _ptr(params), _ptr(m), _ptr(v), _ptr(grad),
-                                int(step), lr, beta1, beta2, eps, _stream(stream)))
+                                int(step), lr, beta1, beta2, eps, float(clip_norm), _ptr(scratch),
+                                _stream(stream)))
 
 
 def rism3d_net_input(dp, opts, ws, x, stream=None):
@@ -435,6 +445,37 @@ def rism3d_warmstart(dp, opts, cfg, params, ws, net_ws, tau0, c_scale: float = 1
                                 _ptr(params), float(c_scale), _ptr(ws), ws.numel(), _ptr(net_ws),
                                 net_ws.numel(), _ptr(tau0), _stream(stream)))
     return tau0
+
+
+WEIGHTS_PATH = os.path.join(_HERE, "weights", "warmstart_unet.npz")
+
+
+class WarmStart:
+    """Trained warm-start network: configuration, FP32 parameters on the
+    device, the output scale c_scale and an inference workspace."""
+
+    def __init__(self, path: str = WEIGHTS_PATH, device="cuda"):
+        with np.load(path, allow_pickle=False) as z:
+            self.cfg = unet_config(int(z["in_channels"]), int(z["out_channels"]),
+                                   levels=int(z["levels"]), base=int(z["base"]),
+                                   slope=float(z["slope"]))
+            self.params = torch.tensor(np.asarray(z["params"], dtype=np.float32), device=device)
+            self.c_scale = float(z["c_scale"])
+        if self.params.numel() != unet_param_count(self.cfg):
+            raise ValueError(f"{path}: parameter count does not match the configuration")
+        self.device = device
+        self._ws = {}
+
+    def tau0(self, dp, opts, ws, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """Starting tau of a prepared workspace (after rism3d_potential)."""
+        shape = dp.shape[1:]
+        if shape not in self._ws:
+            self._ws[shape] = alloc_workspace(unet_workspace_bytes(self.cfg, shape, False),
+                                              self.device)
+        if out is None:
+            out = torch.empty(dp.shape, dtype=torch.float32, device=self.device)
+        return rism3d_warmstart(dp, opts, self.cfg, self.params, ws, self._ws[shape], out,
+                                self.c_scale, stream)
 
 
 # --- convenience -------------------------------------------------------------

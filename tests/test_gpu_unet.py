@@ -141,12 +141,16 @@ def test_adam_matches_oracle(R):
     t_g = torch.tensor(theta, device="cuda")
     m_g = torch.zeros(n, device="cuda")
     v_g = torch.zeros(n, device="cuda")
-    opt = U.Adam(lr=1e-3)
+    opt = U.Adam(lr=1e-3, clip=20.0)
     th = theta.astype(np.float64)
-    for step in range(1, 4):
-        g = rng.standard_normal(n).astype(np.float32)
-        R.unet_adam(t_g, m_g, v_g, torch.tensor(g, device="cuda"), step, 1e-3)
+    scratch = R.unet_adam_scratch()
+    for step in range(1, 5):
+        # steps 1 and 3 are clipped (|g| ~ 32 > 20), steps 2 and 4 are not
+        g = (rng.standard_normal(n) * (1.0 if step % 2 else 0.5)).astype(np.float32)
+        R.unet_adam(t_g, m_g, v_g, torch.tensor(g, device="cuda"), step, 1e-3, clip_norm=20.0,
+                    scratch=scratch)
         th, m, v = opt.step(th, g.astype(np.float64), m, v, step)
+        assert abs(scratch[-2].item() - np.linalg.norm(g.astype(np.float64))) < 1e-9 * 32
     assert np.abs(t_g.cpu().numpy() - th).max() < 1e-6
 
 

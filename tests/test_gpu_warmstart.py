@@ -1,0 +1,79 @@
+"""The trained warm start (paper_2403_01039_amd/weights) on held-out seeds.
+
+The warm start may change only the iteration count: on held-out seed 20000
+the warm-started solve must meet the same bar against the stored FP64
+oracle solution (rms 1e-10) as the plain solve, and on further held-out
+seeds it must converge with fewer iterations to the same SFE."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2403_01039_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "warm_20000.npz")
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_2403_01039_amd import rism3d
+    if not os.path.exists(rism3d.WEIGHTS_PATH):
+        pytest.skip("no trained warm-start weights in the package")
+    return rism3d
+
+
+@pytest.fixture(scope="module")
+def net(R):
+    return R.WarmStart()
+
+
+def _solve(R, net, prob, warm):
+    chi, dk = inputs.solvent_table_for(prob.solvent)
+    dp = R.DeviceProblem(prob, chi, dk)
+    opts = R.make_opts(prob.options)
+    s = R.Solver(dp, opts)
+    s.potential()
+    tau0 = net.tau0(dp, opts, s.ws) if warm else None
+    g = torch.empty(dp.shape, dtype=torch.float32, device="cuda")
+    info = s.solve(tau0=tau0, g_out=g)
+    sfe, _ = s.thermo()
+    return g, info, sfe
+
+
+def test_warm_start_meets_the_oracle_bar_on_held_out_seed(R, net):
+    ref = np.load(GOLDEN)
+    prob = inputs.warmstart_problem(20000)
+    idx = torch.as_tensor(ref["idx"], device="cuda")
+    stop = np.abs(ref["g_tol"] - ref["g_ref"]).max()
+    res = {}
+    for warm in (False, True):
+        g, info, sfe = _solve(R, net, prob, warm)
+        err = np.abs(g.reshape(3, -1)[:, idx].cpu().numpy() - ref["g_ref"]).max()
+        res[warm] = (info.iterations, err, sfe)
+        print(f"seed 20000 {'warm' if warm else 'plain'}: {info.iterations} iterations, "
+              f"max|dg| vs oracle {err:.2e} (stopping allowance {1.5 * stop:.2e}), "
+              f"sfe {sfe:.4f} vs {float(ref['sfe_ref']):.4f}", flush=True)
+        assert info.rms < 1e-6
+        assert err <= max(1e-4, 1.5 * stop)
+        assert abs(sfe - ref["sfe_ref"]) <= 1e-3 * abs(ref["sfe_ref"])
+        if warm:
+            assert info.warm_start_used == 1
+    assert res[True][0] < res[False][0]
+
+
+def test_warm_start_saves_iterations_on_held_out_seeds(R, net):
+    its_p, its_w = [], []
+    for seed in range(20001, 20005):
+        prob = inputs.warmstart_problem(seed)
+        _, ip, sp = _solve(R, net, prob, False)
+        _, iw, sw = _solve(R, net, prob, True)
+        print(f"seed {seed}: plain {ip.iterations}, warm {iw.iterations}; sfe {sp:.4f} / "
+              f"{sw:.4f}", flush=True)
+        assert iw.warm_start_used == 1 and iw.rms < 1e-6
+        assert abs(sw - sp) <= 1e-3 * abs(sp)
+        its_p.append(ip.iterations)
+        its_w.append(iw.iterations)
+    assert np.mean(its_w) <= 0.85 * np.mean(its_p)

@@ -163,6 +163,17 @@ def test_adam_constant_gradient_closed_form():
         assert np.allclose(theta, -t * 0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=1e-15)
 
 
+def test_adam_clipping_scales_the_first_moment():
+    """With clipping the first step stores m = (1 - beta1) g c / |g| when
+    |g| > c, and the unclipped m when |g| <= c."""
+    g = np.array([3.0, -4.0])                    # |g| = 5
+    for clip, expect in [(1.0, 0.1 * g / 5.0), (10.0, 0.1 * g)]:
+        opt = U.Adam(lr=0.01, clip=clip)
+        _, m, v = opt.step(np.zeros(2), g, np.zeros(2), np.zeros(2), 1)
+        assert np.allclose(m, expect, rtol=1e-15)
+        assert np.allclose(v, 0.001 * (expect / 0.1) ** 2, rtol=1e-12)
+
+
 def test_oz_half_step_returns_the_fixed_point():
     """At the converged solution c* = g* - 1 - tau*, the half-step gives
     h* - c* = tau* (the residual h + 1 - g vanishes there)."""
