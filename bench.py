@@ -71,9 +71,10 @@ def source_digest() -> str:
 
 def cpu_baseline(prob, chi, dk, iterations: int):
     """The FP64 oracle on a bounded sample of the workload: its potential on
-    1/64 of the grid points and its long-range spectrum for 1/8 of the atoms
-    (both scaled up), plus one full-size evaluation of the 3D-RISM map, scaled
-    by the iteration count of a solve.  Single-threaded numpy."""
+    1/16 of the grid points and its long-range spectrum for 1/4 of the atoms
+    (both scaled up), plus three full-size evaluations of the 3D-RISM map
+    (their mean scaled by the iteration count of a solve).  Single-threaded
+    numpy."""
     import numpy as np
     from threadpoolctl import threadpool_limits
     from oracle import rism3d as O
@@ -84,12 +85,12 @@ def cpu_baseline(prob, chi, dk, iterations: int):
         grid = prob.grid
         pts = O.grid_points(grid).reshape(-1, 3)
         rng = np.random.default_rng(0)
-        sample = pts[rng.choice(len(pts), size=len(pts) // 64, replace=False)]
+        sample = pts[rng.choice(len(pts), size=len(pts) // 16, replace=False)]
         t0 = time.perf_counter()
         O.potential_at(prob.solute, prob.solvent, sample)
-        t_pot = (time.perf_counter() - t0) * 64
-        sub = inputs.Solute(prob.solute.xyz[::8], prob.solute.q[::8], prob.solute.sigma[::8],
-                            prob.solute.eps[::8])
+        t_pot = (time.perf_counter() - t0) * 16
+        sub = inputs.Solute(prob.solute.xyz[::4], prob.solute.q[::4], prob.solute.sigma[::4],
+                            prob.solute.eps[::4])
         t0 = time.perf_counter()
         beta = O.beta_of(prob.solvent.temperature)
         O.ftilde_unit(sub, grid, beta)
@@ -103,16 +104,17 @@ def cpu_baseline(prob, chi, dk, iterations: int):
                           np.zeros(shape, dtype=np.complex128), chi3, "kh", 1)
         t = 0.01 * rng.standard_normal(shape)
         t0 = time.perf_counter()
-        O.rism_map(system, t)
-        t_map = time.perf_counter() - t0
+        for _ in range(3):
+            O.rism_map(system, t)
+        t_map = (time.perf_counter() - t0) / 3
         wall = time.perf_counter() - t_start
     per_solve = t_pot + t_ft + t_chi + iterations * t_map
     return {
         "value": 1.0 / per_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
-        "sample": (f"FP64 numpy oracle, 1 thread: potential on 1/64 of the grid points (x64), "
-                   f"long-range spectrum for 1/8 of the atoms (x8), chi interpolation, and one "
-                   f"full-size map evaluation ({t_map:.2f} s) x {iterations} iterations; "
-                   f"{wall:.1f} s of CPU work"),
+        "sample": (f"FP64 numpy oracle, 1 thread: potential on 1/16 of the grid points (x16), "
+                   f"long-range spectrum for 1/4 of the atoms (x4), chi interpolation, and the "
+                   f"full-size map evaluation (mean of 3: {t_map:.2f} s) x {iterations} "
+                   f"iterations; {wall:.1f} s of CPU work"),
         "seconds_per_solve": per_solve,
     }
 
@@ -216,6 +218,8 @@ def warm_start_comparison(R, inputs, n_seeds: int):
         R.rism3d_thermo(dp, opts, ws)
         return info
 
+    R.rism3d_potential(dps[0], opts, ws)
+    R.rism3d_autotune(dps[0], opts, ws)  # this grid's tile widths, as for the headline
     plain(dps[0]); warm(dps[0])          # warm-up (graph capture, workspaces)
     out = {}
     for name, fn in (("plain", plain), ("warm", warm)):
@@ -289,6 +293,9 @@ def main():
     torch.cuda.synchronize()
     R.timing_enable(False)
     breakdown = R.timing_read()
+    # one-time set-up outside the timed region: pick the tile widths of the
+    # FP32 iteration kernels for this grid (no effect on results)
+    tuning = R.rism3d_autotune(dp, opts, solver.ws, stream)
     for _ in range(max(args.warmup - 1, 0)):
         step()
     torch.cuda.synchronize()
@@ -364,6 +371,7 @@ def main():
                      "launches": timed["launches"], "avg_us": timed["avg_us"],
                      "bytes_per_launch": timed["bytes_per_launch"]},
         "kernels_first_warmup_step": kernels,
+        "tuning": tuning,
     }
     if args.warm_seeds > 0:
         out["warm_start"] = warm_start_comparison(R, inputs, args.warm_seeds)

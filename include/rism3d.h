@@ -303,6 +303,31 @@ rism3d_status rism3d_warmstart(const rism3d_problem* problem, const rism3d_opts*
                                void* d_ws, size_t ws_bytes, void* d_net_ws, size_t net_ws_bytes,
                                float* d_tau0, hipStream_t stream);
 
+/* Autotuning of the FP32 iteration kernels on grids with the fused path:
+ * times, on the prepared workspace d_ws (its spectrum buffer is zeroed and
+ * used as scratch), the y-pass transform with 8, 16, 32 or 64 lines per
+ * workgroup and the z-transform/contraction kernel with 4, 8 or 16 column
+ * pairs per workgroup (widths whose LDS tile would not fit are skipped),
+ * and keeps the fastest of each for this (nx, ny, nz, n_sites) in a
+ * process-wide table that every later solve of that shape uses (cached
+ * graphs are released).  The widths change which workgroup transforms a
+ * line, not the operations on it: results agree to round-off (separately
+ * compiled variants may fuse multiply-adds differently).  out (host, may be
+ * NULL) receives the
+ * choices (0 = the compiled default) and their times in microseconds.
+ * rism3d_tune_set() records given widths for a problem's shape (0 = default;
+ * widths without a compiled kernel for that length run the default), and
+ * rism3d_tune_reset() restores the defaults for every shape. */
+typedef struct {
+  int y_lines, z_cols;
+  double y_us, z_us, y_default_us, z_default_us;
+} rism3d_tuning;
+rism3d_status rism3d_autotune(const rism3d_problem* problem, const rism3d_opts* opts, void* d_ws,
+                              size_t ws_bytes, rism3d_tuning* out, hipStream_t stream);
+rism3d_status rism3d_tune_set(const rism3d_problem* problem, const rism3d_opts* opts, int y_lines,
+                              int z_cols);
+void rism3d_tune_reset(void);
+
 /* Kernel timing, for profiling (thread-local switch).  While enabled, calls on
  * this thread record a pair of HIP events on the call's stream around every
  * kernel launch and add the elapsed time to a per-family total when the call

@@ -341,12 +341,13 @@ __device__ inline void passes_from(C* buf, int nl, const C* tw2, S sgn) {
   }
 }
 
-template <typename C, int N, int AXIS>
+// LINES (lines per workgroup) defaults to fixed_lines; the autotuner may pick
+// another width for the y pass; it does not change the operations on a line.
+template <typename C, int N, int AXIS, int LINES = fixed_lines<C, N, AXIS>()>
 __global__ __launch_bounds__(kFftThreads) void k_fft_fixed(
     C* __restrict__ data, int nx, int ny, int nz, int npair, const C* __restrict__ tw2_g,
     int forward, const int* __restrict__ done, size_t bstride) {
   using S = typename ScalarOf<C>::type;
-  constexpr int LINES = fixed_lines<C, N, AXIS>();
   constexpr int TILE = LINES * N;
   constexpr int EPT = (TILE + kFftThreads - 1) / kFftThreads;
   done = member_ptr(done, bstride);

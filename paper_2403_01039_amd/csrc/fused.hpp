@@ -176,7 +176,9 @@ constexpr int zcz_cols() {
   return per_col * 16 <= 65536 ? 16 : per_col * 8 <= 65536 ? 8 : per_col * 4 <= 65536 ? 4 : 2;
 }
 
-template <typename C, int NZ, int NV, bool WITHF>
+// B (columns per side and workgroup) defaults to zcz_cols; the autotuner may
+// pick another width; it does not change the operations on a column.
+template <typename C, int NZ, int NV, bool WITHF, int B = zcz_cols<C, NZ, NV>()>
 __global__ __launch_bounds__(kFftThreads) void k_zcz(
     C* __restrict__ spec, int nx, int ny, const C* __restrict__ tw2_g, float dkx, float dky,
     float dkz, const C* __restrict__ F, const typename ScalarOf<C>::type* __restrict__ chi,
@@ -184,7 +186,6 @@ __global__ __launch_bounds__(kFftThreads) void k_zcz(
     const int* __restrict__ done, size_t bstride) {
   using S = typename ScalarOf<C>::type;
   constexpr int P = (NV + 1) / 2;
-  constexpr int B = zcz_cols<C, NZ, NV>();
   constexpr int LINES = 2 * P * B;     // line l = (side * P + p) * B + b
   done = member_ptr(done, bstride);
   if (done && *done) return;

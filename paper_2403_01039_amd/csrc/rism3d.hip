@@ -6,6 +6,7 @@
 // iterate.hpp.
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -415,10 +416,37 @@ struct Batch {
   size_t stride = 0;
 };
 
-template <typename C, int N, int AXIS>
+// Tile choices of the autotuner, per (nx, ny, nz, sites): y-pass lines per
+// workgroup and z-kernel columns per workgroup of the FP32 iterations (0 =
+// the compiled default).  They change which workgroup transforms a line, not
+// the operations on it (results agree to round-off).
+struct Tune {
+  int y_lines = 0;
+  int z_cols = 0;
+};
+std::mutex g_tune_mu;
+std::vector<std::pair<std::array<int, 4>, Tune>> g_tunes;
+
+Tune tune_for(const Layout& L) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  for (const auto& e : g_tunes)
+    if (e.first == std::array<int, 4>{L.nx, L.ny, L.nz, L.nv}) return e.second;
+  return Tune{};
+}
+
+void set_tune(const Layout& L, Tune t) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  for (auto& e : g_tunes)
+    if (e.first == std::array<int, 4>{L.nx, L.ny, L.nz, L.nv}) {
+      e.second = t;
+      return;
+    }
+  g_tunes.push_back({std::array<int, 4>{L.nx, L.ny, L.nz, L.nv}, t});
+}
+
+template <typename C, int N, int AXIS, int LINES = fixed_lines<C, N, AXIS>()>
 void launch_fixed_n(const Layout& L, C* spec, const C* tw, int forward, const int* done,
                     hipStream_t s, Batch bt = {}) {
-  constexpr int LINES = fixed_lines<C, N, AXIS>();
   unsigned grid;
   if (AXIS == 0) {
     const size_t rows = (size_t)L.npair * L.nz * L.ny;
@@ -428,8 +456,46 @@ void launch_fixed_n(const Layout& L, C* spec, const C* tw, int forward, const in
     const int outer = AXIS == 1 ? L.npair * L.nz : L.npair * L.ny;
     grid = (unsigned)outer * tiles_x;
   }
-  hipLaunchKernelGGL((k_fft_fixed<C, N, AXIS>), dim3(grid, bt.nb), dim3(kFftThreads), 0, s, spec,
-                     L.nx, L.ny, L.nz, L.npair, tw, forward, done, bt.stride);
+  hipLaunchKernelGGL((k_fft_fixed<C, N, AXIS, LINES>), dim3(grid, bt.nb), dim3(kFftThreads), 0, s,
+                     spec, L.nx, L.ny, L.nz, L.npair, tw, forward, done, bt.stride);
+}
+
+// y pass of the FP32 iterations with a tuned width (lines = 0: default).
+template <int N>
+void launch_y32_n(const Layout& L, float2* spec, const float2* tw, int forward, const int* done,
+                  hipStream_t s, Batch bt, int lines) {
+  switch (lines) {
+    case 8: launch_fixed_n<float2, N, 1, 8>(L, spec, tw, forward, done, s, bt); break;
+    case 16: launch_fixed_n<float2, N, 1, 16>(L, spec, tw, forward, done, s, bt); break;
+    case 32:
+      if constexpr (N <= 256) {
+        launch_fixed_n<float2, N, 1, 32>(L, spec, tw, forward, done, s, bt);
+        break;
+      }
+      [[fallthrough]];
+    case 64:
+      if constexpr (N <= 128) {
+        launch_fixed_n<float2, N, 1, 64>(L, spec, tw, forward, done, s, bt);
+        break;
+      }
+      [[fallthrough]];
+    default: launch_fixed_n<float2, N, 1>(L, spec, tw, forward, done, s, bt); break;
+  }
+}
+
+bool launch_y32(const Layout& L, float2* spec, const float2* tw, int forward, const int* done,
+                hipStream_t s, Batch bt, int lines) {
+  TIMED(F_FFTY32, s);
+  switch (L.ny) {
+    case 32: launch_y32_n<32>(L, spec, tw, forward, done, s, bt, lines); return true;
+    case 64: launch_y32_n<64>(L, spec, tw, forward, done, s, bt, lines); return true;
+    case 96: launch_y32_n<96>(L, spec, tw, forward, done, s, bt, lines); return true;
+    case 128: launch_y32_n<128>(L, spec, tw, forward, done, s, bt, lines); return true;
+    case 192: launch_y32_n<192>(L, spec, tw, forward, done, s, bt, lines); return true;
+    case 256: launch_y32_n<256>(L, spec, tw, forward, done, s, bt, lines); return true;
+    case 512: launch_y32_n<512>(L, spec, tw, forward, done, s, bt, lines); return true;
+    default: return false;
+  }
 }
 
 template <typename C, int AXIS>
@@ -515,16 +581,15 @@ bool zcz_supported(const Layout& L) {
   return (L.ny % 2) == 0 && (L.nz == 64 || L.nz == 96 || L.nz == 128 || L.nz == 256);
 }
 
-template <typename C, int NZ, int NV>
-void launch_zcz_n(const Layout& L, void* ws, float inv_dkt, const int* done, hipStream_t s,
+template <typename C, int NZ, int NV, int B = zcz_cols<C, NZ, NV>()>
+void launch_zcz_b(const Layout& L, void* ws, float inv_dkt, const int* done, hipStream_t s,
                   Batch bt) {
   constexpr bool F64 = std::is_same<C, double2>::value;
-  constexpr int B = zcz_cols<C, NZ, NV>();
   const int tiles_x = (L.nx + B - 1) / B;
   const dim3 grid((unsigned)(L.ny / 2) * tiles_x, bt.nb), block(kFftThreads);
   using S = typename ScalarOf<C>::type;
   TIMED(F64 ? F_ZCZ64 : F_ZCZ32, s);
-  hipLaunchKernelGGL((k_zcz<C, NZ, NV, F64>), grid, block, 0, s, at<C>(ws, L.off_spec), L.nx,
+  hipLaunchKernelGGL((k_zcz<C, NZ, NV, F64, B>), grid, block, 0, s, at<C>(ws, L.off_spec), L.nx,
                      L.ny, at<C>(ws, F64 ? L.off_tw64[2] : L.off_tw32[2]), (float)L.dkx,
                      (float)L.dky, (float)L.dkz, F64 ? at<C>(ws, L.off_F) : (const C*)nullptr,
                      at<S>(ws, F64 ? L.off_chi64 : L.off_chi32),
@@ -532,29 +597,45 @@ void launch_zcz_n(const Layout& L, void* ws, float inv_dkt, const int* done, hip
                      bt.stride);
 }
 
+// FP32 z kernel with a tuned width (cols = 0: default); widths whose tile
+// would exceed 120 KB of LDS are not compiled and fall back to the default.
+template <typename C, int NZ, int NV>
+void launch_zcz_n(const Layout& L, void* ws, float inv_dkt, const int* done, hipStream_t s,
+                  Batch bt, int cols = 0) {
+  if constexpr (std::is_same<C, float2>::value) {
+    constexpr int per_col = 2 * ((NV + 1) / 2) * Lds<NZ>::PITCH * (int)sizeof(C);
+    if (cols == 4) { launch_zcz_b<C, NZ, NV, 4>(L, ws, inv_dkt, done, s, bt); return; }
+    if constexpr (per_col * 8 <= 122880)
+      if (cols == 8) { launch_zcz_b<C, NZ, NV, 8>(L, ws, inv_dkt, done, s, bt); return; }
+    if constexpr (per_col * 16 <= 122880)
+      if (cols == 16) { launch_zcz_b<C, NZ, NV, 16>(L, ws, inv_dkt, done, s, bt); return; }
+  }
+  launch_zcz_b<C, NZ, NV>(L, ws, inv_dkt, done, s, bt);
+}
+
 template <typename C, int NZ>
 void launch_zcz_nz(const Layout& L, void* ws, float inv_dkt, const int* done, hipStream_t s,
-                   Batch bt) {
+                   Batch bt, int cols) {
   switch (L.nv) {
-    case 1: launch_zcz_n<C, NZ, 1>(L, ws, inv_dkt, done, s, bt); break;
-    case 2: launch_zcz_n<C, NZ, 2>(L, ws, inv_dkt, done, s, bt); break;
-    case 3: launch_zcz_n<C, NZ, 3>(L, ws, inv_dkt, done, s, bt); break;
-    case 4: launch_zcz_n<C, NZ, 4>(L, ws, inv_dkt, done, s, bt); break;
-    case 5: launch_zcz_n<C, NZ, 5>(L, ws, inv_dkt, done, s, bt); break;
-    case 6: launch_zcz_n<C, NZ, 6>(L, ws, inv_dkt, done, s, bt); break;
-    case 7: launch_zcz_n<C, NZ, 7>(L, ws, inv_dkt, done, s, bt); break;
-    default: launch_zcz_n<C, NZ, 8>(L, ws, inv_dkt, done, s, bt); break;
+    case 1: launch_zcz_n<C, NZ, 1>(L, ws, inv_dkt, done, s, bt, cols); break;
+    case 2: launch_zcz_n<C, NZ, 2>(L, ws, inv_dkt, done, s, bt, cols); break;
+    case 3: launch_zcz_n<C, NZ, 3>(L, ws, inv_dkt, done, s, bt, cols); break;
+    case 4: launch_zcz_n<C, NZ, 4>(L, ws, inv_dkt, done, s, bt, cols); break;
+    case 5: launch_zcz_n<C, NZ, 5>(L, ws, inv_dkt, done, s, bt, cols); break;
+    case 6: launch_zcz_n<C, NZ, 6>(L, ws, inv_dkt, done, s, bt, cols); break;
+    case 7: launch_zcz_n<C, NZ, 7>(L, ws, inv_dkt, done, s, bt, cols); break;
+    default: launch_zcz_n<C, NZ, 8>(L, ws, inv_dkt, done, s, bt, cols); break;
   }
 }
 
 template <typename C>
 void launch_zcz(const Layout& L, void* ws, float inv_dkt, const int* done, hipStream_t s,
-                Batch bt) {
+                Batch bt, int cols = 0) {
   switch (L.nz) {
-    case 64: launch_zcz_nz<C, 64>(L, ws, inv_dkt, done, s, bt); break;
-    case 96: launch_zcz_nz<C, 96>(L, ws, inv_dkt, done, s, bt); break;
-    case 128: launch_zcz_nz<C, 128>(L, ws, inv_dkt, done, s, bt); break;
-    default: launch_zcz_nz<C, 256>(L, ws, inv_dkt, done, s, bt); break;
+    case 64: launch_zcz_nz<C, 64>(L, ws, inv_dkt, done, s, bt, cols); break;
+    case 96: launch_zcz_nz<C, 96>(L, ws, inv_dkt, done, s, bt, cols); break;
+    case 128: launch_zcz_nz<C, 128>(L, ws, inv_dkt, done, s, bt, cols); break;
+    default: launch_zcz_nz<C, 256>(L, ws, inv_dkt, done, s, bt, cols); break;
   }
 }
 
@@ -633,9 +714,12 @@ void launch_iteration(const Layout& L, void* ws, const rism3d_opts* op, float in
         launch_zcz<double2>(L, ws, inv_dkt, done, s, bt);
         launch_axis(L, at<double2>(ws, L.off_spec), tw64, 1, 0, done, s, bt);
       } else {
-        launch_axis(L, at<float2>(ws, L.off_spec), tw32, 1, 1, done, s, bt);
-        launch_zcz<float2>(L, ws, inv_dkt, done, s, bt);
-        launch_axis(L, at<float2>(ws, L.off_spec), tw32, 1, 0, done, s, bt);
+        const Tune tn = tune_for(L);
+        if (!launch_y32(L, at<float2>(ws, L.off_spec), tw32[1], 1, done, s, bt, tn.y_lines))
+          launch_axis(L, at<float2>(ws, L.off_spec), tw32, 1, 1, done, s, bt);
+        launch_zcz<float2>(L, ws, inv_dkt, done, s, bt, tn.z_cols);
+        if (!launch_y32(L, at<float2>(ws, L.off_spec), tw32[1], 0, done, s, bt, tn.y_lines))
+          launch_axis(L, at<float2>(ws, L.off_spec), tw32, 1, 0, done, s, bt);
       }
     } else {
       if (anchor) launch_fft3<double2>(L, ws, 1, done, s, true);
@@ -1613,6 +1697,84 @@ rism3d_status rism3d_warmstart(const rism3d_problem* pr, const rism3d_opts* op,
                                 s)) != RISM3D_OK)
     return st;
   return rism3d_oz_half_step(pr, op, c0, c_scale, ws, ws_bytes, d_tau0, s);
+}
+
+rism3d_status rism3d_autotune(const rism3d_problem* pr, const rism3d_opts* op, void* ws,
+                              size_t ws_bytes, rism3d_tuning* out, hipStream_t s) {
+  Layout L;
+  rism3d_status st = make_layout(pr, op, &L);
+  if (st != RISM3D_OK) return st;
+  if ((st = check_ws(L, ws, ws_bytes)) != RISM3D_OK) return st;
+  rism3d_tuning res;
+  memset(&res, 0, sizeof(res));
+  if (!(fixed_fft_size(L.nx) && fixed_fft_size(L.ny) && zcz_supported(L))) {
+    if (out) *out = res;
+    return RISM3D_OK;   // no tunable kernels on this grid
+  }
+  const bool timing = g_timer.on;
+  g_timer.on = false;
+  float2* spec = at<float2>(ws, L.off_spec);
+  const float2* tw = at<float2>(ws, L.off_tw32[1]);
+  HIP_TRY(hipMemsetAsync(spec, 0, (size_t)L.npair * L.N * sizeof(float2), s));
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  const float inv_dkt = (float)(1.0 / pr->dk);
+  constexpr int kReps = 10;
+  auto time_us = [&](auto&& launch) -> double {
+    for (int r = 0; r < 2; ++r) launch();
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < kReps; ++r) launch();
+    (void)hipEventRecord(e1, s);
+    (void)hipEventSynchronize(e1);
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    return 1e3 * ms / kReps;
+  };
+  const int y_cands[] = {0, 8, 16, 32, 64};
+  const int z_cands[] = {0, 4, 8, 16};
+  double best_y = 1e30, best_z = 1e30;
+  for (int c : y_cands) {
+    if (c == 64 && L.ny > 128) continue;
+    const double us = time_us([&] { launch_y32(L, spec, tw, 1, nullptr, s, Batch{}, c); });
+    if (c == 0) res.y_default_us = us;
+    if (us < best_y) { best_y = us; res.y_lines = c; }
+  }
+  for (int c : z_cands) {
+    const double us =
+        time_us([&] { launch_zcz<float2>(L, ws, inv_dkt, nullptr, s, Batch{}, c); });
+    if (c == 0) res.z_default_us = us;
+    if (us < best_z) { best_z = us; res.z_cols = c; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  g_timer.on = timing;
+  LAUNCH_CHECK();
+  res.y_us = best_y;
+  res.z_us = best_z;
+  set_tune(L, Tune{res.y_lines, res.z_cols});
+  rism3d_release_graphs();   // captured graphs hold the previous kernels
+  if (out) *out = res;
+  return RISM3D_OK;
+}
+
+rism3d_status rism3d_tune_set(const rism3d_problem* pr, const rism3d_opts* op, int y_lines,
+                              int z_cols) {
+  Layout L;
+  rism3d_status st = make_layout(pr, op, &L);
+  if (st != RISM3D_OK) return st;
+  if (!(y_lines == 0 || y_lines == 8 || y_lines == 16 || y_lines == 32 || y_lines == 64) ||
+      !(z_cols == 0 || z_cols == 4 || z_cols == 8 || z_cols == 16))
+    return fail(RISM3D_E_ARG, "y_lines must be 0, 8, 16, 32 or 64 and z_cols 0, 4, 8 or 16");
+  set_tune(L, Tune{y_lines, z_cols});
+  rism3d_release_graphs();
+  return RISM3D_OK;
+}
+
+void rism3d_tune_reset(void) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tunes.clear();
+  rism3d_release_graphs();
 }
 
 const char* rism3d_last_error(void) { return g_error.c_str(); }

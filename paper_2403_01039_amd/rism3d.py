@@ -63,6 +63,12 @@ class ThermoOut(ctypes.Structure):
     _fields_ = [("sfe", ctypes.c_double), ("sfe_site", ctypes.c_double * MAX_SITES)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("y_lines", ctypes.c_int), ("z_cols", ctypes.c_int), ("y_us", ctypes.c_double),
+                ("z_us", ctypes.c_double), ("y_default_us", ctypes.c_double),
+                ("z_default_us", ctypes.c_double)]
+
+
 class UnetConfig(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int), ("base", ctypes.c_int), ("in_channels", ctypes.c_int),
                 ("out_channels", ctypes.c_int), ("slope", ctypes.c_float)]
@@ -94,6 +100,9 @@ def _load():
                                               ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
         "rism3d_timing_select": (ctypes.c_int, [ctypes.c_char_p]),
+        "rism3d_autotune": (ctypes.c_int, [P(Problem), P(Opts), vp, sz, P(Tuning), st]),
+        "rism3d_tune_reset": (None, []),
+        "rism3d_tune_set": (ctypes.c_int, [P(Problem), P(Opts), ctypes.c_int, ctypes.c_int]),
         "rism3d_unet_param_count": (sz, [P(UnetConfig)]),
         "rism3d_unet_workspace_bytes": (sz, [P(UnetConfig), ctypes.c_int, ctypes.c_int,
                                              ctypes.c_int, ctypes.c_int]),
@@ -132,7 +141,8 @@ EXPORTED = ("rism3d_workspace_bytes", "rism3d_potential", "rism3d_solve", "rism3
             "rism3d_batch_workspace_bytes", "rism3d_solve_batch", "rism3d_unet_param_count",
             "rism3d_unet_workspace_bytes", "rism3d_unet_forward", "rism3d_unet_gradient",
             "rism3d_unet_adam", "rism3d_unet_adam_scratch_bytes", "rism3d_net_input", "rism3d_csr", "rism3d_oz_half_step",
-            "rism3d_warmstart", "rism3d_last_error", "rism3d_constants")
+            "rism3d_warmstart", "rism3d_autotune", "rism3d_tune_reset",
+            "rism3d_tune_set", "rism3d_last_error", "rism3d_constants")
 
 
 def last_error() -> str:
@@ -351,6 +361,22 @@ def rism3d_solve_batch(dps, opts: Opts, ws: torch.Tensor, tau0=None, g_out=None,
     if thermo:
         sfe = [(t.sfe, np.array(t.sfe_site[:dp.shape[0]])) for t, dp in zip(th, dps)]
     return out_info, sfe
+
+
+def rism3d_autotune(dp, opts, ws, stream=None) -> dict:
+    t = Tuning()
+    _check(LIB.rism3d_autotune(ctypes.byref(dp.struct), ctypes.byref(opts), _ptr(ws), ws.numel(),
+                               ctypes.byref(t), _stream(stream)))
+    return {f: getattr(t, f) for f, _ in Tuning._fields_}
+
+
+def tune_reset():
+    LIB.rism3d_tune_reset()
+
+
+def tune_set(dp, opts, y_lines: int, z_cols: int):
+    _check(LIB.rism3d_tune_set(ctypes.byref(dp.struct), ctypes.byref(opts), int(y_lines),
+                               int(z_cols)))
 
 
 # --- warm-start network ------------------------------------------------------

@@ -100,3 +100,35 @@ def test_batch_nonconvergence_reports_member(R):
     assert infos[0].status == 3
     assert all(inf.iterations == 5 for inf in infos)
     assert "batch member" in R.last_error()
+
+
+def test_tile_widths_change_no_result(R):
+    """Every y-pass and z-kernel width the autotuner can choose, and its own
+    choice, converge to the default solve's fixed point: the widths change
+    which workgroup transforms a line, not the operations on it, so the
+    results agree to round-off (separately compiled variants may fuse
+    multiply-adds differently, and MDIIS can turn that into an iteration
+    more or less)."""
+    prob = inputs.small_problem(51, n_atoms=8, shape=(64, 32, 64), radius=3.0)
+    opts = R.make_opts(prob.options)
+    dp = R.DeviceProblem(prob, *inputs.solvent_table_for(prob.solvent))
+    R.tune_reset()
+    g0, i0, s0, _ = _single(R, prob, opts)
+    try:
+        for y, z in [(8, 4), (16, 8), (32, 16), (64, 0), (0, 16)]:
+            R.tune_set(dp, opts, y, z)
+            g, info, sfe, _ = _single(R, prob, opts)
+            dg = (g - g0).abs().max().item()
+            print(f"  widths y {y} z {z}: it {info.iterations} (default {i0.iterations}), "
+                  f"max|dg| {dg:.2e}", flush=True)
+            assert abs(info.iterations - i0.iterations) <= 5 and info.rms < 1e-6
+            assert dg <= 1e-3 and abs(sfe - s0) <= 1e-4 * abs(s0)
+        s = R.Solver(dp, opts)
+        s.potential()
+        res = R.rism3d_autotune(dp, opts, s.ws)
+        print(f"  autotune: {res}", flush=True)
+        assert res["y_us"] <= res["y_default_us"] and res["z_us"] <= res["z_default_us"]
+        g, info, sfe, _ = _single(R, prob, opts)
+        assert (g - g0).abs().max().item() <= 1e-3 and abs(sfe - s0) <= 1e-4 * abs(s0)
+    finally:
+        R.tune_reset()

@@ -118,17 +118,20 @@ CASES = [
     dict(seed=31, saline=False, closure="kh", q=1.0, shape=(64, 24, 32)),
     dict(seed=32, saline=True, closure="kh", q=1.0, shape=(32, 16, 64)),
     dict(seed=33, saline=False, closure="pse", q=0.5, shape=(96, 20, 32)),
+    # the 4000-atom globule's settings (PSE-3, MDIIS depth 10) on a fused grid
+    dict(seed=34, saline=False, closure="pse", q=0.5, shape=(64, 32, 32), depth=10),
 ]
 
 
 def _case_id(c):
     return (f"{c['closure']}-{'saline' if c['saline'] else 'water'}-q{c['q']}-"
-            f"{'x'.join(map(str, c['shape']))}")
+            f"{'x'.join(map(str, c['shape']))}" + (f"-m{c['depth']}" if "depth" in c else ""))
 
 
 def _case_problem(c):
     prob = inputs.small_problem(c["seed"], n_atoms=8, shape=c["shape"], radius=2.5,
-                                saline=c["saline"], closure=c["closure"], charge_scale=c["q"])
+                                saline=c["saline"], closure=c["closure"], charge_scale=c["q"],
+                                mdiis_depth=c.get("depth", 5))
     prob.options.mdiis_eta = c.get("eta", prob.options.mdiis_eta)
     return prob
 
@@ -235,6 +238,54 @@ def test_full_size_golden(R, name):
     assert err <= max(G_TOL, 1.5 * stop)
     assert abs(sfe - ref["sfe_ref"]) <= SFE_RTOL * abs(ref["sfe_ref"])
     assert abs(info.iterations - it_ref) <= 0.25 * it_ref
+
+
+def test_globule_4000_at_256(R, O):
+    """The 4000-atom globule (net +4, water, 256^3 at 0.4 A, PSE-3, MDIIS
+    depth 10) at full size: the potential at 2000 sampled points against the
+    oracle's pair sums, KH to rms 3e-6, then PSE-2 and PSE-3 from it to rms
+    1e-5, and the returned tau's residual under one FP64 evaluation of the
+    map."""
+    import time
+    prob = inputs.globule_4000_problem()
+    print("globule_4000 256^3", flush=True)
+    s, chi, dk = _run(R, prob)
+    w, phi = s.fields()
+    rng = np.random.default_rng(3)
+    idx = rng.choice(prob.grid.n_points, 2000, replace=False)
+    pts = O.grid_points(prob.grid).reshape(-1, 3)[idx]
+    u, phi_ref = O.potential_at(prob.solute, prob.solvent, pts)
+    beta = O.beta_of(prob.solvent.temperature)
+    q_v = prob.solvent.site_arrays()[0]
+    w_ref = np.minimum(beta * u, O.BETA_U_CAP) - beta * O.COULOMB * q_v[:, None] * phi_ref[None]
+    w_s = w.reshape(3, -1)[:, torch.as_tensor(idx, device="cuda")].cpu().numpy()
+    rel = np.abs(w_s - w_ref) / np.maximum(1.0, np.abs(w_ref))
+    soft = w_ref < 5.0
+    assert rel[soft].max() < 2e-5 and rel[~soft].max() < 1e-3
+    # Closure ramp: PSE-3 from tau0 = 0, or directly from the KH solution,
+    # diverges for this strongly charged solute (as the oracle does for small
+    # fully charged PSE-n cases); KH -> PSE-2 -> PSE-3 with damping 0.3.
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    # At this size FP32 storage of tau (|tau| up to hundreds in the core)
+    # floors the residual: KH reaches rms 3e-6; PSE-3 stalls near 6.5e-6
+    # (3000 iterations), so the PSE stages run to rms 1e-5.
+    s.opts = R.make_opts(prob.options, closure="kh", max_iter=3000, tol=3e-6)
+    info_kh = s.solve()
+    for order in (2, 3):   # PSE-2, then PSE-3, each from the previous solution
+        tau = s.tau()
+        s.opts = R.make_opts(prob.options, pse_order=order, mdiis_eta=0.3, max_iter=3000,
+                             tol=1e-5)
+        info = s.solve(tau0=tau)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    sfe, _ = s.thermo()
+    res, rms = s.map(s.tau())
+    print(f"  KH {info_kh.iterations} it, then PSE-2/PSE-3: {info.iterations} it, rms {info.rms:.2e}, "
+          f"{el:.2f} s; FP64 map rms at the returned tau {rms:.2e}; sfe {sfe:.2f}", flush=True)
+    assert info_kh.rms < 3e-6 and info.rms < 1e-5 and info.status == 0
+    assert rms < 2e-5
+    assert np.isfinite(sfe)
 
 
 def test_empty_solute_is_bulk(R):
