@@ -306,8 +306,10 @@ rism3d_status rism3d_warmstart(const rism3d_problem* problem, const rism3d_opts*
 /* Autotuning of the FP32 iteration kernels on grids with the fused path:
  * times, on the prepared workspace d_ws (its spectrum buffer is zeroed and
  * used as scratch), the y-pass transform with 8, 16, 32 or 64 lines per
- * workgroup and the z-transform/contraction kernel with 4, 8 or 16 column
- * pairs per workgroup (widths whose LDS tile would not fit are skipped),
+ * workgroup, the z-transform/contraction kernel with 4, 8 or 16 column
+ * pairs per workgroup, and the fused update/x-transform and x-transform/
+ * residual kernels with 8, 16 or 32 rows per workgroup (widths whose LDS
+ * tile would not fit run the default; the workspace's solution is not kept),
  * and keeps the fastest of each for this (nx, ny, nz, n_sites) in a
  * process-wide table that every later solve of that shape uses (cached
  * graphs are released).  The widths change which workgroup transforms a
@@ -319,13 +321,13 @@ rism3d_status rism3d_warmstart(const rism3d_problem* problem, const rism3d_opts*
  * widths without a compiled kernel for that length run the default), and
  * rism3d_tune_reset() restores the defaults for every shape. */
 typedef struct {
-  int y_lines, z_cols;
-  double y_us, z_us, y_default_us, z_default_us;
+  int y_lines, z_cols, x_lines;
+  double y_us, z_us, x_us, y_default_us, z_default_us, x_default_us;
 } rism3d_tuning;
 rism3d_status rism3d_autotune(const rism3d_problem* problem, const rism3d_opts* opts, void* d_ws,
                               size_t ws_bytes, rism3d_tuning* out, hipStream_t stream);
 rism3d_status rism3d_tune_set(const rism3d_problem* problem, const rism3d_opts* opts, int y_lines,
-                              int z_cols);
+                              int z_cols, int x_lines);
 void rism3d_tune_reset(void);
 
 /* Kernel timing, for profiling (thread-local switch).  While enabled, calls on

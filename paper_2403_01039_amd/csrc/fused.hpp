@@ -16,7 +16,9 @@ namespace rism {
 template <bool ANCHOR>
 using PrecC = typename std::conditional<ANCHOR, double2, float2>::type;
 
-template <bool ANCHOR, int N>
+// LINES (x rows per workgroup) of both fused kernels defaults to fixed_lines;
+// the autotuner may pick another count for the FP32 iterations.
+template <bool ANCHOR, int N, int LINES = fixed_lines<PrecC<ANCHOR>, N, 0>()>
 __global__ __launch_bounds__(kFftThreads) void k_update_fftx(
     const IterState* __restrict__ st, float* __restrict__ tau_hist,
     const float* __restrict__ res_hist, const float* __restrict__ w,
@@ -25,7 +27,6 @@ __global__ __launch_bounds__(kFftThreads) void k_update_fftx(
     const PrecC<ANCHOR>* __restrict__ tw2_g, size_t bstride) {
   using C = PrecC<ANCHOR>;
   using S = typename ScalarOf<C>::type;
-  constexpr int LINES = fixed_lines<C, N, 0>();
   constexpr int Q = N / 4;
   st = member_ptr(st, bstride);
   if (st->done) return;
@@ -72,7 +73,7 @@ __global__ __launch_bounds__(kFftThreads) void k_update_fftx(
   }
 }
 
-template <bool ANCHOR, int N>
+template <bool ANCHOR, int N, int LINES = fixed_lines<PrecC<ANCHOR>, N, 0>()>
 __global__ __launch_bounds__(kFftThreads) void k_fftx_residual(
     const IterState* __restrict__ st, const void* __restrict__ spec_v,
     const float* __restrict__ w, const float* __restrict__ tau_hist, float* __restrict__ res_hist,
@@ -81,7 +82,6 @@ __global__ __launch_bounds__(kFftThreads) void k_fftx_residual(
     double* __restrict__ partials, size_t bstride) {
   using C = PrecC<ANCHOR>;
   using S = typename ScalarOf<C>::type;
-  constexpr int LINES = fixed_lines<C, N, 0>();
   constexpr int Q = N / 4;
   st = member_ptr(st, bstride);
   if (st->done) return;

@@ -292,7 +292,9 @@ rism3d_status make_layout(const rism3d_problem* pr, const rism3d_opts* op, Layou
   const size_t part_q = (size_t)((M + 1) > nv ? (M + 1) : nv);
   size_t part_blocks = kRedBlocks;
   if (fixed_fft_size(pr->nx)) {   // one partial row per workgroup of the fused residual
-    const size_t lines = (size_t)(2048 / pr->nx > 1 ? 2048 / pr->nx : 1);
+    // (the narrowest variant: the FP64 tile, or 8 rows for a tuned FP32 one)
+    size_t lines = (size_t)(2048 / pr->nx > 1 ? 2048 / pr->nx : 1);
+    if (lines > 8) lines = 8;
     const size_t b = ((size_t)L->npair * pr->nz * pr->ny + lines - 1) / lines;
     if (b > part_blocks) part_blocks = b;
   }
@@ -423,6 +425,7 @@ struct Batch {
 struct Tune {
   int y_lines = 0;
   int z_cols = 0;
+  int x_lines = 0;   // rows per workgroup of the fused x kernels
 };
 std::mutex g_tune_mu;
 std::vector<std::pair<std::array<int, 4>, Tune>> g_tunes;
@@ -641,11 +644,10 @@ void launch_zcz(const Layout& L, void* ws, float inv_dkt, const int* done, hipSt
 
 // Fused first and last kernels of an iteration (x-axis transform fused with the
 // update+closure and with the residual+Gram+control).
-template <bool ANCHOR, int N>
-void launch_fused_n(const Layout& L, void* ws, const rism3d_opts* op, bool first_half,
-                    hipStream_t s, Batch bt) {
+template <bool ANCHOR, int N, int LINES = fixed_lines<PrecC<ANCHOR>, N, 0>()>
+void launch_fused_l(const Layout& L, void* ws, const rism3d_opts* op, bool first_half,
+                    hipStream_t s, Batch bt, bool control) {
   using C = PrecC<ANCHOR>;
-  constexpr int LINES = fixed_lines<C, N, 0>();
   IterState* st = at<IterState>(ws, L.off_state);
   const int kind = (int)op->closure;
   const int order = op->closure == RISM3D_PSE ? op->pse_order : 1;
@@ -654,7 +656,7 @@ void launch_fused_n(const Layout& L, void* ws, const rism3d_opts* op, bool first
   const C* tw = at<C>(ws, ANCHOR ? L.off_tw64[0] : L.off_tw32[0]);
   if (first_half) {
     TIMED(ANCHOR ? F_UPDFFT64 : F_UPDFFT32, s);
-    hipLaunchKernelGGL((k_update_fftx<ANCHOR, N>), grid, block, 0, s, st,
+    hipLaunchKernelGGL((k_update_fftx<ANCHOR, N, LINES>), grid, block, 0, s, st,
                        at<float>(ws, L.off_tau), at<float>(ws, L.off_res), at<float>(ws, L.off_w),
                        at<float>(ws, L.off_tref), at<float>(ws, L.off_dg),
                        at<void>(ws, L.off_spec), L.ny, L.nz, L.nv, L.npair, L.M, kind, order, tw,
@@ -662,13 +664,14 @@ void launch_fused_n(const Layout& L, void* ws, const rism3d_opts* op, bool first
   } else {
     {
       TIMED(ANCHOR ? F_FFTRES64 : F_FFTRES32, s);
-      hipLaunchKernelGGL((k_fftx_residual<ANCHOR, N>), grid, block, 0, s, st,
+      hipLaunchKernelGGL((k_fftx_residual<ANCHOR, N, LINES>), grid, block, 0, s, st,
                          at<void>(ws, L.off_spec), at<float>(ws, L.off_w),
                          at<float>(ws, L.off_tau), at<float>(ws, L.off_res),
                          at<float>(ws, L.off_tref), at<float>(ws, L.off_rref),
                          at<float>(ws, L.off_dg), L.ny, L.nz, L.nv, L.npair, L.M, kind, order, tw,
                          at<double>(ws, L.off_part), bt.stride);
     }
+    if (!control) return;
     TIMED(F_CONTROL, s);
     const double inv_count = 1.0 / ((double)L.N * (double)L.nv);
     hipLaunchKernelGGL(k_control, dim3(1, bt.nb), dim3(kRedThreads), 0, s, st,
@@ -677,17 +680,44 @@ void launch_fused_n(const Layout& L, void* ws, const rism3d_opts* op, bool first
   }
 }
 
+// FP32 fused kernels with a tuned row count (lines = 0: default); counts
+// whose LDS tile would exceed 64 KB are not compiled and run the default.
+template <bool ANCHOR, int N>
+void launch_fused_n(const Layout& L, void* ws, const rism3d_opts* op, bool first_half,
+                    hipStream_t s, Batch bt, int lines, bool control) {
+  if constexpr (!ANCHOR) {
+    constexpr int row = Lds<N>::PITCH * (int)sizeof(float2);
+    if (lines == 8) {
+      launch_fused_l<false, N, 8>(L, ws, op, first_half, s, bt, control);
+      return;
+    }
+    if constexpr (16 * row <= 65536)
+      if (lines == 16) {
+        launch_fused_l<false, N, 16>(L, ws, op, first_half, s, bt, control);
+        return;
+      }
+    if constexpr (32 * row <= 65536)
+      if (lines == 32) {
+        launch_fused_l<false, N, 32>(L, ws, op, first_half, s, bt, control);
+        return;
+      }
+  }
+  launch_fused_l<ANCHOR, N>(L, ws, op, first_half, s, bt, control);
+}
+
+// control = false leaves out the MDIIS control launch after the residual
+// kernel (the autotuner times the two fused kernels alone).
 template <bool ANCHOR>
 void launch_fused(const Layout& L, void* ws, const rism3d_opts* op, bool first_half,
-                  hipStream_t s, Batch bt) {
+                  hipStream_t s, Batch bt, int lines = 0, bool control = true) {
   switch (L.nx) {
-    case 32: launch_fused_n<ANCHOR, 32>(L, ws, op, first_half, s, bt); break;
-    case 64: launch_fused_n<ANCHOR, 64>(L, ws, op, first_half, s, bt); break;
-    case 96: launch_fused_n<ANCHOR, 96>(L, ws, op, first_half, s, bt); break;
-    case 128: launch_fused_n<ANCHOR, 128>(L, ws, op, first_half, s, bt); break;
-    case 192: launch_fused_n<ANCHOR, 192>(L, ws, op, first_half, s, bt); break;
-    case 256: launch_fused_n<ANCHOR, 256>(L, ws, op, first_half, s, bt); break;
-    default: launch_fused_n<ANCHOR, 512>(L, ws, op, first_half, s, bt); break;
+    case 32: launch_fused_n<ANCHOR, 32>(L, ws, op, first_half, s, bt, lines, control); break;
+    case 64: launch_fused_n<ANCHOR, 64>(L, ws, op, first_half, s, bt, lines, control); break;
+    case 96: launch_fused_n<ANCHOR, 96>(L, ws, op, first_half, s, bt, lines, control); break;
+    case 128: launch_fused_n<ANCHOR, 128>(L, ws, op, first_half, s, bt, lines, control); break;
+    case 192: launch_fused_n<ANCHOR, 192>(L, ws, op, first_half, s, bt, lines, control); break;
+    case 256: launch_fused_n<ANCHOR, 256>(L, ws, op, first_half, s, bt, lines, control); break;
+    default: launch_fused_n<ANCHOR, 512>(L, ws, op, first_half, s, bt, lines, control); break;
   }
 }
 
@@ -701,8 +731,9 @@ void launch_iteration(const Layout& L, void* ws, const rism3d_opts* op, float in
   const int kind = (int)op->closure;
   const int order = op->closure == RISM3D_PSE ? op->pse_order : 1;
   if (fixed_fft_size(L.nx)) {
+    const int xl = anchor ? 0 : tune_for(L).x_lines;
     if (anchor) launch_fused<true>(L, ws, op, true, s, bt);
-    else launch_fused<false>(L, ws, op, true, s, bt);
+    else launch_fused<false>(L, ws, op, true, s, bt, xl);
     if (zcz_supported(L)) {
       // y pass, then z + contraction + z fused, then inverse y pass
       const float2* tw32[3] = {at<float2>(ws, L.off_tw32[0]), at<float2>(ws, L.off_tw32[1]),
@@ -729,7 +760,7 @@ void launch_iteration(const Layout& L, void* ws, const rism3d_opts* op, float in
       else launch_fft3<float2>(L, ws, 0, done, s, true);
     }
     if (anchor) launch_fused<true>(L, ws, op, false, s, bt);
-    else launch_fused<false>(L, ws, op, false, s, bt);
+    else launch_fused<false>(L, ws, op, false, s, bt, xl);
     return;
   }
   const bool v4 = (L.N % 4) == 0;
@@ -1105,6 +1136,25 @@ __global__ void k_tau_from_h(const double2* __restrict__ spec, const float* __re
   const size_t n = id - (size_t)g * N;
   const double2 h = spec[(size_t)(g / 2) * N + n];
   tau0[id] = (float)(((g & 1) ? h.y : h.x) - scale * (double)c[id]);
+}
+
+// A state with every MDIIS slot stored and equal coefficients, so that timed
+// launches of the fused kernels do the work of a steady-state iteration.
+__global__ void k_tune_state(IterState* st, int M, float eta) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int i = 0; i < kMaxDepth; ++i) {
+    st->stored[i] = i < M;
+    st->coef[i] = i < M ? 1.0f / (float)M : 0.0f;
+    st->stamp[i] = i;
+  }
+  st->eta = eta;
+  st->dest = 0;
+  st->newest = M - 1;
+  st->iter = 1;
+  st->done = 0;
+  st->converged = 0;
+  st->status = 0;
+  st->final_slot = -1;
 }
 
 }  // namespace
@@ -1733,7 +1783,22 @@ rism3d_status rism3d_autotune(const rism3d_problem* pr, const rism3d_opts* op, v
   };
   const int y_cands[] = {0, 8, 16, 32, 64};
   const int z_cands[] = {0, 4, 8, 16};
-  double best_y = 1e30, best_z = 1e30;
+  const int x_cands[] = {0, 8, 16, 32};
+  double best_y = 1e30, best_z = 1e30, best_x = 1e30;
+  // fused x kernels: zeroed history and reference grids and a steady-state
+  // MDIIS state (the potential stays; the workspace's solution is not kept,
+  // the next rism3d_solve starts afresh)
+  HIP_TRY(hipMemsetAsync(at<char>(ws, L.off_tau), 0, L.off_spec - L.off_tau, s));
+  hipLaunchKernelGGL(k_tune_state, dim3(1), dim3(1), 0, s, at<IterState>(ws, L.off_state), L.M,
+                     (float)op->mdiis_eta);
+  for (int c : x_cands) {
+    const double us = time_us([&] {
+      launch_fused<false>(L, ws, op, true, s, Batch{}, c, false);
+      launch_fused<false>(L, ws, op, false, s, Batch{}, c, false);
+    });
+    if (c == 0) res.x_default_us = us;
+    if (us < best_x) { best_x = us; res.x_lines = c; }
+  }
   for (int c : y_cands) {
     if (c == 64 && L.ny > 128) continue;
     const double us = time_us([&] { launch_y32(L, spec, tw, 1, nullptr, s, Batch{}, c); });
@@ -1752,21 +1817,24 @@ rism3d_status rism3d_autotune(const rism3d_problem* pr, const rism3d_opts* op, v
   LAUNCH_CHECK();
   res.y_us = best_y;
   res.z_us = best_z;
-  set_tune(L, Tune{res.y_lines, res.z_cols});
+  res.x_us = best_x;
+  set_tune(L, Tune{res.y_lines, res.z_cols, res.x_lines});
   rism3d_release_graphs();   // captured graphs hold the previous kernels
   if (out) *out = res;
   return RISM3D_OK;
 }
 
 rism3d_status rism3d_tune_set(const rism3d_problem* pr, const rism3d_opts* op, int y_lines,
-                              int z_cols) {
+                              int z_cols, int x_lines) {
   Layout L;
   rism3d_status st = make_layout(pr, op, &L);
   if (st != RISM3D_OK) return st;
   if (!(y_lines == 0 || y_lines == 8 || y_lines == 16 || y_lines == 32 || y_lines == 64) ||
-      !(z_cols == 0 || z_cols == 4 || z_cols == 8 || z_cols == 16))
-    return fail(RISM3D_E_ARG, "y_lines must be 0, 8, 16, 32 or 64 and z_cols 0, 4, 8 or 16");
-  set_tune(L, Tune{y_lines, z_cols});
+      !(z_cols == 0 || z_cols == 4 || z_cols == 8 || z_cols == 16) ||
+      !(x_lines == 0 || x_lines == 8 || x_lines == 16 || x_lines == 32))
+    return fail(RISM3D_E_ARG,
+                "y_lines must be 0, 8, 16, 32 or 64, z_cols 0, 4, 8 or 16, x_lines 0, 8, 16 or 32");
+  set_tune(L, Tune{y_lines, z_cols, x_lines});
   rism3d_release_graphs();
   return RISM3D_OK;
 }

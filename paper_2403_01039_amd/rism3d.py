@@ -64,9 +64,10 @@ class ThermoOut(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("y_lines", ctypes.c_int), ("z_cols", ctypes.c_int), ("y_us", ctypes.c_double),
-                ("z_us", ctypes.c_double), ("y_default_us", ctypes.c_double),
-                ("z_default_us", ctypes.c_double)]
+    _fields_ = [("y_lines", ctypes.c_int), ("z_cols", ctypes.c_int), ("x_lines", ctypes.c_int),
+                ("y_us", ctypes.c_double), ("z_us", ctypes.c_double), ("x_us", ctypes.c_double),
+                ("y_default_us", ctypes.c_double), ("z_default_us", ctypes.c_double),
+                ("x_default_us", ctypes.c_double)]
 
 
 class UnetConfig(ctypes.Structure):
@@ -102,7 +103,8 @@ def _load():
         "rism3d_timing_select": (ctypes.c_int, [ctypes.c_char_p]),
         "rism3d_autotune": (ctypes.c_int, [P(Problem), P(Opts), vp, sz, P(Tuning), st]),
         "rism3d_tune_reset": (None, []),
-        "rism3d_tune_set": (ctypes.c_int, [P(Problem), P(Opts), ctypes.c_int, ctypes.c_int]),
+        "rism3d_tune_set": (ctypes.c_int, [P(Problem), P(Opts), ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_int]),
         "rism3d_unet_param_count": (sz, [P(UnetConfig)]),
         "rism3d_unet_workspace_bytes": (sz, [P(UnetConfig), ctypes.c_int, ctypes.c_int,
                                              ctypes.c_int, ctypes.c_int]),
@@ -374,9 +376,9 @@ def tune_reset():
     LIB.rism3d_tune_reset()
 
 
-def tune_set(dp, opts, y_lines: int, z_cols: int):
+def tune_set(dp, opts, y_lines: int, z_cols: int, x_lines: int = 0):
     _check(LIB.rism3d_tune_set(ctypes.byref(dp.struct), ctypes.byref(opts), int(y_lines),
-                               int(z_cols)))
+                               int(z_cols), int(x_lines)))
 
 
 # --- warm-start network ------------------------------------------------------

@@ -115,11 +115,11 @@ def test_tile_widths_change_no_result(R):
     R.tune_reset()
     g0, i0, s0, _ = _single(R, prob, opts)
     try:
-        for y, z in [(8, 4), (16, 8), (32, 16), (64, 0), (0, 16)]:
-            R.tune_set(dp, opts, y, z)
+        for y, z, x in [(8, 4, 8), (16, 8, 16), (32, 16, 32), (64, 0, 0), (0, 16, 8)]:
+            R.tune_set(dp, opts, y, z, x)
             g, info, sfe, _ = _single(R, prob, opts)
             dg = (g - g0).abs().max().item()
-            print(f"  widths y {y} z {z}: it {info.iterations} (default {i0.iterations}), "
+            print(f"  widths y {y} z {z} x {x}: it {info.iterations} (default {i0.iterations}), "
                   f"max|dg| {dg:.2e}", flush=True)
             assert abs(info.iterations - i0.iterations) <= 5 and info.rms < 1e-6
             assert dg <= 1e-3 and abs(sfe - s0) <= 1e-4 * abs(s0)
@@ -128,7 +128,28 @@ def test_tile_widths_change_no_result(R):
         res = R.rism3d_autotune(dp, opts, s.ws)
         print(f"  autotune: {res}", flush=True)
         assert res["y_us"] <= res["y_default_us"] and res["z_us"] <= res["z_default_us"]
+        assert res["x_us"] <= res["x_default_us"]
         g, info, sfe, _ = _single(R, prob, opts)
+        assert (g - g0).abs().max().item() <= 1e-3 and abs(sfe - s0) <= 1e-4 * abs(s0)
+    finally:
+        R.tune_reset()
+
+
+def test_autotune_keeps_the_prepared_potential(R):
+    """A solve right after rism3d_autotune on the same workspace (no second
+    rism3d_potential) reaches the same fixed point as an untuned solve."""
+    prob = inputs.small_problem(52, n_atoms=8, shape=(64, 32, 64), radius=3.0)
+    opts = R.make_opts(prob.options)
+    g0, i0, s0, _ = _single(R, prob, opts)
+    dp = R.DeviceProblem(prob, *inputs.solvent_table_for(prob.solvent))
+    s = R.Solver(dp, opts)
+    s.potential()
+    try:
+        R.rism3d_autotune(dp, opts, s.ws)
+        g = torch.empty(dp.shape, dtype=torch.float32, device="cuda")
+        info = s.solve(g_out=g)
+        sfe, _ = s.thermo()
+        assert info.rms < 1e-6
         assert (g - g0).abs().max().item() <= 1e-3 and abs(sfe - s0) <= 1e-4 * abs(s0)
     finally:
         R.tune_reset()
