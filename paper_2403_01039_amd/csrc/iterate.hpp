@@ -612,10 +612,8 @@ __device__ inline bool bordered_dispatch(const IterState& st, const int* slot, i
     case 4: return bordered_solve<4>(st, slot, m, c);
     case 5: return bordered_solve<5>(st, slot, m, c);
     case 6: return bordered_solve<6>(st, slot, m, c);
-    case 7: return bordered_solve<7>(st, slot, m, c);
-    case 8: return bordered_solve<8>(st, slot, m, c);
-    case 9: return bordered_solve<9>(st, slot, m, c);
-    case 10: return bordered_solve<10>(st, slot, m, c);
+    // deeper histories solve in LDS: a register-resident system of 8 or more
+    // unknowns would cap the control workgroup at 256 threads
     default: return bordered_solve_lds(st, slot, m, c, A);
   }
 }
@@ -725,10 +723,15 @@ __device__ inline void control_step(IterState& st, const double* sums,
 }
 
 // Shared-memory scratch of the control step.
+// The control workgroup: 1024 threads, so the thousands of per-workgroup
+// partial rows of the fused residual are summed in a few rounds (the Gram
+// solve keeps to 128 registers: systems beyond depth 6 solve in LDS).
+constexpr int kCtlThreads = 1024;
+
 struct ControlScratch {
   IterState st;
-  double red[kRedThreads / 64];
-  double wsum[kRedThreads / 64][kMaxDepth + 1];
+  double red[kCtlThreads / 64];
+  double wsum[kCtlThreads / 64][kMaxDepth + 1];
   double sums[kMaxDepth + 1];
   double A[kMaxDepth + 1][kMaxDepth + 2];
 };
@@ -782,7 +785,7 @@ __device__ inline void control_block(IterState* __restrict__ st_g,
   }
 }
 
-__global__ __launch_bounds__(kRedThreads) void k_control(
+__global__ __launch_bounds__(kCtlThreads) void k_control(
     IterState* __restrict__ st_g, const double* __restrict__ partials, int nblocks, int M,
     double inv_count, double tol, int max_iter, float eta_static, int eta_dynamic,
     size_t bstride) {
