@@ -361,6 +361,70 @@ def mdiis_solve(residual_fn, x0: np.ndarray, tol: float, depth: int, eta: float,
 
 
 # ---------------------------------------------------------------------------
+# Modified Anderson with two histories (Eq 34-39), the paper's GPU accelerator
+# ---------------------------------------------------------------------------
+
+
+def anderson_theta(R0, R1, R2, weight):
+    """theta of Eq 36, read as the normal equations of the least-squares
+    problem min |R0 - sum_i theta_i (R0 - R_i)| in the weighted inner product
+    of Eq 38: sum_j (D_j, D_i) theta_j = (R0, D_i), D_i = R0 - R_i.  Returns
+    None when the 2x2 system is singular (relative determinant < 1e-12)."""
+    ip = lambda a, b: float(np.sum(a * b * weight))
+    D1, D2 = R0 - R1, R0 - R2
+    a11, a12, a22 = ip(D1, D1), ip(D1, D2), ip(D2, D2)
+    r1, r2 = ip(R0, D1), ip(R0, D2)
+    det = a11 * a22 - a12 * a12
+    if not abs(det) > 1e-12 * max(a11 * a22, 1e-300):
+        return None
+    return np.array([(r1 * a22 - r2 * a12) / det, (a11 * r2 - a12 * r1) / det])
+
+
+def anderson_solve(residual_fn, x0: np.ndarray, tol: float, s, b: float, weight,
+                   max_iter: int, callback=None) -> SolveResult:
+    """Modified Anderson iteration on R(X) = Y - X with Y = F(X) (Eq 37):
+    Picard X <- X + b R for the first two steps, then with the three newest
+    inputs X^(n-1), X^(n-2), X^(n-3) and their outputs
+        u = X^(n-1) + sum_i (theta_i + s_i) (X^(n-i-1) - X^(n-1))     (Eq 34)
+        v = Y^(n)   + sum_i (theta_i + s_i) (Y^(n-i)   - Y^(n))        (Eq 35)
+        X^(n) = u + b (v - u)                                          (Eq 39)
+    A singular theta system falls back to a Picard step.  Stops when RMS(R)
+    < tol and returns the iterate whose residual passed."""
+    hist = []          # [x, R], newest last
+    x = x0
+    history = []
+    for it in range(1, max_iter + 1):
+        out = residual_fn(x)
+        R = out[0]
+        rms = rms_of(R)
+        history.append(rms)
+        if callback is not None:
+            callback(it, rms)
+        if not np.isfinite(rms):
+            raise FloatingPointError(f"non-finite residual at iteration {it}")
+        if rms < tol:
+            return SolveResult(x, R, out[1], out[2], it, rms, 0, True, history)
+        if it == max_iter:
+            return SolveResult(x, R, out[1], out[2], it, rms, 0, False, history)
+        hist.append([x, R])
+        if len(hist) > 3:
+            hist.pop(0)
+        theta = None
+        if len(hist) == 3:
+            (X2, R2), (X1, R1), (X0, R0) = hist
+            theta = anderson_theta(R0, R1, R2, weight)
+        if theta is None:
+            x = x + b * R
+            continue
+        Y0, Y1, Y2 = X0 + R0, X1 + R1, X2 + R2
+        k1, k2 = theta[0] + s[0], theta[1] + s[1]
+        u = X0 + k1 * (X1 - X0) + k2 * (X2 - X0)
+        v = Y0 + k1 * (Y1 - Y0) + k2 * (Y2 - Y0)
+        x = u + b * (v - u)
+    raise AssertionError("unreachable")
+
+
+# ---------------------------------------------------------------------------
 # Solve (steps 1-7) and thermodynamics (Eq 17-18)
 # ---------------------------------------------------------------------------
 
@@ -388,16 +452,25 @@ def solve(sys_: System, tol: Optional[float] = None, tau0: Optional[np.ndarray] 
           max_iter: Optional[int] = None, depth: Optional[int] = None,
           eta: Optional[float] = None, callback=None) -> Solution:
     """Step 1: t0 = f (tau0 = t0 - f = 0 unless a start is supplied); steps 2-7
-    with MDIIS.  Returns the converged t together with g, h = g - 1 and
+    with MDIIS, or with modified Anderson when the options ask for it.  Returns the converged t together with g, h = g - 1 and
     c = g - 1 - t."""
     opts = sys_.problem.options
     tol = opts.tol if tol is None else tol
     t0 = sys_.f.copy() if tau0 is None else sys_.f + tau0
-    res = mdiis_solve(lambda t: rism_map(sys_, t), t0, tol,
-                      opts.mdiis_depth if depth is None else depth,
-                      opts.mdiis_eta if eta is None else eta,
-                      opts.max_iter if max_iter is None else max_iter,
-                      opts.eta_dynamic, callback)
+    if getattr(opts, "accelerator", "mdiis") == "anderson":
+        # Eq 38: inner product weighted by 1 / rho of each solvent site
+        rho = sys_.problem.solvent.site_arrays()[3]
+        weight = (1.0 / rho)[:, None, None, None]
+        res = anderson_solve(lambda t: rism_map(sys_, t), t0, tol,
+                             (opts.anderson_s1, opts.anderson_s2),
+                             opts.mdiis_eta if eta is None else eta, weight,
+                             opts.max_iter if max_iter is None else max_iter, callback)
+    else:
+        res = mdiis_solve(lambda t: rism_map(sys_, t), t0, tol,
+                          opts.mdiis_depth if depth is None else depth,
+                          opts.mdiis_eta if eta is None else eta,
+                          opts.max_iter if max_iter is None else max_iter,
+                          opts.eta_dynamic, callback)
     d = -sys_.beta_u + res.t
     g = closure(d, sys_.kind, sys_.order)
     h = g - 1.0

@@ -259,3 +259,112 @@ def test_mdiis_depth_one_is_damped_picard():
     for k in range(6):
         assert np.allclose(seen[k], x, atol=1e-14)
         x = x + 0.5 * (A @ x + b - x)
+
+
+# ---------------------------------------------------------------------------
+# Modified Anderson (Eq 34-39)
+# ---------------------------------------------------------------------------
+
+def test_anderson_first_two_steps_are_picard():
+    """Steps 1 and 2 are X <- X + b R; the third uses theta."""
+    A = np.array([[0.5, 0.1, 0.0], [0.0, 0.3, 0.2], [0.1, 0.0, 0.4]])
+    c = np.array([1.0, -2.0, 0.5])
+    seen = []
+
+    def F(x):
+        seen.append(x.copy())
+        R = A @ x + c - x
+        return R, None, None
+
+    O.anderson_solve(F, np.zeros(3), 1e-30, (0.2, 0.0), 0.6, 1.0, 3)
+    x0 = np.zeros(3)
+    x1 = x0 + 0.6 * (A @ x0 + c - x0)
+    x2 = x1 + 0.6 * (A @ x1 + c - x1)
+    assert np.allclose(seen[1], x1, rtol=0, atol=1e-15)
+    assert np.allclose(seen[2], x2, rtol=0, atol=1e-15)
+
+
+def test_anderson_solves_a_two_dimensional_linear_map_exactly():
+    """With s = 0 and b = 1, Anderson with two histories on an affine map of
+    a 2-dimensional space reaches the fixed point exactly at its first
+    Anderson step: the two residual differences span the space, so the
+    least-squares combination has zero residual."""
+    A = np.array([[0.6, 0.3], [-0.2, 0.5]])
+    c = np.array([1.0, 2.0])
+    xstar = np.linalg.solve(np.eye(2) - A, c)
+    seen = []
+
+    def F(x):
+        seen.append(x.copy())
+        return A @ x + c - x, None, None
+
+    res = O.anderson_solve(F, np.zeros(2), 1e-13, (0.0, 0.0), 1.0, 1.0, 10)
+    assert res.converged and res.iterations <= 4
+    assert np.abs(seen[3] - xstar).max() < 1e-12
+
+
+def test_anderson_converges_to_the_linear_fixed_point():
+    """Paper parameters (s1 0.2, s2 0, b 0.6) on a contraction of R^20."""
+    rng = np.random.default_rng(4)
+    A = rng.standard_normal((20, 20))
+    A *= 0.8 / np.max(np.abs(np.linalg.eigvals(A)))
+    c = rng.standard_normal(20)
+    xstar = np.linalg.solve(np.eye(20) - A, c)
+    res = O.anderson_solve(lambda x: (A @ x + c - x, None, None), np.zeros(20), 1e-12,
+                           (0.2, 0.0), 0.6, 1.0, 2000)
+    assert res.converged
+    assert np.abs(res.t - xstar).max() < 1e-10
+
+
+def test_anderson_and_mdiis_reach_the_same_3d_fixed_point():
+    """The accelerator changes only the path: both reach the same discrete
+    fixed point (water, KH), and the inner-product weights 1/rho enter only
+    the choice of theta."""
+    import copy
+    prob = I.small_problem(5, n_atoms=6, shape=(16, 16, 16), radius=2.5)
+    chi, dk = I.solvent_table_for(prob.solvent)
+    sys_ = O.build_system(prob, chi, dk)
+    a = O.solve(sys_, tol=1e-10)
+    p2 = copy.deepcopy(prob)
+    p2.options.accelerator = "anderson"
+    p2.options.mdiis_eta = 0.6
+    sys2 = O.build_system(p2, chi, dk)
+    b = O.solve(sys2, tol=1e-10)
+    assert a.converged and b.converged
+    assert np.abs(a.g - b.g).max() < 1e-8
+
+
+def test_anderson_theta_is_the_weighted_least_squares_solution():
+    """theta minimises |sqrt(w) (R0 - sum_i theta_i (R0 - R_i))|: compare with
+    numpy's least-squares solver on the weight-scaled vectors (per-site weights
+    1/rho differ for an electrolyte)."""
+    rng = np.random.default_rng(11)
+    R0, R1, R2 = (rng.standard_normal((5, 4, 4, 4)) for _ in range(3))
+    w = (1.0 / np.array([0.0334, 0.0334, 0.0334, 6.0e-5, 6.0e-5]))[:, None, None, None]
+    theta = O.anderson_theta(R0, R1, R2, w)
+    sw = np.sqrt(w) * np.ones_like(R0)
+    M = np.stack([(sw * (R0 - R1)).ravel(), (sw * (R0 - R2)).ravel()], axis=1)
+    ref, *_ = np.linalg.lstsq(M, (sw * R0).ravel(), rcond=None)
+    assert np.allclose(theta, ref, rtol=1e-10, atol=1e-12)
+
+
+def test_anderson_shifts_and_mixing_closed_form():
+    """For an affine map F(x) = A x + c the residual is affine in x, so with
+    sum c_k = 1 the first Anderson step X3 = sum c_k (X_k + b R_k) has
+    R(X3) = (I + b (A - I)) sum c_k R_k.  In two dimensions the optimal theta
+    makes the unshifted combination vanish, leaving
+        sum c_k R_k = s1 (R^(n-2) - R^(n-1)) + s2 (R^(n-3) - R^(n-1)),
+    so R(X3) pins which shift pairs with which history and the role of b."""
+    A = np.array([[0.6, 0.3], [-0.2, 0.5]])
+    c = np.array([1.0, 2.0])
+    b, s = 0.6, (0.2, 0.05)
+    seen = []
+
+    def F(x):
+        seen.append(x.copy())
+        return A @ x + c - x, None, None
+
+    O.anderson_solve(F, np.zeros(2), 1e-30, s, b, 1.0, 4)
+    R = [A @ x + c - x for x in seen]
+    expect = (np.eye(2) + b * (A - np.eye(2))) @ (s[0] * (R[1] - R[2]) + s[1] * (R[0] - R[2]))
+    assert np.abs(R[3] - expect).max() < 1e-12
