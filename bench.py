@@ -190,8 +190,9 @@ def summarize_counters(fetch_csv: str, write_csv: str, copy_bytes: int, out_path
 def warm_start_comparison(R, inputs, n_seeds: int):
     """Plain vs warm-started solves on held-out seeds of the warm-start
     workload (200-atom solutes in water, 128^3 at 0.5 A, KH, MDIIS 5, rms
-    1e-6).  One solve = potential + [network inference + OZ half-step] +
-    iterations + SFE; inputs resident on the device."""
+    1e-6), and the same two with modified Anderson.  One solve = potential +
+    [network inference + OZ half-step] + iterations + SFE; inputs resident on
+    the device."""
     import numpy as np
     import torch
     if not os.path.exists(R.WEIGHTS_PATH):
@@ -220,9 +221,28 @@ def warm_start_comparison(R, inputs, n_seeds: int):
 
     R.rism3d_potential(dps[0], opts, ws)
     R.rism3d_autotune(dps[0], opts, ws)  # this grid's tile widths, as for the headline
+    opts_a = R.make_opts(probs[0].options, accelerator="anderson", mdiis_eta=0.6,
+                         anderson_s1=0.2, anderson_s2=0.0)
+
+    def warm_anderson(dp):
+        R.rism3d_potential(dp, opts_a, ws)
+        net.tau0(dp, opts_a, ws, tau0)
+        info = R.rism3d_solve(dp, opts_a, ws, tau0)
+        R.rism3d_thermo(dp, opts_a, ws)
+        return info
+
+    def plain_anderson(dp):
+        R.rism3d_potential(dp, opts_a, ws)
+        info = R.rism3d_solve(dp, opts_a, ws)
+        R.rism3d_thermo(dp, opts_a, ws)
+        return info
+
+    R.rism3d_autotune(dps[0], opts_a, ws)
     plain(dps[0]); warm(dps[0])          # warm-up (graph capture, workspaces)
+    plain_anderson(dps[0]); warm_anderson(dps[0])
     out = {}
-    for name, fn in (("plain", plain), ("warm", warm)):
+    for name, fn in (("plain", plain), ("warm", warm), ("plain_anderson", plain_anderson),
+                     ("warm_anderson", warm_anderson)):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         its = [fn(dp).iterations for dp in dps]
@@ -230,9 +250,37 @@ def warm_start_comparison(R, inputs, n_seeds: int):
         el = time.perf_counter() - t0
         out[name] = {"solves_per_s": len(dps) / el, "iterations_mean": float(np.mean(its))}
     out["speedup"] = out["warm"]["solves_per_s"] / out["plain"]["solves_per_s"]
+    out["speedup_warm_anderson_vs_plain_mdiis"] = (out["warm_anderson"]["solves_per_s"]
+                                                  / out["plain"]["solves_per_s"])
     out["workload"] = (f"warm_start: held-out seeds {seeds[0]}..{seeds[-1]}, 200-atom solutes in "
                        f"water (3 sites), 128^3 at 0.5 A, KH, MDIIS 5, rms 1e-6")
     return out
+
+
+def anderson_comparison(R, prob, dp, stream, n: int):
+    """The headline workload with the paper's GPU accelerator (modified
+    Anderson, two histories, s1 0.2, s2 0, b 0.6) instead of MDIIS."""
+    import torch
+    opts = R.make_opts(prob.options, accelerator="anderson", mdiis_eta=0.6,
+                       anderson_s1=0.2, anderson_s2=0.0)
+    solver = R.Solver(dp, opts)
+    R.rism3d_potential(dp, opts, solver.ws, stream)
+    R.rism3d_autotune(dp, opts, solver.ws, stream)
+
+    def step():
+        solver.potential(stream)
+        info = solver.solve(stream=stream)
+        solver.thermo(stream)
+        return info
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = [step().iterations for _ in range(n)]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    return {"solves_per_s": n / el, "iterations_mean": sum(its) / n,
+            "accelerator": "modified Anderson (s1 0.2, s2 0, b 0.6)"}
 
 
 def main():
@@ -241,6 +289,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--anderson-steps", type=int, default=2,
+                    help="solves of the headline workload with modified Anderson (0: skip)")
     ap.add_argument("--warm-seeds", type=int, default=8,
                     help="held-out seeds of the plain vs warm-start comparison (0: skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -373,6 +423,8 @@ def main():
         "kernels_first_warmup_step": kernels,
         "tuning": tuning,
     }
+    if args.anderson_steps > 0:
+        out["anderson"] = anderson_comparison(R, prob, dp, stream, args.anderson_steps)
     if args.warm_seeds > 0:
         out["warm_start"] = warm_start_comparison(R, inputs, args.warm_seeds)
     if not args.no_cpu_baseline:

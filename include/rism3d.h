@@ -102,7 +102,14 @@ typedef struct {
  * check_every (host polls the device convergence flag every this many
  * iterations; 0 picks a default), anchor_every (every this many iterations the
  * residual is evaluated exactly in FP64 and the FP32 iterations in between
- * transform only the increment from that anchor; 0 picks a default). */
+ * transform only the increment from that anchor; 0 picks a default),
+ * accelerator (RISM3D_MDIIS, or RISM3D_ANDERSON: the modified Anderson method
+ * with two histories of section "Convergence acceleration", Eq 34-39: Picard
+ * for the first two steps, then theta from Eq 36 in the inner product of
+ * Eq 38 with weights 1/rho_g, shifts anderson_s1 and anderson_s2 (the paper
+ * uses 0.2 and 0.0) and mixing b = mdiis_eta (the paper uses 0.6); it keeps
+ * three (tau, R) pairs whatever mdiis_depth says). */
+typedef enum { RISM3D_MDIIS = 0, RISM3D_ANDERSON = 1 } rism3d_accelerator;
 typedef struct {
   rism3d_closure closure;
   int pse_order;
@@ -113,6 +120,8 @@ typedef struct {
   int eta_dynamic;
   int check_every;
   int anchor_every;
+  rism3d_accelerator accelerator;
+  double anderson_s1, anderson_s2;
 } rism3d_opts;
 
 typedef struct {

@@ -31,6 +31,12 @@ struct SiteConsts {
   double rho[kMaxSites];
 };
 
+// Per-site weights of the Gram inner product: 1 for MDIIS (unweighted), 1/rho
+// for modified Anderson (Eq 38).  The RMS of Eq 41 stays unweighted.
+struct GramW {
+  float w[kMaxSites];
+};
+
 // Solvent-site LJ parameters (Lorentz-Berthelot mixing with each solute atom).
 struct SiteLJ {
   double sigma[kMaxSites];

@@ -79,7 +79,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fftx_residual(
     const float* __restrict__ w, const float* __restrict__ tau_hist, float* __restrict__ res_hist,
     float* __restrict__ tau_ref, float* __restrict__ r_ref, const float* __restrict__ dg, int ny,
     int nz, int nv, int npair, int M, int kind, int order, const PrecC<ANCHOR>* __restrict__ tw2_g,
-    double* __restrict__ partials, size_t bstride) {
+    double* __restrict__ partials, GramW gw, size_t bstride) {
   using C = PrecC<ANCHOR>;
   using S = typename ScalarOf<C>::type;
   constexpr int Q = N / 4;
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fftx_residual(
       h64[1][v] = (double)h.y;
     }
     residual_points<ANCHOR, 4>(hre, him, h64, w, tau_hist, res_hist, tau_ref, r_ref, dg, N3, nv,
-                               p, n, dest, mask, kind, order, acc);
+                               p, n, dest, mask, kind, order, gw, acc);
   }
   write_partials(acc, M, partials, red);
 }

@@ -367,10 +367,11 @@ __device__ inline void residual_points(const float* hre, const float* him, const
                                        float* __restrict__ res_hist, float* __restrict__ tau_ref,
                                        float* __restrict__ r_ref, const float* __restrict__ dg,
                                        size_t N, int nv, int p, size_t n, int dest, unsigned mask,
-                                       int kind, int order, double* acc) {
+                                       int kind, int order, const GramW& gw, double* acc) {
   for (int s = 0; s < 2; ++s) {
     const int g = 2 * p + s;
     if (g >= nv) break;
+    const double wg = (double)gw.w[g];
     const size_t gn = (size_t)g * N + n;
     const size_t od = (size_t)dest * nv * N + gn;
     float R[V];
@@ -393,15 +394,20 @@ __device__ inline void residual_points(const float* hre, const float* him, const
       for (int v = 0; v < V; ++v) R[v] = rr[v] + ((s ? him[v] : hre[v]) - dd[v]);
     }
     stv<V>(res_hist + od, R);
+    double rr = 0.0;
 #pragma unroll
-    for (int v = 0; v < V; ++v) acc[kMaxDepth] += (double)R[v] * (double)R[v];
+    for (int v = 0; v < V; ++v) rr += (double)R[v] * (double)R[v];
+    acc[kMaxDepth] += rr;          // unweighted: the RMS
 #pragma unroll
     for (int i = 0; i < kMaxDepth; ++i) {
+      if (i == dest) acc[i] += wg * rr;   // weighted Gram diagonal
       if (mask & (1u << i)) {
         float ri[V];
         ldv<V>(res_hist + (size_t)i * nv * N + gn, ri);
+        double d = 0.0;
 #pragma unroll
-        for (int v = 0; v < V; ++v) acc[i] += (double)R[v] * (double)ri[v];
+        for (int v = 0; v < V; ++v) d += (double)R[v] * (double)ri[v];
+        acc[i] += wg * d;
       }
     }
   }
@@ -433,7 +439,7 @@ __global__ __launch_bounds__(kRedThreads) void k_residual(
     const IterState* __restrict__ st, const void* __restrict__ spec, const float* __restrict__ w,
     const float* __restrict__ tau_hist, float* __restrict__ res_hist, float* __restrict__ tau_ref,
     float* __restrict__ r_ref, const float* __restrict__ dg, size_t N, int nv, int npair, int M,
-    int kind, int order, double* __restrict__ partials) {
+    int kind, int order, double* __restrict__ partials, GramW gw) {
   if (st->done) return;
   __shared__ double red[kRedThreads / 64];
   const int dest = st->dest;
@@ -474,7 +480,7 @@ __global__ __launch_bounds__(kRedThreads) void k_residual(
       }
     }
     residual_points<ANCHOR, V>(hre, him, h64, w, tau_hist, res_hist, tau_ref, r_ref, dg, N, nv, p,
-                               n, dest, mask, kind, order, acc);
+                               n, dest, mask, kind, order, gw, acc);
   }
   write_partials(acc, M, partials, red);
 }
@@ -619,9 +625,28 @@ __device__ inline bool bordered_dispatch(const IterState& st, const int* slot, i
 }
 
 // One control step on a (shared-memory) copy of the state; single thread.
+// theta of Eq 36 from the stored weighted Gram entries of the newest (0) and
+// the two previous (1, 2) residuals; false when the 2x2 system is singular.
+__device__ inline bool anderson_theta(const IterState& st, int s0, int s1, int s2, double* theta) {
+  const double g00 = st.gram[s0][s0], g01 = st.gram[s0][s1], g02 = st.gram[s0][s2];
+  const double g11 = st.gram[s1][s1], g12 = st.gram[s1][s2], g22 = st.gram[s2][s2];
+  const double a11 = g00 - 2.0 * g01 + g11;   // (D1, D1), D_i = R0 - R_i
+  const double a12 = g00 - g01 - g02 + g12;   // (D1, D2)
+  const double a22 = g00 - 2.0 * g02 + g22;   // (D2, D2)
+  const double r1 = g00 - g01, r2 = g00 - g02;  // (R0, D_i)
+  const double det = a11 * a22 - a12 * a12;
+  if (!(fabs(det) > 1e-12 * fmax(a11 * a22, 1e-300))) return false;
+  theta[0] = (r1 * a22 - r2 * a12) / det;
+  theta[1] = (a11 * r2 - a12 * r1) / det;
+  return true;
+}
+
+// accel: RISM3D_MDIIS or RISM3D_ANDERSON (shifts as1, as2; mixing eta_static).
 __device__ inline void control_step(IterState& st, const double* sums,
                                     double (*A)[kMaxDepth + 2], int M, double inv_count,
-                                    double tol, int max_iter, float eta_static, int eta_dynamic) {
+                                    double tol, int max_iter, float eta_static, int eta_dynamic,
+                                    int accel, double as1, double as2) {
+  const bool anderson = accel == RISM3D_ANDERSON;
   const int dest = st.dest;
   const double rr = sums[M];
   const double rms = sqrt(rr * inv_count);
@@ -657,7 +682,7 @@ __device__ inline void control_step(IterState& st, const double* sums,
       best_rms = st.rms_slot[i];
     }
   }
-  if (best >= 0 && rms > 10.0 * best_rms) {
+  if (!anderson && best >= 0 && rms > 10.0 * best_rms) {
     for (int i = 0; i < M; ++i) st.stored[i] = (i == best);
     st.newest = best;
     st.restarts += 1;
@@ -672,7 +697,7 @@ __device__ inline void control_step(IterState& st, const double* sums,
         st.gram[i][dest] = sums[i];
       }
     }
-    st.gram[dest][dest] = rr;
+    st.gram[dest][dest] = anderson ? sums[dest] : rr;   // weighted for Anderson (Eq 38)
   }
   // Stored slots, oldest first.
   int slot[kMaxDepth];
@@ -689,7 +714,20 @@ __device__ inline void control_step(IterState& st, const double* sums,
     slot[b + 1] = v;
   }
   double c[kMaxDepth];
-  if (m == 1) {
+  double theta[2];
+  if (anderson) {
+    // Picard for the first two steps (and for a singular theta system), then
+    // X = sum c_k (X_k + b R_k) with c = (theta_2 + s_2, theta_1 + s_1,
+    // 1 - sum(theta + s)) on the three pairs oldest first (Eq 34-39)
+    for (int i = 0; i < m; ++i) c[i] = 0.0;
+    c[m - 1] = 1.0;
+    if (m == 3 && anderson_theta(st, slot[2], slot[1], slot[0], theta)) {
+      const double k1 = theta[0] + as1, k2 = theta[1] + as2;
+      c[2] = 1.0 - k1 - k2;
+      c[1] = k1;
+      c[0] = k2;
+    }
+  } else if (m == 1) {
     c[0] = 1.0;
   } else if (!bordered_dispatch(st, slot, m, M, c, A)) {
     // ill-conditioned subspace: restart from the best stored pair
@@ -706,7 +744,7 @@ __device__ inline void control_step(IterState& st, const double* sums,
   for (int i = 0; i < M; ++i) st.coef[i] = 0.0f;
   for (int i = 0; i < m; ++i) st.coef[slot[i]] = (float)c[i];
   float eta = eta_static;
-  if (eta_dynamic) eta = (float)fmin(fmax(-0.2 * log(rms), 0.1), 1.0);
+  if (eta_dynamic && !anderson) eta = (float)fmin(fmax(-0.2 * log(rms), 0.1), 1.0);
   st.eta = eta;
   // Next destination: a free slot while the ring is not full, else the oldest.
   int next = -1;
@@ -741,7 +779,8 @@ struct ControlScratch {
 __device__ inline void control_block(IterState* __restrict__ st_g,
                                      const double* __restrict__ partials, int nblocks, int M,
                                      double inv_count, double tol, int max_iter, float eta_static,
-                                     int eta_dynamic, ControlScratch& cs) {
+                                     int eta_dynamic, int accel, double as1, double as2,
+                                     ControlScratch& cs) {
   {
     const int* src = reinterpret_cast<const int*>(st_g);
     int* dst = reinterpret_cast<int*>(&cs.st);
@@ -775,7 +814,8 @@ __device__ inline void control_block(IterState* __restrict__ st_g,
   }
   __syncthreads();
   if (threadIdx.x == 0)
-    control_step(cs.st, cs.sums, cs.A, M, inv_count, tol, max_iter, eta_static, eta_dynamic);
+    control_step(cs.st, cs.sums, cs.A, M, inv_count, tol, max_iter, eta_static, eta_dynamic,
+                 accel, as1, as2);
   __syncthreads();
   {
     const int* src = reinterpret_cast<const int*>(&cs.st);
@@ -788,13 +828,13 @@ __device__ inline void control_block(IterState* __restrict__ st_g,
 __global__ __launch_bounds__(kCtlThreads) void k_control(
     IterState* __restrict__ st_g, const double* __restrict__ partials, int nblocks, int M,
     double inv_count, double tol, int max_iter, float eta_static, int eta_dynamic,
-    size_t bstride) {
+    int accel, double as1, double as2, size_t bstride) {
   __shared__ ControlScratch cs;
   st_g = member_ptr(st_g, bstride);
   if (st_g->done) return;
   partials = member_ptr(partials, bstride);
   control_block(st_g, partials, nblocks, M, inv_count, tol, max_iter, eta_static, eta_dynamic,
-                cs);
+                accel, as1, as2, cs);
 }
 
 // ---------------------------------------------------------------------------

@@ -199,6 +199,7 @@ double axis_kmax(int n, double dk) {
 
 struct Layout {
   int nx, ny, nz, nv, npair, M, n_atoms, m_tab;
+  GramW gw;   // Gram inner-product weights (1, or 1/rho for modified Anderson)
   size_t N, half;
   double dkx, dky, dkz, beta, dv;
   AxisPlan px, py, pz;
@@ -246,13 +247,22 @@ rism3d_status make_layout(const rism3d_problem* pr, const rism3d_opts* op, Layou
     return fail(RISM3D_E_ARG, "mdiis_eta must be in (0, 2]");
   if (op->check_every < 0 || op->anchor_every < 0)
     return fail(RISM3D_E_ARG, "check_every and anchor_every must be >= 0");
+  if (op->accelerator != RISM3D_MDIIS && op->accelerator != RISM3D_ANDERSON)
+    return fail(RISM3D_E_ARG, "unknown accelerator %d", (int)op->accelerator);
+  if (op->accelerator == RISM3D_ANDERSON &&
+      !(std::isfinite(op->anderson_s1) && std::isfinite(op->anderson_s2)))
+    return fail(RISM3D_E_ARG, "anderson_s1 and anderson_s2 must be finite");
 
   L->nx = pr->nx;
   L->ny = pr->ny;
   L->nz = pr->nz;
   L->nv = pr->n_sites;
   L->npair = (pr->n_sites + 1) / 2;
-  L->M = op->mdiis_depth;
+  // modified Anderson keeps the newest input/output pair and two histories
+  L->M = op->accelerator == RISM3D_ANDERSON ? 3 : op->mdiis_depth;
+  for (int g = 0; g < kMaxSites; ++g)
+    L->gw.w[g] = (op->accelerator == RISM3D_ANDERSON && g < pr->n_sites)
+                     ? (float)(1.0 / pr->site_rho[g]) : 1.0f;
   L->n_atoms = pr->n_atoms;
   L->N = (size_t)pr->nx * pr->ny * pr->nz;
   L->half = (L->N + 1) / 2;
@@ -669,14 +679,15 @@ void launch_fused_l(const Layout& L, void* ws, const rism3d_opts* op, bool first
                          at<float>(ws, L.off_tau), at<float>(ws, L.off_res),
                          at<float>(ws, L.off_tref), at<float>(ws, L.off_rref),
                          at<float>(ws, L.off_dg), L.ny, L.nz, L.nv, L.npair, L.M, kind, order, tw,
-                         at<double>(ws, L.off_part), bt.stride);
+                         at<double>(ws, L.off_part), L.gw, bt.stride);
     }
     if (!control) return;
     TIMED(F_CONTROL, s);
     const double inv_count = 1.0 / ((double)L.N * (double)L.nv);
     hipLaunchKernelGGL(k_control, dim3(1, bt.nb), dim3(kCtlThreads), 0, s, st,
                        at<double>(ws, L.off_part), (int)grid.x, L.M, inv_count, op->tol,
-                       op->max_iter, (float)op->mdiis_eta, op->eta_dynamic, bt.stride);
+                       op->max_iter, (float)op->mdiis_eta, op->eta_dynamic,
+                       (int)op->accelerator, op->anderson_s1, op->anderson_s2, bt.stride);
   }
 }
 
@@ -788,7 +799,8 @@ void launch_iteration(const Layout& L, void* ws, const rism3d_opts* op, float in
 #define RISM_RESID_ARGS                                                                       \
   st, at<void>(ws, L.off_spec), at<float>(ws, L.off_w), at<float>(ws, L.off_tau),             \
       at<float>(ws, L.off_res), at<float>(ws, L.off_tref), at<float>(ws, L.off_rref),         \
-      at<float>(ws, L.off_dg), L.N, L.nv, L.npair, L.M, kind, order, at<double>(ws, L.off_part)
+      at<float>(ws, L.off_dg), L.N, L.nv, L.npair, L.M, kind, order, at<double>(ws, L.off_part), \
+      L.gw
   {
     TIMED(anchor ? F_RESIDUAL64 : F_RESIDUAL32, s);
     const dim3 rg(nblk), rb(kRedThreads);
@@ -803,7 +815,8 @@ void launch_iteration(const Layout& L, void* ws, const rism3d_opts* op, float in
     TIMED(F_CONTROL, s);
     hipLaunchKernelGGL(k_control, dim3(1), dim3(kCtlThreads), 0, s, st, at<double>(ws, L.off_part),
                        (int)nblk, L.M, inv_count, op->tol, op->max_iter, (float)op->mdiis_eta,
-                       op->eta_dynamic, (size_t)0);
+                       op->eta_dynamic, (int)op->accelerator, op->anderson_s1, op->anderson_s2,
+                       (size_t)0);
   }
 }
 
@@ -856,11 +869,18 @@ hipStream_t capture_stream() {
 std::string graph_key(const Layout& L, const void* ws, const rism3d_opts* op, float inv_dkt,
                       int every, Batch bt) {
   char buf[512];
-  snprintf(buf, sizeof(buf), "%p|%zu|%d,%d,%d,%d,%d,%d|%d,%d,%.17g,%d,%.17g,%d,%d|%a|%d|%d,%zu",
+  snprintf(buf, sizeof(buf),
+           "%p|%zu|%d,%d,%d,%d,%d,%d|%d,%d,%.17g,%d,%.17g,%d,%d|%a|%d|%d,%zu|%d,%a,%a,%a",
            ws, L.total, L.nx, L.ny, L.nz, L.nv, L.M, L.m_tab, (int)op->closure, op->pse_order,
            op->tol, op->max_iter, op->mdiis_eta, op->eta_dynamic, every, (double)inv_dkt,
-           g_timer.on ? g_timer.only : -2, bt.nb, bt.stride);
-  return buf;
+           g_timer.on ? g_timer.only : -2, bt.nb, bt.stride, (int)op->accelerator,
+           op->anderson_s1, op->anderson_s2, 0.0);
+  std::string key = buf;
+  for (int g = 0; g < kMaxSites; ++g) {   // Gram weights are kernel arguments too
+    snprintf(buf, sizeof(buf), ",%a", (double)L.gw.w[g]);
+    key += buf;
+  }
+  return key;
 }
 
 void drop_graph(GraphEntry* e) {
@@ -1031,7 +1051,8 @@ bool batchable(const Layout& L) {
 
 bool same_iteration_layout(const Layout& a, const Layout& b) {
   return a.nx == b.nx && a.ny == b.ny && a.nz == b.nz && a.nv == b.nv && a.M == b.M &&
-         a.m_tab == b.m_tab && a.off_out == b.off_out;
+         a.m_tab == b.m_tab && a.off_out == b.off_out &&
+         std::memcmp(a.gw.w, b.gw.w, sizeof(a.gw.w)) == 0;
 }
 
 struct BatchPlan {

@@ -22,6 +22,7 @@ MAX_DEPTH = 16
 
 STATUS = {0: "OK", 1: "E_ARG", 2: "E_DEVICE", 3: "E_NOCONV", 4: "E_NONFINITE", 5: "E_WORKSPACE"}
 CLOSURES = {"kh": 0, "hnc": 1, "pse": 2}
+ACCELERATORS = {"mdiis": 0, "anderson": 1}
 
 
 class RismError(RuntimeError):
@@ -51,6 +52,8 @@ class Opts(ctypes.Structure):
         ("max_iter", ctypes.c_int), ("mdiis_depth", ctypes.c_int),
         ("mdiis_eta", ctypes.c_double), ("eta_dynamic", ctypes.c_int),
         ("check_every", ctypes.c_int), ("anchor_every", ctypes.c_int),
+        ("accelerator", ctypes.c_int), ("anderson_s1", ctypes.c_double),
+        ("anderson_s2", ctypes.c_double),
     ]
 
 
@@ -254,6 +257,10 @@ def make_opts(options, check_every: int = 0, anchor_every: int = 0, **override) 
     o.eta_dynamic = int(bool(override.get("eta_dynamic", options.eta_dynamic)))
     o.check_every = int(check_every)
     o.anchor_every = int(anchor_every)
+    o.accelerator = ACCELERATORS[override.get("accelerator",
+                                              getattr(options, "accelerator", "mdiis"))]
+    o.anderson_s1 = float(override.get("anderson_s1", getattr(options, "anderson_s1", 0.2)))
+    o.anderson_s2 = float(override.get("anderson_s2", getattr(options, "anderson_s2", 0.0)))
     return o
 
 

@@ -79,7 +79,7 @@ def generate(P: Problems, seeds, c_scale: float, log):
 
 
 def train(cfg, X, Y, epochs_max: int, budget_s: float, lr: float, seed: int, clip: float,
-          warmup: int, log):
+          warmup: int, log, init=None):
     """Adam on one solute per step: linear warm-up over `warmup` steps, then
     cosine decay; global-norm clipping; every CHECK steps the mean loss of the
     last CHECK steps is compared with the best so far and a blow-up (not
@@ -87,8 +87,9 @@ def train(cfg, X, Y, epochs_max: int, budget_s: float, lr: float, seed: int, cli
     learning rate."""
     CHECK = 500
     n = X.shape[0]
-    theta = torch.tensor(inputs.unet_init_params(R.unet_layers(cfg), seed, slope=cfg.slope),
-                         device=X.device)
+    if init is None:
+        init = inputs.unet_init_params(R.unet_layers(cfg), seed, slope=cfg.slope)
+    theta = torch.tensor(np.asarray(init, dtype=np.float32), device=X.device)
     m = torch.zeros_like(theta)
     v = torch.zeros_like(theta)
     grad = torch.empty_like(theta)
@@ -203,6 +204,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--c-scale", type=float, default=4.0)
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--init", default=None,
+                    help="continue from the parameters of a weights file (same configuration)")
     ap.add_argument("--out", default="warmstart_unet.npz")
     ap.add_argument("--report", default="warmstart_report.json")
     args = ap.parse_args()
@@ -213,8 +216,15 @@ def main():
     X, Y, its = generate(P, range(TRAIN_SEED0, TRAIN_SEED0 + args.n_train), args.c_scale, log)
     log(f"targets / c_scale: mean {Y.mean().item():.3e} std {Y.std().item():.3e} "
         f"min {Y.min().item():.3e} max {Y.max().item():.3e}")
+    init = None
+    if args.init:
+        with np.load(args.init, allow_pickle=False) as z:
+            init = np.asarray(z["params"], dtype=np.float32)
+            if float(z["c_scale"]) != args.c_scale:
+                raise ValueError("--init weights were trained with another c_scale")
+        log(f"continuing from {args.init}")
     theta, history, step_s = train(cfg, X, Y, args.epochs, args.budget, args.lr, args.seed,
-                                   args.clip, args.warmup, log)
+                                   args.clip, args.warmup, log, init)
     np.savez(args.out, params=theta.cpu().numpy(), levels=cfg.levels, base=cfg.base,
              in_channels=cfg.in_channels, out_channels=cfg.out_channels, slope=cfg.slope,
              c_scale=args.c_scale)
@@ -225,7 +235,7 @@ def main():
                              range(TEST_SEED0, TEST_SEED0 + args.n_test), log)
     report = {"n_train": args.n_train, "train_seeds": [TRAIN_SEED0, TRAIN_SEED0 + args.n_train],
               "test_seeds": [TEST_SEED0, TEST_SEED0 + args.n_test], "c_scale": args.c_scale,
-              "lr": args.lr, "clip": args.clip, "warmup": args.warmup, "step_ms": step_s * 1e3, "data_iterations_mean": float(np.mean(its)),
+              "init": args.init, "lr": args.lr, "clip": args.clip, "warmup": args.warmup, "step_ms": step_s * 1e3, "data_iterations_mean": float(np.mean(its)),
               "history": history, "eval": summary, "eval_rows": rows}
     with open(args.report, "w") as f:
         json.dump(report, f, indent=1)

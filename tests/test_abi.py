@@ -68,6 +68,7 @@ def _opts(R, **kw):
     o = R.Opts()
     o.closure, o.pse_order, o.tol, o.max_iter = 0, 3, 1e-6, 100
     o.mdiis_depth, o.mdiis_eta, o.eta_dynamic, o.check_every, o.anchor_every = 5, 0.7, 0, 0, 0
+    o.accelerator, o.anderson_s1, o.anderson_s2 = 0, 0.2, 0.0
     for k, v in kw.items():
         setattr(o, k, v)
     return o
@@ -97,7 +98,8 @@ def test_bad_problem_is_rejected(R, field, value, msg):
 
 
 @pytest.mark.parametrize("field,value", [("mdiis_depth", 0), ("mdiis_depth", 17), ("tol", 0.0),
-                                         ("closure", 7), ("max_iter", 0), ("mdiis_eta", 0.0)])
+                                         ("closure", 7), ("max_iter", 0), ("mdiis_eta", 0.0),
+                                         ("accelerator", 2)])
 def test_bad_options_are_rejected(R, field, value):
     p, keep = _fake_problem(R)
     assert R.LIB.rism3d_workspace_bytes(ctypes.byref(p), ctypes.byref(_opts(R, **{field: value}))) == 0
@@ -138,3 +140,16 @@ def test_batch_workspace_plan(R):
     assert "batch member 1" in R.last_error()
     assert R.LIB.rism3d_batch_workspace_bytes(0, ctypes.cast(arr, ctypes.c_void_p),
                                               ctypes.byref(_opts(R))) == 0
+
+
+def test_anderson_keeps_three_pairs(R):
+    """Modified Anderson stores the newest pair and two histories whatever
+    mdiis_depth says: its workspace equals the MDIIS workspace at depth 3."""
+    p, keep = _fake_problem(R)
+    wa = R.LIB.rism3d_workspace_bytes(ctypes.byref(p), ctypes.byref(_opts(R, accelerator=1,
+                                                                           mdiis_depth=9)))
+    w3 = R.LIB.rism3d_workspace_bytes(ctypes.byref(p), ctypes.byref(_opts(R, mdiis_depth=3)))
+    assert wa == w3 > 0
+    bad = _opts(R, accelerator=1, anderson_s1=float("nan"))
+    assert R.LIB.rism3d_workspace_bytes(ctypes.byref(p), ctypes.byref(bad)) == 0
+    assert "anderson_s1" in R.last_error()

@@ -120,12 +120,17 @@ CASES = [
     dict(seed=33, saline=False, closure="pse", q=0.5, shape=(96, 20, 32)),
     # the 4000-atom globule's settings (PSE-3, MDIIS depth 10) on a fused grid
     dict(seed=34, saline=False, closure="pse", q=0.5, shape=(64, 32, 32), depth=10),
+    # modified Anderson (s1 0.2, s2 0, b 0.6): generic grid in water, fused grid in
+    # saline (Gram weights 1/rho differ by a factor of ~550 between sites)
+    dict(seed=7, saline=False, closure="kh", q=1.0, shape=(24, 20, 18), accel="anderson"),
+    dict(seed=35, saline=True, closure="kh", q=1.0, shape=(64, 24, 32), accel="anderson"),
 ]
 
 
 def _case_id(c):
     return (f"{c['closure']}-{'saline' if c['saline'] else 'water'}-q{c['q']}-"
-            f"{'x'.join(map(str, c['shape']))}" + (f"-m{c['depth']}" if "depth" in c else ""))
+            f"{'x'.join(map(str, c['shape']))}" + (f"-m{c['depth']}" if "depth" in c else "")
+            + (f"-{c['accel']}" if "accel" in c else ""))
 
 
 def _case_problem(c):
@@ -133,6 +138,9 @@ def _case_problem(c):
                                 saline=c["saline"], closure=c["closure"], charge_scale=c["q"],
                                 mdiis_depth=c.get("depth", 5))
     prob.options.mdiis_eta = c.get("eta", prob.options.mdiis_eta)
+    if c.get("accel") == "anderson":
+        prob.options.accelerator = "anderson"
+        prob.options.mdiis_eta = 0.6
     return prob
 
 
@@ -161,6 +169,17 @@ def test_solve_matches_oracle(R, O, case):
     assert err <= max(G_TOL, 1.5 * stop_err)
     assert abs(sfe - sfe_ref) <= SFE_RTOL * abs(sfe_ref)
     assert np.allclose(sfe_site, site_ref, rtol=SFE_RTOL, atol=SFE_RTOL * abs(sfe_ref))
+    if case.get("accel") == "anderson":
+        # the same accelerator as the oracle's: the RMS after each of the first
+        # iterations (Picard, Picard, then Anderson steps) follows the oracle's
+        # history before FP32 and FP64 trajectories part (late in a solve they
+        # do: the iteration counts differ by up to a quarter)
+        for k in range(1, 9):
+            s.opts.max_iter = k
+            info_k = s.solve(allow_noconv=True)
+            ref_k = at6.rms_history[k - 1]
+            print(f"    iteration {k}: rms {info_k.rms:.6e} oracle {ref_k:.6e}", flush=True)
+            assert abs(info_k.rms - ref_k) <= 1e-4 * ref_k
 
 
 def test_below_the_fp32_transform_floor(R, O):
