@@ -90,6 +90,16 @@ def test_uneven_batch_64_solutes(R):
     assert all(inf.rms < 1e-6 for inf in infos)
 
 
+def test_anderson_batch_equals_single_solves(R):
+    """Modified Anderson in a batch: members in water and in saline (different
+    Gram weights, so different groups) equal their single solves bit for bit."""
+    probs = [inputs.small_problem(26, n_atoms=6, shape=(64, 24, 32), radius=2.5),
+             inputs.small_problem(27, n_atoms=8, shape=(64, 24, 32), radius=2.5),
+             inputs.small_problem(28, n_atoms=6, shape=(64, 24, 32), radius=2.5, saline=True)]
+    opts = R.make_opts(probs[0].options, accelerator="anderson", mdiis_eta=0.6)
+    _compare(R, probs, opts, range(len(probs)))
+
+
 def test_batch_nonconvergence_reports_member(R):
     probs = [inputs.small_problem(31, n_atoms=6, shape=(64, 24, 32), radius=2.5),
              inputs.small_problem(32, n_atoms=6, shape=(64, 24, 32), radius=2.5)]
