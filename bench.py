@@ -283,12 +283,45 @@ def anderson_comparison(R, prob, dp, stream, n: int):
             "accelerator": "modified Anderson (s1 0.2, s2 0, b 0.6)"}
 
 
+def batch_comparison(R, inputs, count: int):
+    """The uneven batch (count solutes of 20-300 atoms in water on 96^3 /
+    128^3 grids at 0.5 A, KH, MDIIS 5, rms 1e-6) in one rism3d_solve_batch
+    call: potentials, solves and SFEs of every member; solves/s = count /
+    wall time (inputs resident on the device)."""
+    import torch
+    probs = inputs.batch_uneven_problems(count=count)
+    chi, dk = inputs.solvent_table("water")
+    dps = [R.DeviceProblem(p, chi, dk) for p in probs]
+    opts = R.make_opts(probs[0].options)
+    ws = R.alloc_workspace(R.rism3d_batch_workspace_bytes(dps, opts))
+    for shape in sorted({dp.shape for dp in dps}):   # tile widths per grid, as elsewhere
+        dp = next(d for d in dps if d.shape == shape)
+        one = R.alloc_workspace(R.rism3d_workspace_bytes(dp, opts))
+        R.rism3d_potential(dp, opts, one)
+        R.rism3d_autotune(dp, opts, one)
+        del one
+    R.rism3d_solve_batch(dps, opts, ws)          # warm-up (graph capture)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos, _ = R.rism3d_solve_batch(dps, opts, ws)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    sizes = [p.grid.nx for p in probs]
+    return {"solves_per_s": count / el, "seconds": el,
+            "iterations_mean": sum(i.iterations for i in infos) / count,
+            "workload": (f"batch_uneven: {count} solutes (seeds 1000..{999 + count}), "
+                         f"{sizes.count(96)} x 96^3 + {sizes.count(128)} x 128^3, water, KH, "
+                         f"MDIIS 5, rms 1e-6, one rism3d_solve_batch call")}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-solutes", type=int, default=64,
+                    help="solutes of the batched-solve leg (0: skip)")
     ap.add_argument("--anderson-steps", type=int, default=2,
                     help="solves of the headline workload with modified Anderson (0: skip)")
     ap.add_argument("--warm-seeds", type=int, default=8,
@@ -423,6 +456,8 @@ def main():
         "kernels_first_warmup_step": kernels,
         "tuning": tuning,
     }
+    if args.batch_solutes > 0:
+        out["batch"] = batch_comparison(R, inputs, args.batch_solutes)
     if args.anderson_steps > 0:
         out["anderson"] = anderson_comparison(R, prob, dp, stream, args.anderson_steps)
     if args.warm_seeds > 0:
