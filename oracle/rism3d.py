@@ -479,6 +479,45 @@ def solve(sys_: System, tol: Optional[float] = None, tau0: Optional[np.ndarray] 
                     res.converged, res.rms_history)
 
 
+def sfe_gradient(problem, g: np.ndarray, atoms=None) -> np.ndarray:
+    """Solvent term of the derivative of the MM/3D-RISM free energy with
+    respect to a solute atom position (section "Hybrid implementation", the
+    derivative of Eq 23):
+
+        d(dmu)/dR_a = sum_g rho_g \int g_g(r) du_g(r)/dR_a dr,
+
+    u_g from Eq 22 (pairs inside the 0.01 A clamp contribute nothing, since
+    the clamped pair term does not depend on R_a there), the integral as the
+    box sum dV sum_n.  g is any distribution [n_v, nz, ny, nx].  Returns
+    [n_atoms, 3] in kcal/(mol A) (or the rows of the listed ``atoms``); the
+    solvation force is its negative."""
+    solute = problem.solute
+    q_v, sig_v, eps_v, rho = problem.solvent.site_arrays()
+    pts = grid_points(problem.grid)
+    dv = problem.grid.spacing ** 3
+    g = np.asarray(g, dtype=np.float64)
+    atoms = range(solute.n_atoms) if atoms is None else list(atoms)
+    out = np.zeros((len(atoms), 3))
+    for row, a in enumerate(atoms):
+        diff = pts - solute.xyz[a]                       # r - R_a
+        dist = np.sqrt(np.sum(diff * diff, axis=-1))
+        live = dist >= D_MIN
+        d = np.where(live, dist, 1.0)
+        weight = np.zeros(dist.shape)                    # sum_g rho_g g_g (du_g/dd) / d
+        for s_ in range(len(q_v)):
+            sig = 0.5 * (solute.sigma[a] + sig_v[s_])
+            eps = math.sqrt(solute.eps[a] * eps_v[s_])
+            sr6 = (sig / d) ** 6
+            # derivative in d of the pair term of Eq 22
+            du_dd = (-COULOMB * solute.q[a] * q_v[s_] / (d * d)
+                     + 4.0 * eps * (-12.0 * sr6 * sr6 + 6.0 * sr6) / d)
+            weight += rho[s_] * g[s_] * du_dd / d
+        weight = np.where(live, weight, 0.0)
+        # du/dR_a = (du/dd) (R_a - r) / d
+        out[row] = -dv * np.sum(weight[..., None] * diff, axis=(0, 1, 2))
+    return out
+
+
 def sfe(sol: Solution):
     """Eq 17 / 18 (and the PSE-n form): k_B T sum_g rho_g dV sum_n Phi.
     Returns (total, per_site) in kcal/mol."""

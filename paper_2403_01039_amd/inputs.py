@@ -307,6 +307,27 @@ def small_problem(seed: int, n_atoms: int = 12, shape=(24, 20, 18), spacing: flo
                    Options(closure=closure, mdiis_depth=mdiis_depth), seed)
 
 
+def synthetic_distribution(problem: Problem, seed: int, exclusion: float = 2.0,
+                           spread: float = 0.3) -> np.ndarray:
+    """A seeded stand-in for a solvent distribution g [n_v, nz, ny, nx] (float32):
+    0 within ``exclusion`` A of any atom centre (the excluded core), elsewhere
+    max(0, 1 + spread * N(0, 1)).  Grid point (ix, iy, iz) sits at
+    centre + ((ix, iy, iz) - (nx, ny, nz) div 2) * spacing."""
+    gr = problem.grid
+    rng = np.random.default_rng(seed)
+    nv = len(problem.solvent.site_names())
+    g = np.maximum(0.0, 1.0 + spread * rng.standard_normal((nv, gr.nz, gr.ny, gr.nx)))
+    axes = [gr.center[i] + (np.arange(n) - n // 2) * gr.spacing
+            for i, n in enumerate((gr.nx, gr.ny, gr.nz))]
+    zz, yy, xx = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
+    core = np.zeros(zz.shape, dtype=bool)
+    for a in range(problem.solute.n_atoms):
+        x, y, z = problem.solute.xyz[a]
+        core |= (xx - x) ** 2 + (yy - y) ** 2 + (zz - z) ** 2 < exclusion ** 2
+    g[:, core] = 0.0
+    return g.astype(np.float32)
+
+
 # ---------------------------------------------------------------------------
 # Solvent susceptibility tables (data files, read-only)
 # ---------------------------------------------------------------------------
