@@ -314,12 +314,45 @@ def batch_comparison(R, inputs, count: int):
                          f"MDIIS 5, rms 1e-6, one rism3d_solve_batch call")}
 
 
+def gradient_leg(R, prob, solver, stream, reps: int):
+    """The solvation free-energy gradient with respect to the 200 atom
+    positions (the solvent term of the derivative of Eq 23) at the solved g of
+    the headline problem: reps calls, kernel time from HIP events on the
+    call's stream."""
+    import torch
+    g = torch.empty(solver.dp.shape, dtype=torch.float32, device=solver.ws.device)
+    solver.potential(stream)
+    solver.solve(g_out=g, stream=stream)
+    solver.sfe_gradient(g, stream)               # warm-up
+    torch.cuda.synchronize()
+    R.timing_reset()
+    R.timing_select("sfe_gradient")
+    R.timing_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        grad = solver.sfe_gradient(g, stream)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    R.timing_enable(False)
+    R.timing_select(None)
+    cnt, ms = R.timing_read()["sfe_gradient"]
+    kernel_s = ms / cnt * 1e-3
+    pairs = prob.solute.n_atoms * prob.grid.n_points
+    return {"ms_per_call": el / reps * 1e3, "kernel_us": kernel_s * 1e6,
+            "atom_point_pairs_per_s": pairs / kernel_s,
+            "max_abs_kcal_mol_A": float(grad.abs().max()),
+            "workload": "d(dmu)/dR for the 200 atoms of solute_200_saline at its solved g "
+                        "(128^3, 5 sites), FP64 pair terms"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--gradient-reps", type=int, default=5,
+                    help="calls of the free-energy gradient leg (0: skip)")
     ap.add_argument("--batch-solutes", type=int, default=64,
                     help="solutes of the batched-solve leg (0: skip)")
     ap.add_argument("--anderson-steps", type=int, default=2,
@@ -456,6 +489,8 @@ def main():
         "kernels_first_warmup_step": kernels,
         "tuning": tuning,
     }
+    if args.gradient_reps > 0:
+        out["sfe_gradient"] = gradient_leg(R, prob, solver, stream, args.gradient_reps)
     if args.batch_solutes > 0:
         out["batch"] = batch_comparison(R, inputs, args.batch_solutes)
     if args.anderson_steps > 0:

@@ -198,6 +198,25 @@ rism3d_status rism3d_thermo(const rism3d_problem* problem, const rism3d_opts* op
                             const void* d_ws, size_t ws_bytes, rism3d_thermo_out* out,
                             hipStream_t stream);
 
+/* Section "Hybrid implementation", the derivative of the MM/3D-RISM free
+ * energy (Eq 23): the solvent term
+ *   d(dmu)/dR_a = sum_g rho_g \int g_g(r) du_g(r)/dR_a dr
+ * for every solute atom a, with u_g the potential of Eq 22 (distances clamped
+ * at 0.01 A, so pairs closer than that add nothing) and the integral taken as
+ * the box sum dV sum_r.  The solvation force on atom a is minus this.
+ *   d_g:    device, float32 [n_sites][nz][ny][nx], any distribution (normally
+ *           the g that rism3d_solve wrote); read only.
+ *   d_grad: device, float64 [n_atoms][3] (x, y, z), kcal/(mol A); written.
+ *           May be NULL when n_atoms is 0.
+ * The workspace must have been prepared by rism3d_potential (it holds the
+ * atoms and their LJ coefficients); the call overwrites the workspace's
+ * Fourier scratch, which no later call reads.  Pair terms and sums are
+ * float64 and the cross-workgroup sum has a fixed order, so the result is
+ * deterministic.  Synchronises the stream (to check the workspace). */
+rism3d_status rism3d_sfe_gradient(const rism3d_problem* problem, const rism3d_opts* opts,
+                                  const float* d_g, void* d_ws, size_t ws_bytes, double* d_grad,
+                                  hipStream_t stream);
+
 /* Copies tau = t - f of the returned iterate (float32 [n_sites][nz][ny][nx]) into
  * d_tau (device); usable as d_tau0 of a later solve (resume / warm start). */
 rism3d_status rism3d_get_tau(const rism3d_problem* problem, const rism3d_opts* opts,

@@ -19,6 +19,7 @@
 #include "common.hpp"
 #include "fft.hpp"
 #include "iterate.hpp"
+#include "forces.hpp"
 #include "fused.hpp"
 #include "setup.hpp"
 #include "unet.hpp"
@@ -61,7 +62,7 @@ enum Family {
   F_UPDATE32, F_UPDATE64, F_FFTX32, F_FFTY32, F_FFTZ32, F_FFTX64, F_FFTY64, F_FFTZ64,
   F_CONTRACT32, F_CONTRACT64, F_RESIDUAL32, F_RESIDUAL64, F_CONTROL, F_UPDFFT32, F_UPDFFT64,
   F_FFTRES32, F_FFTRES64, F_ZCZ32, F_ZCZ64, F_POTENTIAL, F_FTILDE, F_SETUP, F_OUTPUT, F_SFE,
-  F_NET_FWD, F_NET_GRAD, F_HALFSTEP, F_COUNT
+  F_NET_FWD, F_NET_GRAD, F_HALFSTEP, F_SFEGRAD, F_COUNT
 };
 const char* const kFamilyNames[F_COUNT] = {
     "update_closure_f32", "update_closure_f64", "fft_x_f32", "fft_y_f32", "fft_z_f32",
@@ -69,7 +70,8 @@ const char* const kFamilyNames[F_COUNT] = {
     "residual_gram_f64", "mdiis_control", "update_fftx_f32", "update_fftx_f64",
     "fftx_residual_f32", "fftx_residual_f64", "zfft_contract_f32", "zfft_contract_f64",
     "potential", "long_range_spectrum",
-    "setup_tables", "output", "free_energy", "unet_forward", "unet_gradient", "oz_half_step"};
+    "setup_tables", "output", "free_energy", "unet_forward", "unet_gradient", "oz_half_step",
+    "sfe_gradient"};
 
 struct Timer {
   bool on = false;
@@ -1178,6 +1180,18 @@ __global__ void k_tune_state(IterState* st, int M, float eta) {
   st->final_slot = -1;
 }
 
+template <int NV>
+void launch_sfe_grad_nv(const Layout& L, const void* ws, const float* g, double dr,
+                        const SiteConsts& sc, double scale, unsigned nb, double* dst,
+                        hipStream_t s) {
+  const dim3 grid(nb, (unsigned)((L.n_atoms + kGradAtoms - 1) / kGradAtoms));
+  TIMED(F_SFEGRAD, s);
+  hipLaunchKernelGGL(k_sfe_grad<NV>, grid, dim3(kGradThreads), 0, s,
+                     at<double4>(const_cast<void*>(ws), L.off_atoms),
+                     at<double2>(const_cast<void*>(ws), L.off_lj), L.n_atoms, g, L.nx, L.ny, L.N,
+                     dr, sc, dst, scale);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1308,6 +1322,62 @@ rism3d_status rism3d_thermo(const rism3d_problem* pr, const rism3d_opts* op, con
   HIP_TRY(hipStreamSynchronize(s));
   if (g_timer.on) g_timer.harvest();
   fill_thermo(res, L.nv, out);
+  g_error.clear();
+  return RISM3D_OK;
+}
+
+rism3d_status rism3d_sfe_gradient(const rism3d_problem* pr, const rism3d_opts* op, const float* g,
+                                  void* ws, size_t ws_bytes, double* grad, hipStream_t s) {
+  Layout L;
+  rism3d_status st = make_layout(pr, op, &L);
+  if (st != RISM3D_OK) return st;
+  if ((st = check_ws(L, ws, ws_bytes)) != RISM3D_OK) return st;
+  if (!g) return fail(RISM3D_E_ARG, "null g");
+  if (L.n_atoms > 0 && !grad) return fail(RISM3D_E_ARG, "null gradient output");
+  IterState host;
+  HIP_TRY(hipMemcpyAsync(&host, at<IterState>(ws, L.off_state), sizeof(IterState),
+                         hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (host.prepared != kPreparedMagic)
+    return fail(RISM3D_E_WORKSPACE, "workspace not prepared: call rism3d_potential first");
+  if (L.n_atoms == 0) {
+    g_error.clear();
+    return RISM3D_OK;
+  }
+  // One partial row of 3 n_atoms doubles per workgroup column, kept in the
+  // spectrum section (scratch between iterations).  About 2048 workgroups in
+  // all; a single column writes the result directly.
+  const size_t tiles = (L.N + kGradTile - 1) / kGradTile;
+  const size_t chunks = (L.n_atoms + kGradAtoms - 1) / kGradAtoms;
+  size_t nb = std::max<size_t>(1, 2048 / chunks);
+  nb = std::min(nb, tiles);
+  const size_t row = (size_t)L.n_atoms * 3 * sizeof(double);
+  nb = std::min(nb, (size_t)L.npair * L.N * sizeof(double2) / row);
+  if (nb < 1) nb = 1;
+  const SiteConsts sc = site_consts(pr, L.beta);
+  const double scale = L.dv / L.beta;   // k_B T dV
+  double* dst = nb == 1 ? grad : at<double>(ws, L.off_spec);
+  switch (L.nv) {
+    case 1: launch_sfe_grad_nv<1>(L, ws, g, pr->spacing, sc, scale, (unsigned)nb, dst, s); break;
+    case 2: launch_sfe_grad_nv<2>(L, ws, g, pr->spacing, sc, scale, (unsigned)nb, dst, s); break;
+    case 3: launch_sfe_grad_nv<3>(L, ws, g, pr->spacing, sc, scale, (unsigned)nb, dst, s); break;
+    case 4: launch_sfe_grad_nv<4>(L, ws, g, pr->spacing, sc, scale, (unsigned)nb, dst, s); break;
+    case 5: launch_sfe_grad_nv<5>(L, ws, g, pr->spacing, sc, scale, (unsigned)nb, dst, s); break;
+    case 6: launch_sfe_grad_nv<6>(L, ws, g, pr->spacing, sc, scale, (unsigned)nb, dst, s); break;
+    case 7: launch_sfe_grad_nv<7>(L, ws, g, pr->spacing, sc, scale, (unsigned)nb, dst, s); break;
+    default: launch_sfe_grad_nv<8>(L, ws, g, pr->spacing, sc, scale, (unsigned)nb, dst, s); break;
+  }
+  LAUNCH_CHECK();
+  if (nb > 1) {
+    const int n3 = L.n_atoms * 3;
+    hipLaunchKernelGGL(k_sfe_grad_reduce, dim3(blocks_for(n3, 256)), dim3(256), 0, s, dst, (int)nb,
+                       n3, grad);
+    LAUNCH_CHECK();
+  }
+  if (g_timer.on) {
+    HIP_TRY(hipStreamSynchronize(s));
+    g_timer.harvest();
+  }
   g_error.clear();
   return RISM3D_OK;
 }

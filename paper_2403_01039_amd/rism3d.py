@@ -89,6 +89,7 @@ def _load():
         "rism3d_potential": (ctypes.c_int, [P(Problem), P(Opts), vp, sz, st]),
         "rism3d_solve": (ctypes.c_int, [P(Problem), P(Opts), vp, vp, sz, vp, P(Info), st]),
         "rism3d_thermo": (ctypes.c_int, [P(Problem), P(Opts), vp, sz, P(ThermoOut), st]),
+        "rism3d_sfe_gradient": (ctypes.c_int, [P(Problem), P(Opts), vp, vp, sz, vp, st]),
         "rism3d_get_tau": (ctypes.c_int, [P(Problem), P(Opts), vp, sz, vp, st]),
         "rism3d_map": (ctypes.c_int, [P(Problem), P(Opts), vp, vp, sz, vp,
                                       P(ctypes.c_double), st]),
@@ -139,6 +140,7 @@ def _load():
 
 LIB = _load()
 EXPORTED = ("rism3d_workspace_bytes", "rism3d_potential", "rism3d_solve", "rism3d_thermo",
+            "rism3d_sfe_gradient",
             "rism3d_get_tau", "rism3d_map", "rism3d_get_potential",
             "rism3d_transform_workspace_bytes", "rism3d_transform", "rism3d_timing_enable",
             "rism3d_timing_reset", "rism3d_timing_read", "rism3d_use_graphs",
@@ -294,6 +296,21 @@ def rism3d_thermo(dp, opts, ws, stream=None):
                              ws.numel() * ws.element_size(), ctypes.byref(out), _stream(stream)))
     nv = dp.struct.n_sites
     return out.sfe, np.array(out.sfe_site[:nv])
+
+
+def rism3d_sfe_gradient(dp, opts, ws, g: torch.Tensor, out: Optional[torch.Tensor] = None,
+                        stream=None) -> torch.Tensor:
+    """d(dmu)/dR_a [n_atoms, 3] (float64, kcal/(mol A)) for the distribution g."""
+    n = dp.struct.n_atoms
+    gc = g.contiguous()
+    if gc.dtype != torch.float32 or tuple(gc.shape) != tuple(dp.shape):
+        raise ValueError(f"g must be float32 {tuple(dp.shape)}")
+    if out is None:
+        out = torch.empty((n, 3), dtype=torch.float64, device=ws.device)
+    _check(LIB.rism3d_sfe_gradient(ctypes.byref(dp.struct), ctypes.byref(opts), _ptr(gc),
+                                   _ptr(ws), ws.numel() * ws.element_size(),
+                                   _ptr(out) if n > 0 else None, _stream(stream)))
+    return out
 
 
 def rism3d_get_tau(dp, opts, ws, tau_out, stream=None):
@@ -539,6 +556,9 @@ class Solver:
 
     def thermo(self, stream=None):
         return rism3d_thermo(self.dp, self.opts, self.ws, stream)
+
+    def sfe_gradient(self, g: torch.Tensor, stream=None) -> torch.Tensor:
+        return rism3d_sfe_gradient(self.dp, self.opts, self.ws, g, stream=stream)
 
     def tau(self) -> torch.Tensor:
         t = torch.empty(self.dp.shape, dtype=torch.float32, device=self.ws.device)
