@@ -274,6 +274,38 @@ def solve_solvent(solvent, grid: Optional[RadialGrid] = None, closure_kind: str 
                          closure_kind, drism, solvent.dielectric if drism else None, smear)
 
 
+def bulk_pressure(solvent, res: SolventResult) -> float:
+    """Eq 20, the pressure of the bulk solvent in kcal/(mol A^3):
+        P = sum_G rho_G (n_G + 1) / (2 beta)
+            - (2 pi / beta) sum_{g,l} rho_g rho_l \int_0^inf c_gl(r) r^2 dr,
+    G over species (molecular density rho_G, n_G sites), g and l over sites,
+    c the full direct correlation of the 1D solution.  The radial integral is
+    the sum dr sum_i c(r_i) r_i^2 over the grid (the end point r = 0 adds
+    nothing).  The Coulomb tails -beta C q_g q_l (1 - e^{-r})/r of c cancel in
+    the double sum of an electroneutral solvent, sum_g rho_g q_g = 0."""
+    beta = beta_of(solvent.temperature)
+    rho = solvent.site_arrays()[3]
+    r = res.grid.r
+    integral = res.grid.dr * np.sum(res.c * r * r, axis=-1)
+    ideal = sum(sp.density * (len(sp.sites) + 1) for sp in solvent.species) / (2.0 * beta)
+    return float(ideal - (2.0 * math.pi / beta) * np.einsum("a,b,ab->", rho, rho, integral))
+
+
+def compressibility(solvent, res: SolventResult) -> float:
+    """Isothermal compressibility chi_T of the solvent (the input of Eq 19), in
+    A^3 mol / kcal, from the k -> 0 limit of the site-site structure of its
+    first species G: rho_G k_B T chi_T = S(0), with S(k) the mean over the
+    site pairs of G of chi_gl(k) = w_gl + rho h_gl, extrapolated to k = 0 as
+    (4 S(k_1) - S(k_2)) / 3 (S is even in k).  For one species this is the
+    compressibility route 1 + rho h~(0); with dissolved ions it is read as
+    the compressibility of the first (solvent) species."""
+    beta = beta_of(solvent.temperature)
+    n = len(solvent.species[0].sites)
+    s1 = float(np.mean(res.chi[:n, :n, 0]))
+    s2 = float(np.mean(res.chi[:n, :n, 1]))
+    return ((4.0 * s1 - s2) / 3.0) * beta / solvent.species[0].density
+
+
 def charge_structure(solvent, chi: np.ndarray) -> np.ndarray:
     """S_qq(k) = sum_ab q_a rho_b chi_ab(k) q_b (chi_ab = w_ab + rho_a h_ab)."""
     q, _, _, rho = solvent.site_arrays()

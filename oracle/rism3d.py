@@ -518,6 +518,22 @@ def sfe_gradient(problem, g: np.ndarray, atoms=None) -> np.ndarray:
     return out
 
 
+def pmv(sol: Solution, compressibility: float):
+    """Eq 19: the partial molar volume k_B T chi_T (1 - sum_g rho_g \int c_g dr)
+    in A^3, with c = g - 1 - t (full c) and the integral as the box sum
+    dV sum_n.  Returns (pmv, per-site rho_g \int c_g dr)."""
+    sys_ = sol.system
+    rho = sys_.problem.solvent.site_arrays()[3]
+    rho_int_c = np.array([rho[g] * sys_.dv * float(np.sum(sol.c[g]))
+                          for g in range(sys_.n_sites)])
+    return compressibility / sys_.beta * (1.0 - float(np.sum(rho_int_c))), rho_int_c
+
+
+def pressure_correction(pmv_value: float, pressure: float) -> float:
+    """Eq 21: the PC term -P V of the free energy, kcal/mol (P in kcal/(mol A^3))."""
+    return -pressure * pmv_value
+
+
 def sfe(sol: Solution):
     """Eq 17 / 18 (and the PSE-n form): k_B T sum_g rho_g dV sum_n Phi.
     Returns (total, per_site) in kcal/mol."""

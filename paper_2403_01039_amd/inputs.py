@@ -346,6 +346,24 @@ def solvent_table(name: str):
         return np.array(z["chi"]), float(z["dk"])
 
 
+def solvent_bulk(name: str):
+    """(compressibility chi_T [A^3 mol/kcal], pressure [kcal/(mol A^3)]) of a
+    stored solvent, from the same 1D solve as its table."""
+    import json
+    with open(_os.path.join(SOLVENT_TABLE_DIR, f"{name}_bulk.json")) as f:
+        b = json.load(f)
+    return float(b["compressibility"]), float(b["pressure"])
+
+
+def solvent_name(solvent: Solvent) -> str:
+    names = solvent.site_names()
+    if names == water_solvent().site_names():
+        return "water"
+    if names == saline_solvent().site_names():
+        return "saline"
+    raise KeyError(f"no stored solvent with sites {names}")
+
+
 def solvent_table_for(solvent: Solvent):
     """The stored table whose site list matches ``solvent``."""
     names = solvent.site_names()
