@@ -388,7 +388,8 @@ def main():
         del src, dst
     prob = inputs.solute_200_problem(1, saline=True)
     chi, dk = inputs.solvent_table_for(prob.solvent)
-    dp = R.DeviceProblem(prob, chi, dk, device=dev)
+    dp = R.DeviceProblem(prob, chi, dk, device=dev,
+                         bulk=inputs.solvent_bulk(inputs.solvent_name(prob.solvent)))
     opts = R.make_opts(prob.options)
     solver = R.Solver(dp, opts)
     stream = torch.cuda.current_stream(dev)
@@ -489,6 +490,9 @@ def main():
         "kernels_first_warmup_step": kernels,
         "tuning": tuning,
     }
+    th = solver.thermo_all(stream)   # the last timed solve's thermodynamics
+    out["thermo"] = {"sfe_kcal_mol": th["sfe"], "pmv_A3": th["pmv"], "pc_kcal_mol": th["pc"],
+                     "sfe_pc_kcal_mol": th["sfe_pc"], "rho_int_c_total": th["rho_int_c_total"]}
     if args.gradient_reps > 0:
         out["sfe_gradient"] = gradient_leg(R, prob, solver, stream, args.gradient_reps)
     if args.batch_solutes > 0:

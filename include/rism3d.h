@@ -92,6 +92,8 @@ typedef struct {
   int nx, ny, nz;
   double spacing;
   double center[3];
+  double compressibility;  /* chi_T of the bulk solvent (Eq 19), A^3 mol/kcal; 0: unknown */
+  double pressure;         /* bulk solvent pressure (Eq 20), kcal/(mol A^3) */
 } rism3d_problem;
 
 /* Solver options (Eq 40-41 and the closure choice).
@@ -134,6 +136,11 @@ typedef struct {
 typedef struct {
   double sfe;                         /* kcal/mol, Eq 17 / Eq 18 / PSE-n */
   double sfe_site[RISM3D_MAX_SITES];  /* per-site contributions */
+  double rho_int_c[RISM3D_MAX_SITES]; /* rho_g \int c_g(r) dr (box sum, full c), per site */
+  double rho_int_c_total;             /* their sum */
+  double pmv;     /* Eq 19: k_B T chi_T (1 - rho_int_c_total), A^3; NaN if compressibility is 0 */
+  double pc;      /* Eq 21: -pressure * pmv, kcal/mol (NaN likewise) */
+  double sfe_pc;  /* sfe + pc */
 } rism3d_thermo_out;
 
 /* Bytes of device workspace needed for this problem and options. Returns 0 on
@@ -193,7 +200,10 @@ rism3d_status rism3d_solve_batch(int n, const rism3d_problem* problems, const ri
 
 /* Eq 17 (HNC), Eq 18 (KH) and the PSE-n form: the solvation free energy of the
  * iterate rism3d_solve returned, as k_B T sum_g rho_g dV sum_r Phi_g(r) with
- * h = g - 1 and c = g - 1 - t, accumulated in float64.  Writes out (host). */
+ * h = g - 1 and c = g - 1 - t, accumulated in float64; in the same pass the
+ * integrals rho_g dV sum_r c_g(r) of Eq 19.  From them and the problem's bulk
+ * compressibility and pressure: the partial molar volume (Eq 19) and the PC
+ * term -P V (Eq 21).  Writes out (host). */
 rism3d_status rism3d_thermo(const rism3d_problem* problem, const rism3d_opts* opts,
                             const void* d_ws, size_t ws_bytes, rism3d_thermo_out* out,
                             hipStream_t stream);

@@ -861,13 +861,14 @@ __global__ __launch_bounds__(kRedThreads) void k_sfe_partial(
     const IterState* __restrict__ st, const float* __restrict__ tau_hist,
     const float* __restrict__ w, const float* __restrict__ phi_lr, size_t N, int nv, int kind,
     int order, SiteConsts sc, double* __restrict__ partials) {
+  // partials[block][2 nv]: the free-energy density sums, then the sums of c
   __shared__ double red[kRedThreads / 64];
   const int slot = st->final_slot;
   if (slot < 0) return;
   double inv_fact = 1.0;
   for (int i = 2; i <= order + 1; ++i) inv_fact /= (double)i;
   for (int g = 0; g < nv; ++g) {
-    double acc = 0.0;
+    double acc = 0.0, acc_c = 0.0;
     const float* tau = tau_hist + ((size_t)slot * nv + g) * N;
     const float* wg = w + (size_t)g * N;
     for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
@@ -882,23 +883,36 @@ __global__ __launch_bounds__(kRedThreads) void k_sfe_partial(
       else if (kind == RISM3D_KH) phi += (h < 0.0) ? 0.5 * h * h : 0.0;
       else phi += 0.5 * h * h - ((h > 0.0) ? pow(d, (double)(order + 1)) * inv_fact : 0.0);
       acc += phi;
+      acc_c += c;
     }
     const double s = block_sum(acc, red);
-    if (threadIdx.x == 0) partials[(size_t)blockIdx.x * nv + g] = s;
+    const double sc_sum = block_sum(acc_c, red);
+    if (threadIdx.x == 0) {
+      partials[(size_t)blockIdx.x * 2 * nv + g] = s;
+      partials[(size_t)blockIdx.x * 2 * nv + nv + g] = sc_sum;
+    }
   }
 }
 
+// out[g] = k_B T rho_g dV sum Phi_g (Eq 17/18), out[kMaxSites] their total,
+// out[kMaxSites + 1 + g] = rho_g dV sum c_g (the integral of Eq 19).
 __global__ __launch_bounds__(kRedThreads) void k_sfe_reduce(const double* __restrict__ partials,
                                                             int nblocks, int nv, double scale,
-                                                            SiteConsts sc, double* __restrict__ out) {
+                                                            double dv, SiteConsts sc,
+                                                            double* __restrict__ out) {
   __shared__ double red[kRedThreads / 64];
   double total = 0.0;
   for (int g = 0; g < nv; ++g) {
-    double v = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) v += partials[(size_t)b * nv + g];
+    double v = 0.0, vc = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+      v += partials[(size_t)b * 2 * nv + g];
+      vc += partials[(size_t)b * 2 * nv + nv + g];
+    }
     const double s = block_sum(v, red);
+    const double s_c = block_sum(vc, red);
     if (threadIdx.x == 0) {
       out[g] = s * sc.rho[g] * scale;
+      out[kMaxSites + 1 + g] = s_c * sc.rho[g] * dv;
       total += out[g];
     }
   }

@@ -211,6 +211,9 @@ struct Layout {
 };
 
 constexpr int kDefaultCheckEvery = 8;
+// thermodynamic results left in the workspace by launch_sfe: per-site free
+// energies, their total, per-site rho_g \int c_g
+constexpr int kOutDoubles = 2 * kMaxSites + 1;
 constexpr int kDefaultAnchorEvery = 16;
 
 rism3d_status make_layout(const rism3d_problem* pr, const rism3d_opts* op, Layout* L) {
@@ -230,6 +233,9 @@ rism3d_status make_layout(const rism3d_problem* pr, const rism3d_opts* op, Layou
     return fail(RISM3D_E_ARG, "invalid susceptibility table (n_k, dk, chi)");
   if (!(pr->temperature > 0.0)) return fail(RISM3D_E_ARG, "temperature must be > 0");
   if (!(pr->spacing > 0.0)) return fail(RISM3D_E_ARG, "spacing must be > 0");
+  if (!(pr->compressibility >= 0.0) || !std::isfinite(pr->compressibility) ||
+      !std::isfinite(pr->pressure))
+    return fail(RISM3D_E_ARG, "compressibility must be finite and >= 0, pressure finite");
   if (!plan_axis(pr->nx, &L->px) || !plan_axis(pr->ny, &L->py) || !plan_axis(pr->nz, &L->pz) ||
       (pr->nx | pr->ny | pr->nz) & 1)
     return fail(RISM3D_E_ARG,
@@ -301,7 +307,7 @@ rism3d_status make_layout(const rism3d_problem* pr, const rism3d_opts* op, Layou
   L->off_rref = take(nv * N * sizeof(float));
   L->off_dg = take(nv * N * sizeof(float));
   L->off_spec = take((size_t)L->npair * N * sizeof(double2));   // float2 in the bulk iterations
-  const size_t part_q = (size_t)((M + 1) > nv ? (M + 1) : nv);
+  const size_t part_q = (size_t)((M + 1) > 2 * nv ? (M + 1) : 2 * nv);
   size_t part_blocks = kRedBlocks;
   if (fixed_fft_size(pr->nx)) {   // one partial row per workgroup of the fused residual
     // (the narrowest variant: the FP64 tile, or 8 rows for a tuned FP32 one)
@@ -319,7 +325,7 @@ rism3d_status make_layout(const rism3d_problem* pr, const rism3d_opts* op, Layou
     L->off_tw32[a] = take(2 * (size_t)dims[a] * sizeof(float2));
     L->off_tw64[a] = take(2 * (size_t)dims[a] * sizeof(double2));
   }
-  L->off_out = take((kMaxSites + 1) * sizeof(double));
+  L->off_out = take(kOutDoubles * sizeof(double));
   // Solute-size dependent regions last: every offset above depends only on the
   // grid, the sites, the MDIIS depth and the table length, so solves of
   // different solutes on one grid share the offsets the iteration reads.
@@ -1013,13 +1019,28 @@ void launch_sfe(const rism3d_problem* pr, const rism3d_opts* op, const Layout& L
   }
   const double scale = L.dv / L.beta;   // k_B T dV
   hipLaunchKernelGGL(k_sfe_reduce, dim3(1), dim3(kRedThreads), 0, s, at<double>(ws, L.off_part),
-                     (int)nblk, L.nv, scale, sc, at<double>(ws, L.off_out));
+                     (int)nblk, L.nv, scale, L.dv, sc, at<double>(ws, L.off_out));
 }
 
-void fill_thermo(const double* res, int nv, rism3d_thermo_out* out) {
+// Host finish of the thermodynamics: Eq 19 (PMV) and Eq 21 (PC term) from the
+// kernels' rho_g \int c_g and the bulk solvent's chi_T and pressure.
+void fill_thermo(const double* res, const rism3d_problem* pr, rism3d_thermo_out* out) {
   memset(out, 0, sizeof(*out));
   out->sfe = res[kMaxSites];
-  for (int g = 0; g < nv; ++g) out->sfe_site[g] = res[g];
+  double sum_c = 0.0;
+  for (int g = 0; g < pr->n_sites; ++g) {
+    out->sfe_site[g] = res[g];
+    out->rho_int_c[g] = res[kMaxSites + 1 + g];
+    sum_c += out->rho_int_c[g];
+  }
+  out->rho_int_c_total = sum_c;
+  if (pr->compressibility > 0.0) {
+    out->pmv = kBoltzmann * pr->temperature * pr->compressibility * (1.0 - sum_c);
+    out->pc = -pr->pressure * out->pmv;
+  } else {
+    out->pmv = out->pc = std::nan("");
+  }
+  out->sfe_pc = out->sfe + out->pc;
 }
 
 // ---------------------------------------------------------------------------
@@ -1317,11 +1338,11 @@ rism3d_status rism3d_thermo(const rism3d_problem* pr, const rism3d_opts* op, con
     return fail(RISM3D_E_WORKSPACE, "no solution in the workspace: call rism3d_solve first");
   launch_sfe(pr, op, L, ws, s);
   LAUNCH_CHECK();
-  double res[kMaxSites + 1];
+  double res[kOutDoubles];
   HIP_TRY(hipMemcpyAsync(res, at<double>(ws, L.off_out), sizeof(res), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   if (g_timer.on) g_timer.harvest();
-  fill_thermo(res, L.nv, out);
+  fill_thermo(res, pr, out);
   g_error.clear();
   return RISM3D_OK;
 }
@@ -1493,7 +1514,7 @@ rism3d_status rism3d_solve_batch(int n, const rism3d_problem* prs, const rism3d_
   // outputs, SFE and per-member status
   rism3d_status worst = RISM3D_OK;
   int worst_member = -1;
-  std::vector<double> sfe((size_t)n * (kMaxSites + 1), 0.0);
+  std::vector<double> sfe((size_t)n * kOutDoubles, 0.0);
   for (const BatchGroup& g : plan.groups)
     for (size_t m = 0; m < g.members.size(); ++m) {
       const int i = g.members[m];
@@ -1508,8 +1529,8 @@ rism3d_status rism3d_solve_batch(int n, const rism3d_problem* prs, const rism3d_
                            (int)op->closure, order_of(op), g_out[i], (float*)nullptr);
       if (thermo && h.final_slot >= 0) {
         launch_sfe(&prs[i], op, L, w, s);
-        HIP_TRY(hipMemcpyAsync(&sfe[(size_t)i * (kMaxSites + 1)], at<double>(w, L.off_out),
-                               (kMaxSites + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&sfe[(size_t)i * kOutDoubles], at<double>(w, L.off_out),
+                               kOutDoubles * sizeof(double), hipMemcpyDeviceToHost, s));
       }
       LAUNCH_CHECK();
       rism3d_status ms = RISM3D_OK;
@@ -1530,8 +1551,7 @@ rism3d_status rism3d_solve_batch(int n, const rism3d_problem* prs, const rism3d_
   if (g_timer.on) g_timer.harvest();
   if (thermo)
     for (int i = 0; i < n; ++i) {
-      if (host[i].final_slot >= 0) fill_thermo(&sfe[(size_t)i * (kMaxSites + 1)], prs[i].n_sites,
-                                               &thermo[i]);
+      if (host[i].final_slot >= 0) fill_thermo(&sfe[(size_t)i * kOutDoubles], &prs[i], &thermo[i]);
       else memset(&thermo[i], 0, sizeof(thermo[i]));
     }
   if (worst != RISM3D_OK)

@@ -43,6 +43,7 @@ class Problem(ctypes.Structure):
         ("temperature", ctypes.c_double),
         ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
         ("spacing", ctypes.c_double), ("center", ctypes.c_double * 3),
+        ("compressibility", ctypes.c_double), ("pressure", ctypes.c_double),
     ]
 
 
@@ -63,7 +64,9 @@ class Info(ctypes.Structure):
 
 
 class ThermoOut(ctypes.Structure):
-    _fields_ = [("sfe", ctypes.c_double), ("sfe_site", ctypes.c_double * MAX_SITES)]
+    _fields_ = [("sfe", ctypes.c_double), ("sfe_site", ctypes.c_double * MAX_SITES),
+                ("rho_int_c", ctypes.c_double * MAX_SITES), ("rho_int_c_total", ctypes.c_double),
+                ("pmv", ctypes.c_double), ("pc", ctypes.c_double), ("sfe_pc", ctypes.c_double)]
 
 
 class Tuning(ctypes.Structure):
@@ -216,7 +219,9 @@ class DeviceProblem:
     """The problem statement of ``include/rism3d.h`` with its large arrays on
     the device (float64 torch tensors) and the per-site arrays on the host."""
 
-    def __init__(self, problem, chi: np.ndarray, dk: float, device="cuda"):
+    def __init__(self, problem, chi: np.ndarray, dk: float, device="cuda", bulk=None):
+        """bulk: (compressibility [A^3 mol/kcal], pressure [kcal/(mol A^3)]) of the
+        solvent, for the PMV and PC term of rism3d_thermo (None: not computed)."""
         sol = problem.solute
         dev = torch.device(device)
         f64 = torch.float64
@@ -245,6 +250,8 @@ class DeviceProblem:
         s.nx, s.ny, s.nz = g.nx, g.ny, g.nz
         s.spacing = float(g.spacing)
         s.center[:] = [float(c) for c in g.center]
+        if bulk is not None:
+            s.compressibility, s.pressure = float(bulk[0]), float(bulk[1])
         self.struct = s
 
 
@@ -311,6 +318,18 @@ def rism3d_sfe_gradient(dp, opts, ws, g: torch.Tensor, out: Optional[torch.Tenso
                                    _ptr(ws), ws.numel() * ws.element_size(),
                                    _ptr(out) if n > 0 else None, _stream(stream)))
     return out
+
+
+def rism3d_thermo_all(dp, opts, ws, stream=None) -> dict:
+    """Every field of rism3d_thermo_out: SFE (total, per site), rho_g \int c_g,
+    PMV (Eq 19), PC term (Eq 21) and SFE + PC."""
+    out = ThermoOut()
+    _check(LIB.rism3d_thermo(ctypes.byref(dp.struct), ctypes.byref(opts), _ptr(ws),
+                             ws.numel() * ws.element_size(), ctypes.byref(out), _stream(stream)))
+    nv = dp.struct.n_sites
+    return {"sfe": out.sfe, "sfe_site": np.array(out.sfe_site[:nv]),
+            "rho_int_c": np.array(out.rho_int_c[:nv]), "rho_int_c_total": out.rho_int_c_total,
+            "pmv": out.pmv, "pc": out.pc, "sfe_pc": out.sfe_pc}
 
 
 def rism3d_get_tau(dp, opts, ws, tau_out, stream=None):
@@ -556,6 +575,9 @@ class Solver:
 
     def thermo(self, stream=None):
         return rism3d_thermo(self.dp, self.opts, self.ws, stream)
+
+    def thermo_all(self, stream=None) -> dict:
+        return rism3d_thermo_all(self.dp, self.opts, self.ws, stream)
 
     def sfe_gradient(self, g: torch.Tensor, stream=None) -> torch.Tensor:
         return rism3d_sfe_gradient(self.dp, self.opts, self.ws, g, stream=stream)

@@ -153,3 +153,16 @@ def test_anderson_keeps_three_pairs(R):
     bad = _opts(R, accelerator=1, anderson_s1=float("nan"))
     assert R.LIB.rism3d_workspace_bytes(ctypes.byref(p), ctypes.byref(bad)) == 0
     assert "anderson_s1" in R.last_error()
+
+
+def test_bulk_solvent_values_are_checked(R):
+    """A negative or non-finite compressibility, or a non-finite pressure, is
+    refused before any device work."""
+    import math
+    p, keep = _fake_problem(R)
+    o = _opts(R)
+    assert R.LIB.rism3d_workspace_bytes(ctypes.byref(p), ctypes.byref(o)) > 0
+    for chi_t, pres in ((-1.0, 0.1), (math.nan, 0.1), (3.2, math.inf)):
+        p.compressibility, p.pressure = chi_t, pres
+        assert R.LIB.rism3d_workspace_bytes(ctypes.byref(p), ctypes.byref(o)) == 0
+        assert "compressibility" in R.last_error()
