@@ -28,14 +28,15 @@ def O():
 CASES = [
     dict(seed=7, shape=(24, 20, 18), saline=False, closure="kh"),
     dict(seed=35, shape=(64, 24, 32), saline=True, closure="kh"),
-    dict(seed=9, shape=(24, 20, 18), saline=False, closure="hnc", q=0.3, eta=0.4),
-    dict(seed=10, shape=(24, 20, 18), saline=False, closure="pse", q=0.5),
+    dict(seed=9, shape=(24, 20, 18), saline=False, closure="hnc", q=0.3, eta=0.4, n=8),
+    dict(seed=10, shape=(24, 20, 18), saline=False, closure="pse", q=0.5, n=8),
 ]
 
 
 @pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c['closure']}_{c['shape']}")
 def test_pmv_and_pc_match_oracle(R, O, case):
-    prob = inputs.small_problem(case["seed"], n_atoms=6, shape=case["shape"], radius=2.5,
+    prob = inputs.small_problem(case["seed"], n_atoms=case.get("n", 6), shape=case["shape"],
+                                radius=2.5,
                                 saline=case["saline"], closure=case["closure"],
                                 charge_scale=case.get("q", 1.0))
     name = inputs.solvent_name(prob.solvent)
