@@ -256,6 +256,17 @@ def globule_4000_problem(seed: int = 2, n: int = 256, spacing: float = 0.4,
                    Options(closure="pse", pse_order=3, mdiis_depth=10), seed)
 
 
+def globule_12877_problem(seed: int = 3, n: int = 512, spacing: float = 0.5) -> Problem:
+    """Stand-in at the paper's demonstration scale (12877 atoms on 512^3 over a
+    256 A box): a globule at the 4000-atom globule's packing (semi-axes scaled
+    by (12877/4000)^(1/3)), net charge +13, in water + 0.1 M NaCl (5 sites),
+    KH, MDIIS 5."""
+    f = (12877 / 4000.0) ** (1.0 / 3.0)
+    sol = random_solute(seed, 12877, (22.0 * f, 17.6 * f, 15.4 * f), net_charge=13.0)
+    return Problem("globule_12877", sol, saline_solvent(), Grid(n, n, n, spacing),
+                   Options(closure="kh", mdiis_depth=5), seed)
+
+
 BATCH_GRID_CHOICES = (64, 96, 128)
 
 

@@ -300,6 +300,56 @@ def test_globule_4000_at_256(R, O):
     assert np.isfinite(sfe)
 
 
+def test_globule_12877_at_512(R, O):
+    """The paper-scale stand-in: 12877 atoms (net +13) in water + 0.1 M NaCl on
+    512^3 at 0.5 A, one GPU.  The potential at 2000 sampled points against the
+    oracle's pair sums, a KH solve with modified Anderson (the paper's GPU
+    accelerator) through the 512-point transforms, the returned tau's residual
+    under one FP64 evaluation of the map, and finite SFE and PMV.  FP32
+    storage of tau (|tau| reaches ~1.6e3 in the core, where increments below
+    its 1e-4 spacing are lost) floors this solve's residual near rms 6.5e-6,
+    so it runs to rms 1e-5."""
+    import time
+    prob = inputs.globule_12877_problem()
+    print("globule_12877 512^3, 5 sites", flush=True)
+    chi, dk = inputs.solvent_table_for(prob.solvent)
+    dp = R.DeviceProblem(prob, chi, dk, bulk=inputs.solvent_bulk("saline"))
+    s = R.Solver(dp, R.make_opts(prob.options, accelerator="anderson", mdiis_eta=0.6,
+                                 tol=1e-5, max_iter=1500))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.potential()
+    torch.cuda.synchronize()
+    t_pot = time.perf_counter() - t0
+    w, phi = s.fields()
+    rng = np.random.default_rng(4)
+    idx = rng.choice(prob.grid.n_points, 2000, replace=False)
+    pts = O.grid_points(prob.grid).reshape(-1, 3)[idx]
+    u, phi_ref = O.potential_at(prob.solute, prob.solvent, pts)
+    beta = O.beta_of(prob.solvent.temperature)
+    q_v = prob.solvent.site_arrays()[0]
+    w_ref = np.minimum(beta * u, O.BETA_U_CAP) - beta * O.COULOMB * q_v[:, None] * phi_ref[None]
+    w_s = w.reshape(5, -1)[:, torch.as_tensor(idx, device="cuda")].cpu().numpy()
+    del w, phi
+    rel = np.abs(w_s - w_ref) / np.maximum(1.0, np.abs(w_ref))
+    soft = w_ref < 5.0
+    assert rel[soft].max() < 2e-5 and rel[~soft].max() < 1e-3
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = s.solve()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    th = s.thermo_all()
+    res, rms = s.map(s.tau())
+    del res
+    print(f"  potential {t_pot:.2f} s; Anderson: {info.iterations} iterations, rms {info.rms:.2e}, "
+          f"{el:.2f} s ({el / info.iterations * 1e3:.1f} ms each); FP64 map rms {rms:.2e}; "
+          f"sfe {th['sfe']:.1f} kcal/mol, pmv {th['pmv']:.0f} A^3", flush=True)
+    assert info.rms < 1e-5 and info.status == 0
+    assert rms < 2e-5
+    assert np.isfinite(th["sfe"]) and th["pmv"] > 0.0
+
+
 def test_empty_solute_is_bulk(R):
     """No solute atoms: u = 0, so g = 1, h = c = 0 is the fixed point (one map)."""
     prob = inputs.small_problem(1, n_atoms=3, shape=(16, 16, 16))
