@@ -68,7 +68,9 @@ __global__ __launch_bounds__(kPotThreads) void k_potential(
         const double d = sqrt(dx * dx + dy * dy + dz * dz);
         const double dc = fmax(d, kDMin);
         const double inv = 1.0 / dc;
-        const double e = exp(-d);
+        // beyond 38 A, e^{-d} < 2^-54: 1 - e^{-d} rounds to 1 and e^{-d}/d adds
+        // below FP64 resolution, so the exponential is skipped there
+        const double e = d < 38.0 ? exp(-d) : 0.0;
         // (1 - e^{-d})/d with screening length 1 A; expm1 only where 1 - e^{-d} cancels
         const double lr = (d < 0.5) ? ((d > 1.0e-300) ? -expm1(-d) / d : 1.0) : (1.0 - e) / d;
         const double sr = (d >= kDMin) ? e * inv : 1.0 / kDMin - lr;
