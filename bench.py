@@ -36,8 +36,8 @@ def kernel_bytes(nv: int, N: int, M: int, m_avg: float, fam: str) -> float:
     P = (nv + 1) // 2
     if fam == "update_closure_f32":   # read m tau_i, m R_i, w, tau_ref; write tau, dg; write spectra
         return nv * N * 4 * (2 * m_avg + 4) + 8 * P * N
-    if fam == "update_closure_f64":   # read m tau_i, m R_i, w; write tau; write FP64 spectra
-        return nv * N * 4 * (2 * m_avg + 2) + 16 * P * N
+    if fam == "update_closure_f64":   # read m tau_i, m R_i, w, tau_ref; write tau; FP64 spectra
+        return nv * N * 4 * (2 * m_avg + 3) + 16 * P * N
     if fam.startswith("fft_") and fam.endswith("_f32") or fam in ("contract_f32",
                                                                    "zfft_contract_f32"):
         return 16 * P * N
@@ -47,15 +47,16 @@ def kernel_bytes(nv: int, N: int, M: int, m_avg: float, fam: str) -> float:
     if fam == "update_fftx_f32":      # update + closure, spectra written once after the x pass
         return nv * N * 4 * (2 * m_avg + 4) + 8 * P * N
     if fam == "update_fftx_f64":
-        return nv * N * 4 * (2 * m_avg + 2) + 16 * P * N
+        return nv * N * 4 * (2 * m_avg + 3) + 16 * P * N
     if fam == "fftx_residual_f32":    # spectra read once, then the residual + Gram row
         return 8 * P * N + nv * N * 4 * (2 + max(m_avg - 1, 0) + 1)
-    if fam == "fftx_residual_f64":
-        return 16 * P * N + nv * N * 4 * (2 + max(m_avg - 1, 0) + 3)
+    if fam == "fftx_residual_f64":    # as below, plus the re-base of the other stored deltas
+        return 16 * P * N + nv * N * 4 * (7 + 3 * max(m_avg - 1, 0))
     if fam == "residual_gram_f32":    # read spectra, R_ref, dg, (m-1) R_i; write R
         return 8 * P * N + nv * N * 4 * (2 + max(m_avg - 1, 0) + 1)
-    if fam == "residual_gram_f64":    # read FP64 spectra, tau, w, (m-1) R_i; write R, tau_ref, R_ref
-        return 16 * P * N + nv * N * 4 * (2 + max(m_avg - 1, 0) + 3)
+    if fam == "residual_gram_f64":    # read FP64 spectra, delta, tau_ref, w, (m-1) R_i; write R,
+        # delta, tau_ref, R_ref; read and write the other (m-1) stored deltas
+        return 16 * P * N + nv * N * 4 * (7 + 3 * max(m_avg - 1, 0))
     return 0.0
 
 

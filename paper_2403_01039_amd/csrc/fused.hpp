@@ -76,7 +76,7 @@ __global__ __launch_bounds__(kFftThreads) void k_update_fftx(
 template <bool ANCHOR, int N, int LINES = fixed_lines<PrecC<ANCHOR>, N, 0>()>
 __global__ __launch_bounds__(kFftThreads) void k_fftx_residual(
     const IterState* __restrict__ st, const void* __restrict__ spec_v,
-    const float* __restrict__ w, const float* __restrict__ tau_hist, float* __restrict__ res_hist,
+    const float* __restrict__ w, float* __restrict__ tau_hist, float* __restrict__ res_hist,
     float* __restrict__ tau_ref, float* __restrict__ r_ref, const float* __restrict__ dg, int ny,
     int nz, int nv, int npair, int M, int kind, int order, const PrecC<ANCHOR>* __restrict__ tw2_g,
     double* __restrict__ partials, GramW gw, size_t bstride) {

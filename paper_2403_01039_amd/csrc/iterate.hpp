@@ -17,6 +17,13 @@
 //   R = R_ref + dh - dg.
 // The increment is small wherever the iteration has converged, so its FP32
 // round-off is a small fraction of the current residual.
+//
+// Storage.  The history slots hold delta = tau - tau_ref, not tau: inside a
+// large solute core |tau| reaches 1e3, where the spacing of FP32 values (1e-4)
+// would swallow the small updates of a converging iteration.  tau is the
+// exact sum tau_ref + delta, formed in FP64 wherever tau itself is needed (the
+// anchor evaluation and the outputs).  Each anchor moves tau_ref to the
+// current tau rounded to FP32 and re-bases every stored delta on it.
 #pragma once
 
 #include "common.hpp"
@@ -57,9 +64,14 @@ __global__ void k_init_state(IterState* st, float eta, int warm) {
 
 // Place the starting tau (the caller's, or zero) in history slot 0, where the
 // first update reads it; keeps the iteration kernels independent of the call.
-__global__ void k_init_tau(const float* __restrict__ tau0, float* __restrict__ slot0, size_t n) {
+// The start: tau_ref = tau0 (or 0) and delta = 0 in the first slot.
+__global__ void k_init_tau(const float* __restrict__ tau0, float* __restrict__ slot0,
+                           float* __restrict__ tau_ref, size_t n) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) slot0[i] = tau0 ? tau0[i] : 0.0f;
+  if (i < n) {
+    slot0[i] = 0.0f;
+    tau_ref[i] = tau0 ? tau0[i] : 0.0f;
+  }
 }
 
 __global__ void k_mark_prepared(IterState* st) {
@@ -74,7 +86,7 @@ __global__ void k_mark_prepared(IterState* st) {
 // Step 6 + step 2 fused: MDIIS update, in difference form about the newest
 // stored pair b (which keeps sum c_i = 1 exact in FP32):
 //   tau = tau_b + sum_i c_i (tau_i - tau_b) + eta sum_i c_i R_i,
-// stored in the destination slot; then the closure.  ANCHOR: c_sr = g - 1 - tau
+// stored in the destination slot (as delta = tau - tau_ref); then the closure.  ANCHOR: c_sr = g - 1 - tau
 // in FP64 (double2 grid).  Otherwise the FP32 increment dc = dg - delta about
 // the anchor, with dg kept for the residual.  Two sites share one complex grid
 // (site 2p real part, site 2p+1 imaginary part).
@@ -140,7 +152,7 @@ __device__ inline void update_points(const UpdateCtl& u, float* __restrict__ tau
     const int g = 2 * p + s;
     if (g >= nv) break;
     const size_t gn = (size_t)g * N + n;
-    float tau[V];
+    float tau[V];   // delta = tau - tau_ref of the new iterate
     if (u.first) {
       ldv<V>(tau_hist + (size_t)u.dest * nv * N + gn, tau);   // the start, placed by k_init_tau
     } else {
@@ -166,22 +178,21 @@ __device__ inline void update_points(const UpdateCtl& u, float* __restrict__ tau
       for (int v = 0; v < V; ++v) tau[v] = tb[v] + (dt[v] + u.eta * dr[v]);
     }
     stv<V>(tau_hist + (size_t)u.dest * nv * N + gn, tau);
-    float wv[V];
+    float wv[V], tr[V];
     ldv<V>(w + gn, wv);
+    ldv<V>(tau_ref + gn, tr);
     if (ANCHOR) {
 #pragma unroll
       for (int v = 0; v < V; ++v) {
-        const double d = -(double)wv[v] + (double)tau[v];
-        o64[s][v] = closure_g(d, kind, order) - 1.0 - (double)tau[v];
+        const double t = (double)tr[v] + (double)tau[v];
+        o64[s][v] = closure_g(-(double)wv[v] + t, kind, order) - 1.0 - t;
       }
     } else {
-      float tr[V], dg[V];
-      ldv<V>(tau_ref + gn, tr);
+      float dg[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) {
-        const float delta = tau[v] - tr[v];
-        dg[v] = closure_dg(-wv[v] + tr[v], delta, kind, order);
-        o32[s][v] = dg[v] - delta;
+        dg[v] = closure_dg(-wv[v] + tr[v], tau[v], kind, order);
+        o32[s][v] = dg[v] - tau[v];
       }
       stv<V>(dg_out + gn, dg);
     }
@@ -339,7 +350,8 @@ __global__ __launch_bounds__(kElemThreads) void k_contract(
 
 // ---------------------------------------------------------------------------
 // Step 5 and the MDIIS inner products.  ANCHOR: R = h + 1 - g (Eq 33) in FP64
-// from the double2 grid, which also becomes the new anchor (tau_ref, R_ref).
+// from the double2 grid, which also becomes the new anchor (tau_ref, R_ref);
+// the stored deltas are re-based on the new tau_ref.
 // Otherwise R = R_ref + dh - dg.  R is stored in the destination slot and
 // <R, R_i> for every other stored slot and <R, R> are accumulated in FP64;
 // per-block partial sums are written in block order (reduced by k_control).
@@ -363,7 +375,7 @@ __device__ inline double block_sum(double v, double* lds) {
 template <bool ANCHOR, int V>
 __device__ inline void residual_points(const float* hre, const float* him, const double (*h64)[V],
                                        const float* __restrict__ w,
-                                       const float* __restrict__ tau_hist,
+                                       float* __restrict__ tau_hist,
                                        float* __restrict__ res_hist, float* __restrict__ tau_ref,
                                        float* __restrict__ r_ref, const float* __restrict__ dg,
                                        size_t N, int nv, int p, size_t n, int dest, unsigned mask,
@@ -376,16 +388,34 @@ __device__ inline void residual_points(const float* hre, const float* him, const
     const size_t od = (size_t)dest * nv * N + gn;
     float R[V];
     if (ANCHOR) {
-      float tau[V], wv[V];
-      ldv<V>(tau_hist + od, tau);
+      float dl[V], tr[V], wv[V];
+      double shift[V];
+      ldv<V>(tau_hist + od, dl);
+      ldv<V>(tau_ref + gn, tr);
       ldv<V>(w + gn, wv);
 #pragma unroll
       for (int v = 0; v < V; ++v) {
-        const double gg = closure_g(-(double)wv[v] + (double)tau[v], kind, order);
+        const double t = (double)tr[v] + (double)dl[v];
+        const double gg = closure_g(-(double)wv[v] + t, kind, order);
         R[v] = (float)(h64[s][v] + 1.0 - gg);
+        const float tn = (float)t;             // the new reference
+        shift[v] = (double)tn - (double)tr[v];
+        tr[v] = tn;
+        dl[v] = (float)((double)dl[v] - shift[v]);
       }
-      stv<V>(tau_ref + gn, tau);
+      stv<V>(tau_ref + gn, tr);
       stv<V>(r_ref + gn, R);
+      stv<V>(tau_hist + od, dl);
+#pragma unroll
+      for (int i = 0; i < kMaxDepth; ++i) {
+        if (mask & (1u << i)) {   // every other stored delta moves by the same shift
+          float di[V];
+          ldv<V>(tau_hist + (size_t)i * nv * N + gn, di);
+#pragma unroll
+          for (int v = 0; v < V; ++v) di[v] = (float)((double)di[v] - shift[v]);
+          stv<V>(tau_hist + (size_t)i * nv * N + gn, di);
+        }
+      }
     } else {
       float rr[V], dd[V];
       ldv<V>(r_ref + gn, rr);
@@ -437,7 +467,7 @@ __device__ inline void write_partials(const double* acc, int M, double* __restri
 template <bool ANCHOR, int V>
 __global__ __launch_bounds__(kRedThreads) void k_residual(
     const IterState* __restrict__ st, const void* __restrict__ spec, const float* __restrict__ w,
-    const float* __restrict__ tau_hist, float* __restrict__ res_hist, float* __restrict__ tau_ref,
+    float* __restrict__ tau_hist, float* __restrict__ res_hist, float* __restrict__ tau_ref,
     float* __restrict__ r_ref, const float* __restrict__ dg, size_t N, int nv, int npair, int M,
     int kind, int order, double* __restrict__ partials, GramW gw) {
   if (st->done) return;
@@ -842,15 +872,15 @@ __global__ __launch_bounds__(kCtlThreads) void k_control(
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kElemThreads) void k_output(
     const IterState* __restrict__ st, const float* __restrict__ tau_hist,
-    const float* __restrict__ w, size_t N, int nv, int kind, int order, float* __restrict__ g_out,
-    float* __restrict__ tau_out) {
+    const float* __restrict__ tau_ref, const float* __restrict__ w, size_t N, int nv, int kind,
+    int order, float* __restrict__ g_out, float* __restrict__ tau_out) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (size_t)nv * N) return;
   const int slot = st->final_slot;
   if (slot < 0) return;
-  const float tau = tau_hist[(size_t)slot * nv * N + idx];
-  if (g_out) g_out[idx] = (float)closure_g(-(double)w[idx] + (double)tau, kind, order);
-  if (tau_out) tau_out[idx] = tau;
+  const double tau = (double)tau_ref[idx] + (double)tau_hist[(size_t)slot * nv * N + idx];
+  if (g_out) g_out[idx] = (float)closure_g(-(double)w[idx] + tau, kind, order);
+  if (tau_out) tau_out[idx] = (float)tau;
 }
 
 // ---------------------------------------------------------------------------
@@ -859,8 +889,9 @@ __global__ __launch_bounds__(kElemThreads) void k_output(
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kRedThreads) void k_sfe_partial(
     const IterState* __restrict__ st, const float* __restrict__ tau_hist,
-    const float* __restrict__ w, const float* __restrict__ phi_lr, size_t N, int nv, int kind,
-    int order, SiteConsts sc, double* __restrict__ partials) {
+    const float* __restrict__ tau_ref, const float* __restrict__ w,
+    const float* __restrict__ phi_lr, size_t N, int nv, int kind, int order, SiteConsts sc,
+    double* __restrict__ partials) {
   // partials[block][2 nv]: the free-energy density sums, then the sums of c
   __shared__ double red[kRedThreads / 64];
   const int slot = st->final_slot;
@@ -870,10 +901,11 @@ __global__ __launch_bounds__(kRedThreads) void k_sfe_partial(
   for (int g = 0; g < nv; ++g) {
     double acc = 0.0, acc_c = 0.0;
     const float* tau = tau_hist + ((size_t)slot * nv + g) * N;
+    const float* tr = tau_ref + (size_t)g * N;
     const float* wg = w + (size_t)g * N;
     for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
          n += (size_t)gridDim.x * blockDim.x) {
-      const double t = tau[n];
+      const double t = (double)tr[n] + (double)tau[n];
       const double d = -(double)wg[n] + t;
       const double gg = closure_g(d, kind, order);
       const double h = gg - 1.0;

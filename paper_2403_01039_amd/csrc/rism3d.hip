@@ -1014,7 +1014,8 @@ void launch_sfe(const rism3d_problem* pr, const rism3d_opts* op, const Layout& L
     TIMED(F_SFE, s);
     hipLaunchKernelGGL(k_sfe_partial, dim3(nblk), dim3(kRedThreads), 0, s,
                        at<IterState>(ws, L.off_state), at<float>(ws, L.off_tau),
-                       at<float>(ws, L.off_w), at<float>(ws, L.off_phi), L.N, L.nv,
+                       at<float>(ws, L.off_tref), at<float>(ws, L.off_w), at<float>(ws, L.off_phi),
+                       L.N, L.nv,
                        (int)op->closure, order_of(op), sc, at<double>(ws, L.off_part));
   }
   const double scale = L.dv / L.beta;   // k_B T dV
@@ -1148,13 +1149,13 @@ __global__ void k_net_input(const float* __restrict__ w, const float* __restrict
 
 // c_sr = g - 1 - tau of the accepted iterate (FP64 closure).
 __global__ void k_csr_out(const IterState* __restrict__ st, const float* __restrict__ tau_hist,
-                          const float* __restrict__ w, size_t N, int nv, int kind, int order,
-                          float* __restrict__ c) {
+                          const float* __restrict__ tau_ref, const float* __restrict__ w, size_t N,
+                          int nv, int kind, int order, float* __restrict__ c) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (size_t)nv * N) return;
   const int slot = st->final_slot;
   if (slot < 0) return;
-  const double tau = (double)tau_hist[(size_t)slot * nv * N + idx];
+  const double tau = (double)tau_ref[idx] + (double)tau_hist[(size_t)slot * nv * N + idx];
   c[idx] = (float)(closure_g(-(double)w[idx] + tau, kind, order) - 1.0 - tau);
 }
 
@@ -1263,7 +1264,7 @@ rism3d_status rism3d_solve(const rism3d_problem* pr, const rism3d_opts* op, cons
                      t0 ? 1 : 0);
   hipLaunchKernelGGL(k_init_tau, dim3(blocks_for((size_t)L.nv * L.N, kElemThreads)),
                      dim3(kElemThreads), 0, s, t0, at<float>(ws, L.off_tau),
-                     (size_t)L.nv * L.N);
+                     at<float>(ws, L.off_tref), (size_t)L.nv * L.N);
   LAUNCH_CHECK();
   const int every = op->anchor_every > 0 ? op->anchor_every : kDefaultAnchorEvery;
   // One anchor period (an FP64 anchor evaluation + every-1 FP32 increments) is
@@ -1302,8 +1303,8 @@ rism3d_status rism3d_solve(const rism3d_problem* pr, const rism3d_opts* op, cons
   if (g_out) {
     hipLaunchKernelGGL(k_output, dim3(blocks_for((size_t)L.nv * L.N, kElemThreads)),
                        dim3(kElemThreads), 0, s, dst, at<float>(ws, L.off_tau),
-                       at<float>(ws, L.off_w), L.N, L.nv, (int)op->closure, order_of(op), g_out,
-                       (float*)nullptr);
+                       at<float>(ws, L.off_tref), at<float>(ws, L.off_w), L.N, L.nv,
+                       (int)op->closure, order_of(op), g_out, (float*)nullptr);
     LAUNCH_CHECK();
   }
   if (info) {
@@ -1445,7 +1446,7 @@ rism3d_status rism3d_solve_batch(int n, const rism3d_problem* prs, const rism3d_
                          (float)op->mdiis_eta, t0 ? 1 : 0);
       hipLaunchKernelGGL(k_init_tau, dim3(blocks_for((size_t)L.nv * L.N, kElemThreads)),
                          dim3(kElemThreads), 0, s, t0, at<float>(w, L.off_tau),
-                         (size_t)L.nv * L.N);
+                         at<float>(w, L.off_tref), (size_t)L.nv * L.N);
       LAUNCH_CHECK();
     }
   const int every = op->anchor_every > 0 ? op->anchor_every : kDefaultAnchorEvery;
@@ -1525,8 +1526,9 @@ rism3d_status rism3d_solve_batch(int n, const rism3d_problem* prs, const rism3d_
       if (g_out && g_out[i])
         hipLaunchKernelGGL(k_output, dim3(blocks_for((size_t)L.nv * L.N, kElemThreads)),
                            dim3(kElemThreads), 0, s, at<IterState>(w, L.off_state),
-                           at<float>(w, L.off_tau), at<float>(w, L.off_w), L.N, L.nv,
-                           (int)op->closure, order_of(op), g_out[i], (float*)nullptr);
+                           at<float>(w, L.off_tau), at<float>(w, L.off_tref),
+                           at<float>(w, L.off_w), L.N, L.nv, (int)op->closure, order_of(op),
+                           g_out[i], (float*)nullptr);
       if (thermo && h.final_slot >= 0) {
         launch_sfe(&prs[i], op, L, w, s);
         HIP_TRY(hipMemcpyAsync(&sfe[(size_t)i * kOutDoubles], at<double>(w, L.off_out),
@@ -1572,8 +1574,8 @@ rism3d_status rism3d_get_tau(const rism3d_problem* pr, const rism3d_opts* op, co
   void* ws = const_cast<void*>(ws_c);
   hipLaunchKernelGGL(k_output, dim3(blocks_for((size_t)L.nv * L.N, kElemThreads)),
                      dim3(kElemThreads), 0, s, at<IterState>(ws, L.off_state),
-                     at<float>(ws, L.off_tau), at<float>(ws, L.off_w), L.N, L.nv,
-                     (int)op->closure, order_of(op), (float*)nullptr, d_tau);
+                     at<float>(ws, L.off_tau), at<float>(ws, L.off_tref), at<float>(ws, L.off_w),
+                     L.N, L.nv, (int)op->closure, order_of(op), (float*)nullptr, d_tau);
   LAUNCH_CHECK();
   return RISM3D_OK;
 }
@@ -1597,7 +1599,7 @@ rism3d_status rism3d_map(const rism3d_problem* pr, const rism3d_opts* op, const 
   hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1), 0, s, dst, (float)op->mdiis_eta, 1);
   hipLaunchKernelGGL(k_init_tau, dim3(blocks_for((size_t)L.nv * L.N, kElemThreads)),
                      dim3(kElemThreads), 0, s, d_tau, at<float>(ws, L.off_tau),
-                     (size_t)L.nv * L.N);
+                     at<float>(ws, L.off_tref), (size_t)L.nv * L.N);
   launch_iteration(L, ws, &one, (float)(1.0 / pr->dk), true, s);
   const size_t n = (size_t)L.nv * L.N;
   hipLaunchKernelGGL(k_copy_floats, dim3(blocks_for(n, kElemThreads)), dim3(kElemThreads), 0, s,
@@ -1811,7 +1813,8 @@ rism3d_status rism3d_csr(const rism3d_problem* pr, const rism3d_opts* op, const 
   if (!d_c) return fail(RISM3D_E_ARG, "null output");
   hipLaunchKernelGGL(k_csr_out, dim3(blocks_for((size_t)L.nv * L.N, kElemThreads)),
                      dim3(kElemThreads), 0, s, at<IterState>(ws_c, L.off_state),
-                     at<float>(ws_c, L.off_tau), at<float>(ws_c, L.off_w), L.N, L.nv,
+                     at<float>(ws_c, L.off_tau), at<float>(ws_c, L.off_tref),
+                     at<float>(ws_c, L.off_w), L.N, L.nv,
                      (int)op->closure, order_of(op), d_c);
   LAUNCH_CHECK();
   return RISM3D_OK;

@@ -262,13 +262,13 @@ def test_full_size_golden(R, name):
 def test_globule_4000_at_256(R, O):
     """The 4000-atom globule (net +4, water, 256^3 at 0.4 A) at full size:
     the potential at 2000 sampled points against the oracle's pair sums, a
-    KH solve with MDIIS depth 10, and the returned tau's residual under one
-    FP64 evaluation of the map.  At this size FP32 storage of tau (|tau| up
-    to hundreds in the core) floors the residual near rms 2e-6, so the solve
-    runs to rms 3e-6.  (The workload's PSE-3 closure, from zero or ramped
-    from KH, does not converge reliably here in FP32: it stalls between
-    rms 6e-6 and 1e-4; PSE-3 with depth 10 is checked against the oracle on
-    the small parity cases.)"""
+    KH solve with MDIIS depth 10 to the paper's rms 1e-6, and the returned
+    tau's residual under one FP64 evaluation of the map (the returned tau is
+    rounded to FP32, which adds a few 1e-7).  (The workload's PSE-3 closure
+    diverges on this densely charged globule, from zero and from the KH
+    solution alike: its cubic branch turns the strong Coulomb wells into
+    g ~ d^3/6.  PSE-3 with depth 10 is checked against the oracle on the
+    small parity cases.)"""
     import time
     prob = inputs.globule_4000_problem()
     print("globule_4000 256^3", flush=True)
@@ -285,7 +285,7 @@ def test_globule_4000_at_256(R, O):
     rel = np.abs(w_s - w_ref) / np.maximum(1.0, np.abs(w_ref))
     soft = w_ref < 5.0
     assert rel[soft].max() < 2e-5 and rel[~soft].max() < 1e-3
-    s.opts = R.make_opts(prob.options, closure="kh", max_iter=3000, tol=3e-6)
+    s.opts = R.make_opts(prob.options, closure="kh", max_iter=3000, tol=1e-6)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     info = s.solve()
@@ -295,8 +295,8 @@ def test_globule_4000_at_256(R, O):
     res, rms = s.map(s.tau())
     print(f"  KH: {info.iterations} iterations, rms {info.rms:.2e}, {el:.2f} s; FP64 map rms "
           f"at the returned tau {rms:.2e}; sfe {sfe:.2f}", flush=True)
-    assert info.rms < 3e-6 and info.status == 0
-    assert rms < 6e-6
+    assert info.rms < 1e-6 and info.status == 0
+    assert rms < 2e-6
     assert np.isfinite(sfe)
 
 
@@ -304,18 +304,19 @@ def test_globule_12877_at_512(R, O):
     """The paper-scale stand-in: 12877 atoms (net +13) in water + 0.1 M NaCl on
     512^3 at 0.5 A, one GPU.  The potential at 2000 sampled points against the
     oracle's pair sums, a KH solve with modified Anderson (the paper's GPU
-    accelerator) through the 512-point transforms, the returned tau's residual
-    under one FP64 evaluation of the map, and finite SFE and PMV.  FP32
-    storage of tau (|tau| reaches ~1.6e3 in the core, where increments below
-    its 1e-4 spacing are lost) floors this solve's residual between rms
-    6.5e-6 and 1.3e-5 (round-off decides where), so it runs to rms 3e-5."""
+    accelerator) to the paper's rms 1e-6 through the 512-point transforms,
+    the returned tau's residual under one FP64 evaluation of the map, and
+    finite SFE and PMV.  |tau| reaches ~1.6e3 in the core: the iterate is held
+    as a reference plus an increment, so updates far below the FP32 spacing
+    of tau itself still accumulate; the returned tau is rounded to FP32,
+    which adds ~3e-7 to its FP64 residual."""
     import time
     prob = inputs.globule_12877_problem()
     print("globule_12877 512^3, 5 sites", flush=True)
     chi, dk = inputs.solvent_table_for(prob.solvent)
     dp = R.DeviceProblem(prob, chi, dk, bulk=inputs.solvent_bulk("saline"))
     s = R.Solver(dp, R.make_opts(prob.options, accelerator="anderson", mdiis_eta=0.6,
-                                 tol=3e-5, max_iter=1500))
+                                 tol=1e-6, max_iter=2000))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s.potential()
@@ -345,8 +346,8 @@ def test_globule_12877_at_512(R, O):
     print(f"  potential {t_pot:.2f} s; Anderson: {info.iterations} iterations, rms {info.rms:.2e}, "
           f"{el:.2f} s ({el / info.iterations * 1e3:.1f} ms each); FP64 map rms {rms:.2e}; "
           f"sfe {th['sfe']:.1f} kcal/mol, pmv {th['pmv']:.0f} A^3", flush=True)
-    assert info.rms < 3e-5 and info.status == 0
-    assert rms < 6e-5
+    assert info.rms < 1e-6 and info.status == 0
+    assert rms < 2e-6
     assert np.isfinite(th["sfe"]) and th["pmv"] > 0.0
 
 
@@ -365,7 +366,9 @@ def test_empty_solute_is_bulk(R):
 
 def test_warm_start_from_solution(R):
     """Restarting from the converged tau takes one map evaluation and returns
-    the same g (the warm start changes only the iteration count)."""
+    the same g up to the rounding of tau to float32 (the iterate is held as
+    an FP32 reference plus an FP32 increment, and rism3d_get_tau returns their
+    sum rounded to FP32)."""
     prob = inputs.small_problem(12, n_atoms=8, shape=(20, 20, 20), radius=2.5)
     s, _, _ = _run(R, prob)
     g1 = torch.empty(s.dp.shape, dtype=torch.float32, device="cuda")
@@ -375,7 +378,7 @@ def test_warm_start_from_solution(R):
     info = s.solve(tau0=tau, g_out=g2)
     assert info.warm_start_used == 1
     assert info.iterations == 1
-    assert torch.equal(g1, g2)
+    assert torch.allclose(g1, g2, rtol=2e-6, atol=1e-7)
 
 
 def test_noconv_and_bad_args(R):
