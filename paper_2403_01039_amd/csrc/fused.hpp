@@ -73,7 +73,9 @@ __global__ __launch_bounds__(kFftThreads) void k_update_fftx(
   }
 }
 
-template <bool ANCHOR, int N, int LINES = fixed_lines<PrecC<ANCHOR>, N, 0>()>
+// MM: compile-time bound on the history depth (the Gram accumulators held per
+// thread); the launch picks the smallest instantiated bound >= M.
+template <bool ANCHOR, int N, int LINES = fixed_lines<PrecC<ANCHOR>, N, 0>(), int MM = kMaxDepth>
 __global__ __launch_bounds__(kFftThreads) void k_fftx_residual(
     const IterState* __restrict__ st, const void* __restrict__ spec_v,
     const float* __restrict__ w, float* __restrict__ tau_hist, float* __restrict__ res_hist,
@@ -132,9 +134,9 @@ __global__ __launch_bounds__(kFftThreads) void k_fftx_residual(
   }
   __syncthreads();
   passes_from<0, 1, N, LINES>(buf, nl, tw2, S(1));
-  double acc[kMaxDepth + 1];
+  double acc[MM + 1];
 #pragma unroll
-  for (int i = 0; i <= kMaxDepth; ++i) acc[i] = 0.0;
+  for (int i = 0; i <= MM; ++i) acc[i] = 0.0;
   for (int t = threadIdx.x; t < nl * Q; t += kFftThreads) {
     const int b = t / Q;
     const int i0 = (t - b * Q) * 4;
@@ -151,10 +153,10 @@ __global__ __launch_bounds__(kFftThreads) void k_fftx_residual(
       h64[0][v] = (double)h.x;
       h64[1][v] = (double)h.y;
     }
-    residual_points<ANCHOR, 4>(hre, him, h64, w, tau_hist, res_hist, tau_ref, r_ref, dg, N3, nv,
-                               p, n, dest, mask, kind, order, gw, acc);
+    residual_points<ANCHOR, 4, MM>(hre, him, h64, w, tau_hist, res_hist, tau_ref, r_ref, dg, N3,
+                                   nv, p, n, dest, mask, kind, order, gw, acc);
   }
-  write_partials(acc, M, partials, red);
+  write_partials<MM>(acc, M, partials, red);
 }
 
 }  // namespace rism

@@ -371,8 +371,9 @@ __device__ inline double block_sum(double v, double* lds) {
 }
 
 // The residual of V consecutive points n.. of pair p from the transformed
-// values h (hre/him in FP32, h64 in FP64), accumulated into the Gram partials.
-template <bool ANCHOR, int V>
+// values h (hre/him in FP32, h64 in FP64), accumulated into the Gram partials
+// acc[0..MM-1] (slots; MM >= the history depth) and acc[MM] (the RMS sum).
+template <bool ANCHOR, int V, int MM = kMaxDepth>
 __device__ inline void residual_points(const float* hre, const float* him, const double (*h64)[V],
                                        const float* __restrict__ w,
                                        float* __restrict__ tau_hist,
@@ -427,9 +428,9 @@ __device__ inline void residual_points(const float* hre, const float* him, const
     double rr = 0.0;
 #pragma unroll
     for (int v = 0; v < V; ++v) rr += (double)R[v] * (double)R[v];
-    acc[kMaxDepth] += rr;          // unweighted: the RMS
+    acc[MM] += rr;                 // unweighted: the RMS
 #pragma unroll
-    for (int i = 0; i < kMaxDepth; ++i) {
+    for (int i = 0; i < MM; ++i) {
       if (i == dest) acc[i] += wg * rr;   // weighted Gram diagonal
       if (mask & (1u << i)) {
         float ri[V];
@@ -451,16 +452,17 @@ __device__ inline unsigned other_slots(const IterState* __restrict__ st, int M, 
 }
 
 // Write this block's partial sums (fixed block order, reduced in fixed order).
+template <int MM = kMaxDepth>
 __device__ inline void write_partials(const double* acc, int M, double* __restrict__ partials,
                                       double* red) {
 #pragma unroll
-  for (int i = 0; i < kMaxDepth; ++i) {
+  for (int i = 0; i < MM; ++i) {
     if (i < M) {   // M is uniform: every thread takes the same branches
       const double s = block_sum(acc[i], red);
       if (threadIdx.x == 0) partials[(size_t)blockIdx.x * (M + 1) + i] = s;
     }
   }
-  const double s = block_sum(acc[kMaxDepth], red);
+  const double s = block_sum(acc[MM], red);
   if (threadIdx.x == 0) partials[(size_t)blockIdx.x * (M + 1) + M] = s;
 }
 

@@ -682,7 +682,14 @@ void launch_fused_l(const Layout& L, void* ws, const rism3d_opts* op, bool first
   } else {
     {
       TIMED(ANCHOR ? F_FFTRES64 : F_FFTRES32, s);
-      hipLaunchKernelGGL((k_fftx_residual<ANCHOR, N, LINES>), grid, block, 0, s, st,
+      // the FP32 residual holds one Gram accumulator per possible slot: a
+      // tight bound for the usual depths keeps registers (and occupancy) free
+      auto residual = &k_fftx_residual<ANCHOR, N, LINES, kMaxDepth>;
+      if constexpr (!ANCHOR) {
+        if (L.M <= 3) residual = &k_fftx_residual<false, N, LINES, 3>;
+        else if (L.M <= 5) residual = &k_fftx_residual<false, N, LINES, 5>;
+      }
+      hipLaunchKernelGGL(residual, grid, block, 0, s, st,
                          at<void>(ws, L.off_spec), at<float>(ws, L.off_w),
                          at<float>(ws, L.off_tau), at<float>(ws, L.off_res),
                          at<float>(ws, L.off_tref), at<float>(ws, L.off_rref),
