@@ -18,7 +18,7 @@ using PrecC = typename std::conditional<ANCHOR, double2, float2>::type;
 
 // LINES (x rows per workgroup) of both fused kernels defaults to fixed_lines;
 // the autotuner may pick another count for the FP32 iterations.
-template <bool ANCHOR, int N, int LINES = fixed_lines<PrecC<ANCHOR>, N, 0>()>
+template <bool ANCHOR, int N, int LINES = fixed_lines<PrecC<ANCHOR>, N, 0>(), int MM = kMaxDepth>
 __global__ __launch_bounds__(kFftThreads) void k_update_fftx(
     const IterState* __restrict__ st, float* __restrict__ tau_hist,
     const float* __restrict__ res_hist, const float* __restrict__ w,
@@ -56,8 +56,8 @@ __global__ __launch_bounds__(kFftThreads) void k_update_fftx(
     const size_t n = (row - (size_t)p * plane) * N + i0;
     double o64[2][4];
     float o32[2][4];
-    update_points<ANCHOR, 4>(u, tau_hist, res_hist, w, tau_ref, dg_out, N3, nv, p, n, kind, order,
-                             o64, o32);
+    update_points<ANCHOR, 4, MM>(u, tau_hist, res_hist, w, tau_ref, dg_out, N3, nv, p, n, kind,
+                                 order, o64, o32);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const C val = ANCHOR ? make_c((S)o64[0][v], (S)o64[1][v]) : make_c((S)o32[0][v], (S)o32[1][v]);

@@ -134,7 +134,7 @@ __device__ inline UpdateCtl load_update_ctl(const IterState* __restrict__ st, in
 // The update + closure of V consecutive points n.. of pair p: stores the new tau
 // (and dg in the FP32 path) and returns the two sites' FFT inputs.
 // ANCHOR: c_sr = g - 1 - tau (FP64).  Otherwise dc = dg - delta.
-template <bool ANCHOR, int V>
+template <bool ANCHOR, int V, int MM = kMaxDepth>
 __device__ inline void update_points(const UpdateCtl& u, float* __restrict__ tau_hist,
                                      const float* __restrict__ res_hist,
                                      const float* __restrict__ w,
@@ -161,7 +161,7 @@ __device__ inline void update_points(const UpdateCtl& u, float* __restrict__ tau
 #pragma unroll
       for (int v = 0; v < V; ++v) dt[v] = dr[v] = 0.0f;
 #pragma unroll
-      for (int i = 0; i < kMaxDepth; ++i) {
+      for (int i = 0; i < MM; ++i) {
         const float c = u.cf[i];   // zero beyond M and for unused slots
         if (c != 0.0f) {
           float ti[V], ri[V];

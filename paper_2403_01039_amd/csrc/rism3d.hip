@@ -674,7 +674,12 @@ void launch_fused_l(const Layout& L, void* ws, const rism3d_opts* op, bool first
   const C* tw = at<C>(ws, ANCHOR ? L.off_tw64[0] : L.off_tw32[0]);
   if (first_half) {
     TIMED(ANCHOR ? F_UPDFFT64 : F_UPDFFT32, s);
-    hipLaunchKernelGGL((k_update_fftx<ANCHOR, N, LINES>), grid, block, 0, s, st,
+    auto update = &k_update_fftx<ANCHOR, N, LINES, kMaxDepth>;
+    if constexpr (!ANCHOR) {
+      if (L.M <= 3) update = &k_update_fftx<false, N, LINES, 3>;
+      else if (L.M <= 5) update = &k_update_fftx<false, N, LINES, 5>;
+    }
+    hipLaunchKernelGGL(update, grid, block, 0, s, st,
                        at<float>(ws, L.off_tau), at<float>(ws, L.off_res), at<float>(ws, L.off_w),
                        at<float>(ws, L.off_tref), at<float>(ws, L.off_dg),
                        at<void>(ws, L.off_spec), L.ny, L.nz, L.nv, L.npair, L.M, kind, order, tw,
