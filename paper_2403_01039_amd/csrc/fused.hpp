@@ -213,7 +213,51 @@ __global__ __launch_bounds__(kFftThreads) void k_zcz(
     return (size_t)p * N + (size_t)z * zs + (size_t)(side ? jy2 : jy) * nx + x;
   };
   const int total = 2 * P * nb * NZ;
-  {
+  // FP32 tiles of full width move column pairs as 16-byte vectors: on side 0
+  // the pair (b, b+1) sits at x0+b, x0+b+1; on side 1, where columns run
+  // backwards in x, at nx-2-x0-b (column b+1) and nx-1-x0-b (column b).
+  constexpr bool kVec = std::is_same<C, float2>::value && B % 2 == 0;
+  constexpr int H = B / 2;
+  auto pair_addr = [&](int side, int p, int h, int z) -> size_t {
+    const int x = side ? nx - 2 - x0 - 2 * h : x0 + 2 * h;
+    return (size_t)p * N + (size_t)z * zs + (size_t)(side ? jy2 : jy) * nx + x;
+  };
+  const bool vec = kVec && nb == B;
+  if constexpr (kVec) {
+   if (vec) {
+    constexpr int TOT = 2 * P * H * NZ;
+    constexpr int EPT = (TOT + kFftThreads - 1) / kFftThreads;
+    float4 v[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int f = threadIdx.x + e * kFftThreads;
+      if (f < TOT) {
+        const int h = f % H;
+        const int r = f / H;
+        const int z = r % NZ;
+        const int sp = r / NZ;
+        const int side = sp / P, p = sp - side * P;
+        v[e] = *reinterpret_cast<const float4*>(spec + pair_addr(side, p, h, z));
+      }
+    }
+    __syncthreads();   // twiddles visible
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int f = threadIdx.x + e * kFftThreads;
+      if (f < TOT) {
+        const int h = f % H;
+        const int r = f / H;
+        const int z = r % NZ;
+        const int sp = r / NZ;
+        const int side = sp / P;
+        const float2 lo = make_float2(v[e].x, v[e].y), hi = make_float2(v[e].z, v[e].w);
+        buf[Lds<NZ>::at(sp * B + 2 * h, z)] = cmul(side ? hi : lo, tw2[z]);
+        buf[Lds<NZ>::at(sp * B + 2 * h + 1, z)] = cmul(side ? lo : hi, tw2[z]);
+      }
+    }
+   }
+  }
+  if (!vec) {
     // every load of the tile in flight before the first LDS store
     constexpr int EPT = (2 * P * B * NZ + kFftThreads - 1) / kFftThreads;
     C v[EPT];
@@ -292,6 +336,23 @@ __global__ __launch_bounds__(kFftThreads) void k_zcz(
   }
   __syncthreads();
   passes_from<0, 1, NZ, LINES>(buf, LINES, tw2, S(1));
+  if constexpr (kVec) {
+   if (vec) {
+    for (int f = threadIdx.x; f < 2 * P * H * NZ; f += kFftThreads) {
+      const int h = f % H;
+      const int r = f / H;
+      const int z = r % NZ;
+      const int sp = r / NZ;
+      const int side = sp / P, p = sp - side * P;
+      const C a = cmulc(buf[Lds<NZ>::at(sp * B + 2 * h, z)], tw2[z]);
+      const C c = cmulc(buf[Lds<NZ>::at(sp * B + 2 * h + 1, z)], tw2[z]);
+      const C lo = side ? c : a, hi = side ? a : c;
+      *reinterpret_cast<float4*>(spec + pair_addr(side, p, h, z)) =
+          make_float4((float)lo.x, (float)lo.y, (float)hi.x, (float)hi.y);
+    }
+    return;
+   }
+  }
   for (int f = threadIdx.x; f < total; f += kFftThreads) {
     const int b = f % nb;
     const int r = f / nb;
