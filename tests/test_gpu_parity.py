@@ -1,6 +1,6 @@
 """GPU parity: the HIP library (through the C-ABI) against the FP64 oracle.
 
-Bars (spec tolerances): max |g_gpu - g_oracle| <= 1e-4 against the
+Bars: max |g_gpu - g_oracle| <= 1e-4 against the
 oracle converged to rms 1e-10, and |dSFE| / |SFE| <= 1e-3.  Stage checks
 (transform, potential, one map evaluation) use FP32 round-off bounds derived
 in the design doc.
