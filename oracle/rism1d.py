@@ -16,7 +16,7 @@
   for the sites of dipolar species, in a molecular frame centred on the site
   centroid with the dipole along z.  hc0 is fixed by requiring that the
   k -> 0 limit of the charge-charge susceptibility reproduce eps_r (XRISM
-  alone gives 1 + 3y); the derivation is in the design doc.
+  alone gives 1 + 3y).
 * The Coulomb tail is split as in Eq 29-30 with l = 1 A: the iteration
   variable is tau = t - beta C q_a q_b (1 - e^{-r})/r, whose transform is
   h~ - c~sr; the analytic long-range transform 4 pi / (k^2 (k^2 + 1)) enters

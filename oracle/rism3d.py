@@ -7,7 +7,7 @@ Eq 29-30, half-integer k grid, solution steps 1-7 with Eq 31-33), plus the
 MDIIS accelerator of "Convergence acceleration" (Eq 40, read as the
 Kovalenko-Ten-no-Hirata form below).
 
-Readings where the paper is silent or garbled (each listed in the design doc):
+Readings where the paper is silent or garbled:
 * KH closure: g = exp(d) for d <= 0 and 1 + d for d > 0 (the printed Eq 15
   has the two branches swapped; Eq 6 uses the threshold 1).
 * Units: kcal/mol, Angstrom, e; Coulomb factor C = 332.0637133 kcal A/(mol e^2)

@@ -2,8 +2,8 @@
 
 Bars: max |g_gpu - g_oracle| <= 1e-4 against the
 oracle converged to rms 1e-10, and |dSFE| / |SFE| <= 1e-3.  Stage checks
-(transform, potential, one map evaluation) use FP32 round-off bounds derived
-in DESIGN.md.
+(transform, potential, one map evaluation) use FP32 round-off bounds, derived
+where each test states them.
 """
 import numpy as np
 import pytest
