@@ -371,7 +371,8 @@ def main():
                            args.summarize_counters[2])
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the solver runs on one GPU per process; --gpus must be 1 "
+                                   "(independent solves shard across GPUs by process)"}))
         sys.exit(2)
 
     import numpy as np
