@@ -228,7 +228,10 @@ rism3d_status rism3d_sfe_gradient(const rism3d_problem* problem, const rism3d_op
                                   hipStream_t stream);
 
 /* Copies tau = t - f of the returned iterate (float32 [n_sites][nz][ny][nx]) into
- * d_tau (device); usable as d_tau0 of a later solve (resume / warm start). */
+ * d_tau (device); usable as d_tau0 of a later solve (resume / warm start).
+ * The solver holds the iterate as a float32 reference plus a float32
+ * increment; the copy is their sum rounded to float32, so a solve restarted
+ * from it reproduces g to float32 rounding of tau, not bit for bit. */
 rism3d_status rism3d_get_tau(const rism3d_problem* problem, const rism3d_opts* opts,
                              const void* d_ws, size_t ws_bytes, float* d_tau,
                              hipStream_t stream);
