@@ -89,10 +89,13 @@ def test_potential_matches_oracle(R, O, name):
 
 
 @pytest.mark.parametrize("saline,shape", [(False, (18, 20, 24)), (True, (18, 20, 24)),
-                                          (True, (64, 24, 32)), (False, (32, 16, 64))])
+                                          (True, (64, 24, 32)), (False, (32, 16, 64)),
+                                          (True, (512, 8, 32))])
 def test_map_matches_oracle(R, O, saline, shape):
-    """One evaluation of steps 2-5 at the same tau on both sides (the last two
-    shapes take the fused x-transform and fused z-transform/contraction paths)."""
+    """One evaluation of steps 2-5 at the same tau on both sides (the third and
+    fourth shapes take the fused x-transform and fused z-transform/contraction
+    paths; the last, with 512-point z columns, the fused x transform and the
+    separate z transform and contraction)."""
     prob = inputs.small_problem(5, n_atoms=10, shape=shape, saline=saline)
     print(f"map {prob.name} saline={saline}", flush=True)
     s, chi, dk = _run(R, prob)
@@ -349,6 +352,22 @@ def test_globule_12877_at_512(R, O):
     assert info.rms < 1e-6 and info.status == 0
     assert rms < 2e-6
     assert np.isfinite(th["sfe"]) and th["pmv"] > 0.0
+
+
+def test_z512_solve_has_the_fp64_residual(R):
+    """A solve with 512-point z columns (FP32 increments, five sites) stops
+    where one FP64 evaluation of the map (checked against the oracle at this
+    shape by test_map_matches_oracle) agrees that the residual is below the
+    tolerance."""
+    prob = inputs.small_problem(36, n_atoms=6, shape=(512, 8, 32), radius=1.5, saline=True,
+                                charge_scale=0.5)
+    print("z 512 solve", flush=True)
+    s, _, _ = _run(R, prob)
+    info = s.solve()
+    res, rms = s.map(s.tau())
+    print(f"  {info.iterations} iterations, rms {info.rms:.2e}; FP64 map rms {rms:.2e}", flush=True)
+    assert info.rms < 1e-6
+    assert rms < 1.5e-6
 
 
 def test_empty_solute_is_bulk(R):
