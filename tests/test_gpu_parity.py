@@ -319,7 +319,7 @@ def test_globule_12877_at_512(R, O):
     chi, dk = inputs.solvent_table_for(prob.solvent)
     dp = R.DeviceProblem(prob, chi, dk, bulk=inputs.solvent_bulk("saline"))
     s = R.Solver(dp, R.make_opts(prob.options, accelerator="anderson", mdiis_eta=0.6,
-                                 tol=1e-6, max_iter=2000))
+                                 tol=1e-6, max_iter=3000))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s.potential()
