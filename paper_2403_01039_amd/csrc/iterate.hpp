@@ -674,7 +674,7 @@ __device__ inline bool anderson_theta(const IterState& st, int s0, int s1, int s
 }
 
 // accel: RISM3D_MDIIS or RISM3D_ANDERSON (shifts as1, as2; mixing eta_static).
-__device__ inline void control_step(IterState& st, const double* sums,
+__device__ __forceinline__ void control_step(IterState& st, const double* sums,
                                     double (*A)[kMaxDepth + 2], int M, double inv_count,
                                     double tol, int max_iter, float eta_static, int eta_dynamic,
                                     int accel, double as1, double as2) {
@@ -808,7 +808,12 @@ struct ControlScratch {
 
 // Reduce the partials of `nblocks` blocks in fixed order and run one control
 // step on the state; all threads of the calling workgroup participate.
-__device__ inline void control_block(IterState* __restrict__ st_g,
+// MM bounds the history depth (M <= MM): each thread then holds MM + 1 sums
+// and stages U partial rows at a time, so their loads are in flight together
+// (the rows were just written by other CUs: every round trip costs ~2 us).
+// The per-thread order of the additions is the same for every U.
+template <int MM = kMaxDepth>
+__device__ __forceinline__ void control_block(IterState* __restrict__ st_g,
                                      const double* __restrict__ partials, int nblocks, int M,
                                      double inv_count, double tol, int max_iter, float eta_static,
                                      int eta_dynamic, int accel, double as1, double as2,
@@ -822,17 +827,34 @@ __device__ inline void control_block(IterState* __restrict__ st_g,
   // Each thread sums its strided blocks for all M+1 quantities at once (loads
   // in flight together), then one LDS pass combines the per-wave sums in
   // fixed order.
-  double v[kMaxDepth + 1];
+  constexpr int U = MM <= 5 ? 6 : 1;
+  double v[MM + 1];
 #pragma unroll
-  for (int q = 0; q <= kMaxDepth; ++q) v[q] = 0.0;
-  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+  for (int q = 0; q <= MM; ++q) v[q] = 0.0;
+  int b = threadIdx.x;
+  if constexpr (U > 1) {
+    for (; b + (U - 1) * (int)blockDim.x < nblocks; b += U * (int)blockDim.x) {
+      double r[U][MM + 1];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const double* pb = partials + (size_t)(b + u * (int)blockDim.x) * (M + 1);
+#pragma unroll
+        for (int q = 0; q <= MM; ++q) r[u][q] = q <= M ? pb[q] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int q = 0; q <= MM; ++q) v[q] += r[u][q];
+    }
+  }
+  for (; b < nblocks; b += blockDim.x) {
     const double* pb = partials + (size_t)b * (M + 1);
 #pragma unroll
-    for (int q = 0; q <= kMaxDepth; ++q)
+    for (int q = 0; q <= MM; ++q)
       if (q <= M) v[q] += pb[q];
   }
 #pragma unroll
-  for (int q = 0; q <= kMaxDepth; ++q) {
+  for (int q = 0; q <= MM; ++q) {
     if (q <= M) {
       for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_down(v[q], off, 64);
       if ((threadIdx.x & 63) == 0) cs.wsum[threadIdx.x >> 6][q] = v[q];
@@ -857,6 +879,7 @@ __device__ inline void control_block(IterState* __restrict__ st_g,
   }
 }
 
+template <int MM = kMaxDepth>
 __global__ __launch_bounds__(kCtlThreads) void k_control(
     IterState* __restrict__ st_g, const double* __restrict__ partials, int nblocks, int M,
     double inv_count, double tol, int max_iter, float eta_static, int eta_dynamic,
@@ -865,7 +888,7 @@ __global__ __launch_bounds__(kCtlThreads) void k_control(
   st_g = member_ptr(st_g, bstride);
   if (st_g->done) return;
   partials = member_ptr(partials, bstride);
-  control_block(st_g, partials, nblocks, M, inv_count, tol, max_iter, eta_static, eta_dynamic,
+  control_block<MM>(st_g, partials, nblocks, M, inv_count, tol, max_iter, eta_static, eta_dynamic,
                 accel, as1, as2, cs);
 }
 

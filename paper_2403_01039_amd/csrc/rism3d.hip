@@ -704,7 +704,8 @@ void launch_fused_l(const Layout& L, void* ws, const rism3d_opts* op, bool first
     if (!control) return;
     TIMED(F_CONTROL, s);
     const double inv_count = 1.0 / ((double)L.N * (double)L.nv);
-    hipLaunchKernelGGL(k_control, dim3(1, bt.nb), dim3(kCtlThreads), 0, s, st,
+    hipLaunchKernelGGL(L.M <= 5 ? &k_control<5> : &k_control<kMaxDepth>, dim3(1, bt.nb),
+                       dim3(kCtlThreads), 0, s, st,
                        at<double>(ws, L.off_part), (int)grid.x, L.M, inv_count, op->tol,
                        op->max_iter, (float)op->mdiis_eta, op->eta_dynamic,
                        (int)op->accelerator, op->anderson_s1, op->anderson_s2, bt.stride);
@@ -833,7 +834,8 @@ void launch_iteration(const Layout& L, void* ws, const rism3d_opts* op, float in
   const double inv_count = 1.0 / ((double)L.N * (double)L.nv);
   {
     TIMED(F_CONTROL, s);
-    hipLaunchKernelGGL(k_control, dim3(1), dim3(kCtlThreads), 0, s, st, at<double>(ws, L.off_part),
+    hipLaunchKernelGGL(L.M <= 5 ? &k_control<5> : &k_control<kMaxDepth>, dim3(1),
+                       dim3(kCtlThreads), 0, s, st, at<double>(ws, L.off_part),
                        (int)nblk, L.M, inv_count, op->tol, op->max_iter, (float)op->mdiis_eta,
                        op->eta_dynamic, (int)op->accelerator, op->anderson_s1, op->anderson_s2,
                        (size_t)0);
