@@ -158,7 +158,9 @@ size_t rism3d_workspace_bytes(const rism3d_problem* problem, const rism3d_opts* 
 rism3d_status rism3d_potential(const rism3d_problem* problem, const rism3d_opts* opts,
                                void* d_ws, size_t ws_bytes, hipStream_t stream);
 
-/* Steps 1-7 of "Numerical procedure" with MDIIS.  d_tau0 (device, float32
+/* Steps 1-7 of "Numerical procedure" with MDIIS (Eq 40) or, when
+ * opts->accelerator is RISM3D_ANDERSON, the modified Anderson method
+ * (Eq 34-39).  d_tau0 (device, float32
  * [n_sites][nz][ny][nx], may be NULL) is the starting short-range indirect
  * correlation tau = t - f; NULL starts from t = f (tau = 0) as the paper does.
  * On return d_g (device, float32 [n_sites][nz][ny][nx], may be NULL) holds
