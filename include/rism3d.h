@@ -99,7 +99,7 @@ typedef struct {
 /* Solver options (Eq 40-41 and the closure choice).
  * closure, pse_order (PSE-n order n >= 1; PSE-1 is KH), tol (RMS residual
  * threshold, Eq 41; the paper's default is 1e-6), max_iter, mdiis_depth
- * (1..RISM3D_MAX_DEPTH), mdiis_eta (damping of the MDIIS step, (0, 1]),
+ * (1..RISM3D_MAX_DEPTH), mdiis_eta (damping of the MDIIS step, (0, 2]),
  * eta_dynamic (non-zero: eta = clamp(-0.2 ln RMS, 0.1, 1.0) each step),
  * check_every (host polls the device convergence flag every this many
  * iterations; 0 picks a default), anchor_every (every this many iterations the
