@@ -326,7 +326,10 @@ def rism3d_thermo_all(dp, opts, ws, stream=None) -> dict:
     out = ThermoOut()
     _check(LIB.rism3d_thermo(ctypes.byref(dp.struct), ctypes.byref(opts), _ptr(ws),
                              ws.numel() * ws.element_size(), ctypes.byref(out), _stream(stream)))
-    nv = dp.struct.n_sites
+    return _thermo_dict(out, dp.struct.n_sites)
+
+
+def _thermo_dict(out, nv: int) -> dict:
     return {"sfe": out.sfe, "sfe_site": np.array(out.sfe_site[:nv]),
             "rho_int_c": np.array(out.rho_int_c[:nv]), "rho_int_c_total": out.rho_int_c_total,
             "pmv": out.pmv, "pc": out.pc, "sfe_pc": out.sfe_pc}
@@ -383,9 +386,10 @@ def rism3d_batch_workspace_bytes(dps, opts: Opts) -> int:
 
 
 def rism3d_solve_batch(dps, opts: Opts, ws: torch.Tensor, tau0=None, g_out=None, stream=None,
-                       allow_noconv=False, thermo=True):
+                       allow_noconv=False, thermo=True, full_thermo=False):
     """Batched potential + solve (+ SFE) of several problems; returns the list of
-    Info and the list of (sfe, per-site sfe) or None."""
+    Info and the list of (sfe, per-site sfe), or of rism3d_thermo_all's
+    dictionaries when full_thermo, or None."""
     n = len(dps)
     arr = _problem_array(dps)
     ptrs = lambda ts: (None if ts is None else
@@ -403,7 +407,9 @@ def rism3d_solve_batch(dps, opts: Opts, ws: torch.Tensor, tau0=None, g_out=None,
     for inf in out_info:
         inf.status = status
     sfe = None
-    if thermo:
+    if thermo and full_thermo:
+        sfe = [_thermo_dict(t, dp.shape[0]) for t, dp in zip(th, dps)]
+    elif thermo:
         sfe = [(t.sfe, np.array(t.sfe_site[:dp.shape[0]])) for t, dp in zip(th, dps)]
     return out_info, sfe
 

@@ -100,6 +100,28 @@ def test_anderson_batch_equals_single_solves(R):
     _compare(R, probs, opts, range(len(probs)))
 
 
+def test_batch_thermo_includes_pmv(R):
+    """The batch's thermodynamics carry the PMV and PC term of each member
+    (its own solvent's bulk values), equal to the single solves'."""
+    probs = [inputs.small_problem(41, n_atoms=6, shape=(64, 24, 32), radius=2.5),
+             inputs.small_problem(42, n_atoms=6, shape=(64, 24, 32), radius=2.5, saline=True)]
+    opts = R.make_opts(probs[0].options)
+    dps = []
+    for p in probs:
+        name = inputs.solvent_name(p.solvent)
+        dps.append(R.DeviceProblem(p, *inputs.solvent_table(name), bulk=inputs.solvent_bulk(name)))
+    ws = R.alloc_workspace(R.rism3d_batch_workspace_bytes(dps, opts))
+    _, th = R.rism3d_solve_batch(dps, opts, ws, full_thermo=True)
+    for dp, t in zip(dps, th):
+        s = R.Solver(dp, opts)
+        s.potential()
+        s.solve()
+        one = s.thermo_all()
+        print(f"  pmv {t['pmv']:.4f} (single {one['pmv']:.4f}), pc {t['pc']:.4f}", flush=True)
+        assert t["pmv"] == one["pmv"] and t["pc"] == one["pc"]
+        assert np.array_equal(t["rho_int_c"], one["rho_int_c"])
+
+
 def test_batch_nonconvergence_reports_member(R):
     probs = [inputs.small_problem(31, n_atoms=6, shape=(64, 24, 32), radius=2.5),
              inputs.small_problem(32, n_atoms=6, shape=(64, 24, 32), radius=2.5)]
