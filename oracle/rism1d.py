@@ -277,7 +277,7 @@ def solve_solvent(solvent, grid: Optional[RadialGrid] = None, closure_kind: str 
 def bulk_pressure(solvent, res: SolventResult) -> float:
     """Eq 20, the pressure of the bulk solvent in kcal/(mol A^3):
         P = sum_G rho_G (n_G + 1) / (2 beta)
-            - (2 pi / beta) sum_{g,l} rho_g rho_l \int_0^inf c_gl(r) r^2 dr,
+            - (2 pi / beta) sum_{g,l} rho_g rho_l int_0^inf c_gl(r) r^2 dr,
     G over species (molecular density rho_G, n_G sites), g and l over sites,
     c the full direct correlation of the 1D solution.  The radial integral is
     the sum dr sum_i c(r_i) r_i^2 over the grid (the end point r = 0 adds

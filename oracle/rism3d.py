@@ -484,7 +484,7 @@ def sfe_gradient(problem, g: np.ndarray, atoms=None) -> np.ndarray:
     respect to a solute atom position (section "Hybrid implementation", the
     derivative of Eq 23):
 
-        d(dmu)/dR_a = sum_g rho_g \int g_g(r) du_g(r)/dR_a dr,
+        d(dmu)/dR_a = sum_g rho_g int g_g(r) du_g(r)/dR_a dr,
 
     u_g from Eq 22 (pairs inside the 0.01 A clamp contribute nothing, since
     the clamped pair term does not depend on R_a there), the integral as the
@@ -519,9 +519,9 @@ def sfe_gradient(problem, g: np.ndarray, atoms=None) -> np.ndarray:
 
 
 def pmv(sol: Solution, compressibility: float):
-    """Eq 19: the partial molar volume k_B T chi_T (1 - sum_g rho_g \int c_g dr)
+    """Eq 19: the partial molar volume k_B T chi_T (1 - sum_g rho_g int c_g dr)
     in A^3, with c = g - 1 - t (full c) and the integral as the box sum
-    dV sum_n.  Returns (pmv, per-site rho_g \int c_g dr)."""
+    dV sum_n.  Returns (pmv, per-site rho_g int c_g dr)."""
     sys_ = sol.system
     rho = sys_.problem.solvent.site_arrays()[3]
     rho_int_c = np.array([rho[g] * sys_.dv * float(np.sum(sol.c[g]))

@@ -321,7 +321,7 @@ def rism3d_sfe_gradient(dp, opts, ws, g: torch.Tensor, out: Optional[torch.Tenso
 
 
 def rism3d_thermo_all(dp, opts, ws, stream=None) -> dict:
-    """Every field of rism3d_thermo_out: SFE (total, per site), rho_g \int c_g,
+    """Every field of rism3d_thermo_out: SFE (total, per site), rho_g int c_g,
     PMV (Eq 19), PC term (Eq 21) and SFE + PC."""
     out = ThermoOut()
     _check(LIB.rism3d_thermo(ctypes.byref(dp.struct), ctypes.byref(opts), _ptr(ws),

@@ -2,8 +2,10 @@
 the derivative of the MM/3D-RISM free energy, Eq 23): it must be the
 derivative of quantities the oracle computes independently."""
 import copy
+import math
 
 import numpy as np
+import pytest
 
 from oracle import rism3d as O
 from paper_2403_01039_amd import inputs as I
@@ -35,14 +37,15 @@ def test_gradient_is_the_derivative_of_the_potential_energy_in_a_fixed_distribut
     assert np.abs(grad - fd).max() <= 1e-7 * np.abs(fd).max()
 
 
-def test_gradient_is_the_derivative_of_the_free_energy_for_a_neutral_solute():
-    """For an uncharged solute the discrete KH free energy (Eq 18) is stationary
-    in h and c at the fixed point (the OZ operator with the symmetric water
-    table is self-adjoint), so its derivative in R_a is exactly the gradient
-    formula at the solved g: central differences of whole solves agree to
-    the finite-difference error (measured 6e-9 relative)."""
-    prob = I.small_problem(12, n_atoms=2, shape=(14, 14, 14), radius=1.2)
+def _stationarity_deviation(kind, order=3, eta=0.7, components=((0, 0), (0, 2), (1, 1))):
+    """Largest |dF/dR_a - grad_a| / max|grad| over the listed components, with
+    F the oracle's free energy (Eq 17, Eq 18 or PSE-n) of whole solves of an
+    uncharged two-atom solute in water and grad the gradient formula at the
+    solved g."""
+    prob = I.small_problem(12, n_atoms=2, shape=(14, 14, 14), radius=1.2, closure=kind)
     prob.solute.q[:] = 0.0
+    prob.options.pse_order = order
+    prob.options.mdiis_eta = eta
     chi, dk = I.solvent_table("water")
 
     def solved(p):
@@ -52,12 +55,54 @@ def test_gradient_is_the_derivative_of_the_free_energy_for_a_neutral_solute():
     _, sol = solved(prob)
     grad = O.sfe_gradient(prob, sol.g)
     h = 1e-4
-    for a, k in ((0, 0), (0, 2), (1, 1)):
+    worst = 0.0
+    for a, k in components:
         pp, pm = copy.deepcopy(prob), copy.deepcopy(prob)
         pp.solute.xyz[a, k] += h
         pm.solute.xyz[a, k] -= h
         fd = (solved(pp)[0] - solved(pm)[0]) / (2 * h)
-        assert abs(grad[a, k] - fd) <= 1e-6 * np.abs(grad).max(), (a, k, grad[a, k], fd)
+        worst = max(worst, abs(grad[a, k] - fd) / np.abs(grad).max())
+    return worst
+
+
+@pytest.mark.parametrize("kind,order,eta", [("kh", 1, 0.7), ("hnc", 1, 0.4), ("pse", 3, 0.7),
+                                            ("pse", 2, 0.7)])
+def test_gradient_is_the_derivative_of_the_free_energy_for_a_neutral_solute(kind, order, eta):
+    """For an uncharged solute each closure's discrete free energy (Eq 18 for
+    KH, Eq 17 for HNC, the Kast-Kloss form for PSE-n) is stationary in h and c
+    at its fixed point (the OZ operator with the symmetric water table is
+    self-adjoint), so its derivative in R_a is exactly the gradient formula at
+    the solved g: central differences of whole solves agree to the
+    finite-difference error (measured 5e-9 to 3e-8 relative).  This pins the
+    factors 1/2 of Eq 17-18 and the PSE-n term Theta(h) d^(n+1)/(n+1)!."""
+    assert _stationarity_deviation(kind, order, eta) <= 1e-6
+
+
+def _planted_hnc(h, c, d, kind, order=3):
+    """Eq 17 without its factors 1/2 (h = c only in the chi = 1 limit, where the
+    two mistakes cancel)."""
+    return -c - h * c + h * h
+
+
+def _planted_pse_power(h, c, d, kind, order=3):
+    """The PSE-n term with d^n / n! in place of d^(n+1) / (n+1)!."""
+    return -c - 0.5 * h * c + 0.5 * h * h - (h > 0.0) * d ** order / math.factorial(order)
+
+
+def _planted_pse_factorial(h, c, d, kind, order=3):
+    """The PSE-n term with the power right and the factorial one order low."""
+    return -c - 0.5 * h * c + 0.5 * h * h - (h > 0.0) * d ** (order + 1) / math.factorial(order)
+
+
+@pytest.mark.parametrize("kind,planted", [("hnc", _planted_hnc), ("pse", _planted_pse_power),
+                                          ("pse", _planted_pse_factorial)])
+def test_stationarity_pin_catches_planted_free_energy_mistakes(monkeypatch, kind, planted):
+    """Each planted mistake in the free-energy density breaks the stationarity
+    pin above by orders of magnitude (measured 2e-2 to 0.15 relative against
+    the 1e-6 bar)."""
+    monkeypatch.setattr(O, "sfe_density", planted)
+    assert _stationarity_deviation(kind, 3, 0.4 if kind == "hnc" else 0.7,
+                                   components=((0, 0),)) > 1e-3
 
 
 def test_symmetric_distribution_exerts_no_net_gradient():

@@ -130,6 +130,64 @@ def test_free_energy_density_forms():
                        O.sfe_density(d[pos], c[pos], d[pos], "kh"), atol=1e-12)
 
 
+# --- Eq 13: chi(|k|) on the 3D grid by linear interpolation of the radial table ---
+
+
+def _chi_interp_shifted(chi_table, dk_table, kmag, shift=1):
+    """The table read one node off (a planted mistake for the pin below)."""
+    n_k = chi_table.shape[-1]
+    x = np.minimum(kmag / dk_table, n_k - 1.0)
+    m = np.clip(np.floor(x).astype(np.int64) + shift, 0, n_k - 2)
+    fr = x - np.floor(x)
+    return chi_table[:, :, m] * (1.0 - fr) + chi_table[:, :, m + 1] * fr
+
+
+def _chi_pin_errors(fn):
+    """Errors of an interpolation routine against what linear interpolation on
+    a uniform table fixes independently of any implementation:
+      nodes   -- at k = m dk the table value itself;
+      linear  -- a table sampled from a + b k is reproduced exactly anywhere;
+      midpoint-- for f = k^2 the error at (m + 1/2) dk is exactly dk^2 / 4
+                 (the chord of a parabola over one interval);
+      held    -- beyond the table the last value;
+      order   -- entry [g', g] of the result comes from table row [g', g]."""
+    dk, n_k = 0.0306796, 64
+    k = dk * np.arange(n_k)
+    table = np.empty((2, 3, n_k))
+    for a in range(2):
+        for b in range(3):
+            table[a, b] = (10 * a + b + 1) + (a - b + 0.5) * k   # distinct line per entry
+    rng = np.random.default_rng(5)
+    kq = rng.uniform(0.0, (n_k - 1) * dk, 500)
+    err = {}
+    exact = (10 * np.arange(2)[:, None, None] + np.arange(3)[None, :, None] + 1
+             + (np.arange(2)[:, None, None] - np.arange(3)[None, :, None] + 0.5) * kq[None, None])
+    err["linear"] = float(np.abs(fn(table, dk, kq) - exact).max())
+    m = np.arange(n_k)
+    err["nodes"] = float(np.abs(fn(table, dk, m * dk) - table).max())
+    par = np.broadcast_to(k * k, (1, 1, n_k)).copy()
+    mid = (np.arange(n_k - 1) + 0.5) * dk
+    err["midpoint"] = float(np.abs(fn(par, dk, mid)[0, 0] - mid * mid - dk * dk / 4).max())
+    far = np.array([(n_k - 1) * dk * 1.0001, 10.0 * n_k * dk])
+    err["held"] = float(np.abs(fn(table, dk, far) - table[:, :, -1:]).max())
+    return err
+
+
+def test_chi_interpolation_pins():
+    err = _chi_pin_errors(O.chi_interp)
+    assert err["linear"] <= 1e-12, err
+    assert err["nodes"] <= 1e-12, err
+    assert err["midpoint"] <= 1e-14, err
+    assert err["held"] <= 1e-12, err
+
+
+@pytest.mark.parametrize("shift", [1, -1])
+def test_chi_pin_catches_a_one_node_shift(shift):
+    """Reading the table one node off (0.031 A^-1) fails the pin."""
+    err = _chi_pin_errors(lambda t, dk, km: _chi_interp_shifted(t, dk, km, shift))
+    assert max(err["nodes"], err["midpoint"]) > 1e-4, err
+
+
 # --- the map and the solve ------------------------------------------------------------
 
 
