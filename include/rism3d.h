@@ -128,7 +128,8 @@ typedef struct {
 
 typedef struct {
   int iterations;       /* evaluations of the 3D-RISM map (steps 2-5) */
-  double rms;           /* RMS residual of the returned iterate */
+  double rms;           /* RMS residual of the returned iterate; on convergence always that
+                           of an exact FP64 evaluation of the map at it (see rism3d_solve) */
   int restarts;         /* MDIIS restarts */
   int warm_start_used;  /* 1 if a caller tau0 was used */
 } rism3d_info;
@@ -167,7 +168,14 @@ rism3d_status rism3d_potential(const rism3d_problem* problem, const rism3d_opts*
  * g_g(r) of the returned iterate, and info (host, may be NULL) the iteration
  * count, final RMS and restart count.  Returns RISM3D_E_NOCONV when max_iter
  * is reached (outputs then hold the last iterate), RISM3D_E_NONFINITE on a
- * NaN/Inf residual. */
+ * NaN/Inf residual.
+ * Stopping rule (Eq 41).  The bulk iterations evaluate the map in FP32 as an
+ * increment over the last FP64 evaluation (every anchor_every iterations),
+ * so their residual is an estimate.  When an estimate falls below tol, the
+ * next evaluation is an exact FP64 one of that same iterate, and only an FP64
+ * residual below tol ends the solve: the returned iterate's exact residual
+ * (the info->rms reported) is below tol.  That evaluation counts as an
+ * iteration and may run one past max_iter. */
 rism3d_status rism3d_solve(const rism3d_problem* problem, const rism3d_opts* opts,
                            const float* d_tau0, void* d_ws, size_t ws_bytes, float* d_g,
                            rism3d_info* info, hipStream_t stream);
@@ -238,14 +246,33 @@ rism3d_status rism3d_get_tau(const rism3d_problem* problem, const rism3d_opts* o
                              const void* d_ws, size_t ws_bytes, float* d_tau,
                              hipStream_t stream);
 
-/* One evaluation of the discretised 3D-RISM map (steps 2-5, Eq 31-33) at a given
- * tau = t - f (device, float32 [n_sites][nz][ny][nx]): writes the residual
- * R = t' - t = h + 1 - g (device, float32, same layout) and returns its RMS in
- * *rms (host, may be NULL).  Uses the workspace prepared by rism3d_potential and
- * overwrites any solution held there. */
+/* One exact (FP64) evaluation of the discretised 3D-RISM map (steps 2-5,
+ * Eq 31-33) at tau = t - f: writes the residual R = t' - t = h + 1 - g
+ * (device, float32 [n_sites][nz][ny][nx]) and returns its RMS in *rms (host,
+ * may be NULL).  d_tau (device, float32, same layout) gives tau; the workspace
+ * must be prepared by rism3d_potential and any solution held there is
+ * overwritten.  d_tau = NULL evaluates the iterate the last rism3d_solve on
+ * this workspace returned, as it is held (FP32 reference + remainder +
+ * increment, summed in FP64; rism3d_get_tau would round it to FP32); that
+ * solution stays in place. */
 rism3d_status rism3d_map(const rism3d_problem* problem, const rism3d_opts* opts, const float* d_tau,
                          void* d_ws, size_t ws_bytes, float* d_residual, double* rms,
                          hipStream_t stream);
+
+/* The map through the kernels of the bulk FP32 iterations, at
+ * tau = d_tau_ref + d_delta (both device, float32 [n_sites][nz][ny][nx]): an
+ * exact FP64 evaluation at d_tau_ref (the anchor, R_ref), then the FP32
+ * evaluation of the increment, R = R_ref + dh - dg with
+ * dc = [g(d_ref + delta) - g(d_ref)] - delta transformed in FP32 (Eq 31-33
+ * applied to the difference; the long-range term of Eq 32 cancels).  Writes R
+ * (device, float32, same layout) and its RMS (host, may be NULL).  Same
+ * workspace rules as rism3d_map.  The kernels and tile widths are those a
+ * solve of this problem runs, so the FP32 result differs from the exact map
+ * at d_tau_ref + d_delta by FP32 round-off of the increment's terms. */
+rism3d_status rism3d_map_increment(const rism3d_problem* problem, const rism3d_opts* opts,
+                                   const float* d_tau_ref, const float* d_delta, void* d_ws,
+                                   size_t ws_bytes, float* d_residual, double* rms,
+                                   hipStream_t stream);
 
 /* Copies the fields rism3d_potential computed: w (float32 [n_sites][nz][ny][nx],
  * may be NULL) and phi_lr (float32 [nz][ny][nx], may be NULL), device to device. */

@@ -64,7 +64,7 @@ struct IterState {
   int dest;                           // slot receiving the next tau
   int newest;                         // most recently stored slot (difference-form update)
   int iter;                           // completed map evaluations
-  int done;                           // 1 when no further iteration must run
+  int done;                           // kDoneFinished, kDoneVerify or 0 (iterate)
   int converged;
   int status;                         // rism3d_status of the iteration
   int restarts;
@@ -72,7 +72,21 @@ struct IterState {
   int warm;                           // 1 if a caller tau0 seeded iteration 0
   int prepared;                       // magic set by rism3d_potential
   int ticket;                         // workgroups of the fused residual kernel that finished
+  int hold;                           // the next update re-evaluates the iterate in slot dest
 };
+
+// IterState::done.  kDoneVerify: an FP32 evaluation (whose residual is an
+// estimate built from increments) passed the tolerance; the FP32 kernels then
+// skip, and the next FP64 anchor evaluation re-evaluates that same iterate
+// exactly and decides.  Only an FP64 evaluation finishes a converged solve.
+constexpr int kDoneFinished = 1;
+constexpr int kDoneVerify = 2;
+
+// Whether a kernel of an FP64 (anchor) or FP32 evaluation skips its work.
+template <bool F64>
+__device__ __forceinline__ bool skip_iteration(int done) {
+  return F64 ? done == kDoneFinished : done != 0;
+}
 
 constexpr int kPreparedMagic = 0x52495344;  // "RISD"
 

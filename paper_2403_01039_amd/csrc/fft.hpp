@@ -196,7 +196,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_axis(
     const C* __restrict__ tw2_g, int forward, int lines, const int* __restrict__ done) {
   using S = typename ScalarOf<C>::type;
   constexpr int TILE = fft_tile_elems<C>();
-  if (done && *done) return;
+  if (done && skip_iteration<std::is_same<C, double2>::value>(*done)) return;
   __shared__ C lds[2 * TILE + 2 * kFftMaxN];
   C* bufA = lds;
   C* bufB = lds + TILE;
@@ -353,7 +353,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_fixed(
   constexpr int TILE = LINES * N;
   constexpr int EPT = (TILE + kFftThreads - 1) / kFftThreads;
   done = member_ptr(done, bstride);
-  if (done && *done) return;
+  if (done && skip_iteration<std::is_same<C, double2>::value>(*done)) return;
   data = member_ptr(data, bstride);
   tw2_g = member_ptr(tw2_g, bstride);
   __shared__ C buf[LINES * Lds<N>::PITCH];

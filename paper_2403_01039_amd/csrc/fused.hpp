@@ -22,18 +22,19 @@ template <bool ANCHOR, int N, int LINES = fixed_lines<PrecC<ANCHOR>, N, 0>(), in
 __global__ __launch_bounds__(kFftThreads) void k_update_fftx(
     const IterState* __restrict__ st, float* __restrict__ tau_hist,
     const float* __restrict__ res_hist, const float* __restrict__ w,
-    const float* __restrict__ tau_ref, float* __restrict__ dg_out, void* __restrict__ spec_v,
-    int ny, int nz, int nv, int npair, int M, int kind, int order,
-    const PrecC<ANCHOR>* __restrict__ tw2_g, size_t bstride) {
+    const float* __restrict__ tau_ref, const float* __restrict__ tau_lo,
+    float* __restrict__ dg_out, void* __restrict__ spec_v, int ny, int nz, int nv, int npair,
+    int M, int kind, int order, const PrecC<ANCHOR>* __restrict__ tw2_g, size_t bstride) {
   using C = PrecC<ANCHOR>;
   using S = typename ScalarOf<C>::type;
   constexpr int Q = N / 4;
   st = member_ptr(st, bstride);
-  if (st->done) return;
+  if (skip_iteration<ANCHOR>(st->done)) return;
   tau_hist = member_ptr(tau_hist, bstride);
   res_hist = member_ptr(res_hist, bstride);
   w = member_ptr(w, bstride);
   tau_ref = member_ptr(tau_ref, bstride);
+  tau_lo = member_ptr(tau_lo, bstride);
   dg_out = member_ptr(dg_out, bstride);
   spec_v = member_ptr(spec_v, bstride);
   tw2_g = member_ptr(tw2_g, bstride);
@@ -56,8 +57,8 @@ __global__ __launch_bounds__(kFftThreads) void k_update_fftx(
     const size_t n = (row - (size_t)p * plane) * N + i0;
     double o64[2][4];
     float o32[2][4];
-    update_points<ANCHOR, 4, MM>(u, tau_hist, res_hist, w, tau_ref, dg_out, N3, nv, p, n, kind,
-                                 order, o64, o32);
+    update_points<ANCHOR, 4, MM>(u, tau_hist, res_hist, w, tau_ref, tau_lo, dg_out, N3, nv, p, n,
+                                 kind, order, o64, o32);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const C val = ANCHOR ? make_c((S)o64[0][v], (S)o64[1][v]) : make_c((S)o32[0][v], (S)o32[1][v]);
@@ -79,19 +80,21 @@ template <bool ANCHOR, int N, int LINES = fixed_lines<PrecC<ANCHOR>, N, 0>(), in
 __global__ __launch_bounds__(kFftThreads) void k_fftx_residual(
     const IterState* __restrict__ st, const void* __restrict__ spec_v,
     const float* __restrict__ w, float* __restrict__ tau_hist, float* __restrict__ res_hist,
-    float* __restrict__ tau_ref, float* __restrict__ r_ref, const float* __restrict__ dg, int ny,
-    int nz, int nv, int npair, int M, int kind, int order, const PrecC<ANCHOR>* __restrict__ tw2_g,
-    double* __restrict__ partials, GramW gw, size_t bstride) {
+    float* __restrict__ tau_ref, float* __restrict__ tau_lo, float* __restrict__ r_ref,
+    const float* __restrict__ dg, int ny, int nz, int nv, int npair, int M, int kind, int order,
+    const PrecC<ANCHOR>* __restrict__ tw2_g, double* __restrict__ partials, GramW gw,
+    size_t bstride) {
   using C = PrecC<ANCHOR>;
   using S = typename ScalarOf<C>::type;
   constexpr int Q = N / 4;
   st = member_ptr(st, bstride);
-  if (st->done) return;
+  if (skip_iteration<ANCHOR>(st->done)) return;
   spec_v = member_ptr(spec_v, bstride);
   w = member_ptr(w, bstride);
   tau_hist = member_ptr(tau_hist, bstride);
   res_hist = member_ptr(res_hist, bstride);
   tau_ref = member_ptr(tau_ref, bstride);
+  tau_lo = member_ptr(tau_lo, bstride);
   r_ref = member_ptr(r_ref, bstride);
   dg = member_ptr(dg, bstride);
   tw2_g = member_ptr(tw2_g, bstride);
@@ -153,8 +156,8 @@ __global__ __launch_bounds__(kFftThreads) void k_fftx_residual(
       h64[0][v] = (double)h.x;
       h64[1][v] = (double)h.y;
     }
-    residual_points<ANCHOR, 4, MM>(hre, him, h64, w, tau_hist, res_hist, tau_ref, r_ref, dg, N3,
-                                   nv, p, n, dest, mask, kind, order, gw, acc);
+    residual_points<ANCHOR, 4, MM>(hre, him, h64, w, tau_hist, res_hist, tau_ref, tau_lo, r_ref,
+                                   dg, N3, nv, p, n, dest, mask, kind, order, gw, acc);
   }
   write_partials<MM>(acc, M, partials, red);
 }
@@ -182,15 +185,15 @@ constexpr int zcz_cols() {
 // pick another width; it does not change the operations on a column.
 template <typename C, int NZ, int NV, bool WITHF, int B = zcz_cols<C, NZ, NV>()>
 __global__ __launch_bounds__(kFftThreads) void k_zcz(
-    C* __restrict__ spec, int nx, int ny, const C* __restrict__ tw2_g, float dkx, float dky,
-    float dkz, const C* __restrict__ F, const typename ScalarOf<C>::type* __restrict__ chi,
-    const typename ScalarOf<C>::type* __restrict__ qtab, float inv_dkt, int m_tab,
+    C* __restrict__ spec, int nx, int ny, const C* __restrict__ tw2_g, double dkx, double dky,
+    double dkz, const C* __restrict__ F, const typename ScalarOf<C>::type* __restrict__ chi,
+    const typename ScalarOf<C>::type* __restrict__ qtab, double inv_dkt, int m_tab,
     const int* __restrict__ done, size_t bstride) {
   using S = typename ScalarOf<C>::type;
   constexpr int P = (NV + 1) / 2;
   constexpr int LINES = 2 * P * B;     // line l = (side * P + p) * B + b
   done = member_ptr(done, bstride);
-  if (done && *done) return;
+  if (done && skip_iteration<std::is_same<C, double2>::value>(*done)) return;
   spec = member_ptr(spec, bstride);
   tw2_g = member_ptr(tw2_g, bstride);
   F = member_ptr(F, bstride);
@@ -295,20 +298,10 @@ __global__ __launch_bounds__(kFftThreads) void k_zcz(
     const int b = t / NZ;
     const int jz = t - b * NZ;
     const int jx = x0 + b;
-    const float kx = (2 * jx < nx) ? (jx + 0.5f) * dkx : (jx + 0.5f - nx) * dkx;
-    const float ky = (2 * jy < ny) ? (jy + 0.5f) * dky : (jy + 0.5f - ny) * dky;
-    const float kz = (2 * jz < NZ) ? (jz + 0.5f) * dkz : (jz + 0.5f - NZ) * dkz;
-    const float kmag = sqrtf(kx * kx + ky * ky + kz * kz);
-    const float xk = kmag * inv_dkt;
     int m;
     S fr;
-    if (xk >= (float)(m_tab - 1)) {
-      m = m_tab - 2;
-      fr = S(1);
-    } else {
-      m = (int)xk;
-      fr = (S)(xk - (float)m);
-    }
+    table_pos<S>(kappa<S>(jx, nx, dkx), kappa<S>(jy, ny, dky), kappa<S>(jz, NZ, dkz), inv_dkt,
+                 m_tab, &m, &fr);
     C X[NV];
 #pragma unroll
     for (int p = 0; p < P; ++p) {

@@ -22,8 +22,15 @@
 // large solute core |tau| reaches 1e3, where the spacing of FP32 values (1e-4)
 // would swallow the small updates of a converging iteration.  tau is the
 // exact sum tau_ref + delta, formed in FP64 wherever tau itself is needed (the
-// anchor evaluation and the outputs).  Each anchor moves tau_ref to the
-// current tau rounded to FP32 and re-bases every stored delta on it.
+// anchor evaluation and the outputs).  The reference is a pair of FP32 fields,
+// tau_ref + tau_lo (tau_lo the rounding remainder of the FP64 iterate): each
+// anchor moves it to the current tau, exactly to about 2^-48, and re-bases
+// every stored delta on it.  R_ref is then the exact residual at the very
+// reference the FP32 increments are measured from; with tau_ref alone (tau
+// rounded to FP32) every FP32 residual would carry the map's response to that
+// rounding, up to half an FP32 spacing of tau (~3e-5 where |tau| ~ 1e3).  The
+// FP32 kernels read tau_ref only (as d_ref = -w + tau_ref of the closure
+// increment, where the remainder is negligible); only FP64 work reads tau_lo.
 #pragma once
 
 #include "common.hpp"
@@ -60,17 +67,19 @@ __global__ void k_init_state(IterState* st, float eta, int warm) {
   st->last_rms = 0.0;
   st->last_rr = 0.0;
   st->ticket = 0;
+  st->hold = 0;
 }
 
 // Place the starting tau (the caller's, or zero) in history slot 0, where the
 // first update reads it; keeps the iteration kernels independent of the call.
 // The start: tau_ref = tau0 (or 0) and delta = 0 in the first slot.
 __global__ void k_init_tau(const float* __restrict__ tau0, float* __restrict__ slot0,
-                           float* __restrict__ tau_ref, size_t n) {
+                           float* __restrict__ tau_ref, float* __restrict__ tau_lo, size_t n) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
     slot0[i] = 0.0f;
     tau_ref[i] = tau0 ? tau0[i] : 0.0f;
+    tau_lo[i] = 0.0f;
   }
 }
 
@@ -126,7 +135,7 @@ __device__ inline UpdateCtl load_update_ctl(const IterState* __restrict__ st, in
   u.eta = st->eta;
   u.dest = st->dest;
   u.newest = st->newest;
-  u.first = st->iter == 0;
+  u.first = st->iter == 0 || st->hold != 0;   // the iterate already in slot dest
   u.M = M;
   return u;
 }
@@ -138,7 +147,8 @@ template <bool ANCHOR, int V, int MM = kMaxDepth>
 __device__ inline void update_points(const UpdateCtl& u, float* __restrict__ tau_hist,
                                      const float* __restrict__ res_hist,
                                      const float* __restrict__ w,
-                                     const float* __restrict__ tau_ref, float* __restrict__ dg_out,
+                                     const float* __restrict__ tau_ref,
+                                     const float* __restrict__ tau_lo, float* __restrict__ dg_out,
                                      size_t N, int nv, int p, size_t n, int kind, int order,
                                      double (*o64)[V], float (*o32)[V]) {
 #pragma unroll
@@ -182,9 +192,11 @@ __device__ inline void update_points(const UpdateCtl& u, float* __restrict__ tau
     ldv<V>(w + gn, wv);
     ldv<V>(tau_ref + gn, tr);
     if (ANCHOR) {
+      float tl[V];
+      ldv<V>(tau_lo + gn, tl);
 #pragma unroll
       for (int v = 0; v < V; ++v) {
-        const double t = (double)tr[v] + (double)tau[v];
+        const double t = ((double)tr[v] + (double)tl[v]) + (double)tau[v];
         o64[s][v] = closure_g(-(double)wv[v] + t, kind, order) - 1.0 - t;
       }
     } else {
@@ -203,9 +215,10 @@ template <bool ANCHOR, int V>
 __global__ __launch_bounds__(kElemThreads) void k_update_closure(
     const IterState* __restrict__ st, float* __restrict__ tau_hist,
     const float* __restrict__ res_hist, const float* __restrict__ w,
-    const float* __restrict__ tau_ref, float* __restrict__ dg_out, void* __restrict__ spec,
-    size_t N, int nv, int npair, int M, int kind, int order) {
-  if (st->done) return;
+    const float* __restrict__ tau_ref, const float* __restrict__ tau_lo,
+    float* __restrict__ dg_out, void* __restrict__ spec, size_t N, int nv, int npair, int M,
+    int kind, int order) {
+  if (skip_iteration<ANCHOR>(st->done)) return;
   const size_t NQ = N / V;
   const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= (size_t)npair * NQ) return;
@@ -214,8 +227,8 @@ __global__ __launch_bounds__(kElemThreads) void k_update_closure(
   const UpdateCtl u = load_update_ctl(st, M);
   double o64[2][V];
   float o32[2][V];
-  update_points<ANCHOR, V>(u, tau_hist, res_hist, w, tau_ref, dg_out, N, nv, p, n, kind, order,
-                           o64, o32);
+  update_points<ANCHOR, V>(u, tau_hist, res_hist, w, tau_ref, tau_lo, dg_out, N, nv, p, n, kind,
+                           order, o64, o32);
   const size_t o = (size_t)p * N + n;
   if (ANCHOR) {
     double2* sp = static_cast<double2*>(spec) + o;
@@ -245,8 +258,27 @@ __global__ __launch_bounds__(kElemThreads) void k_update_closure(
 // The increments (WITHF = false) carry no long-range term.
 // Thread L handles the mirror pair (L, N-1-L): k_(N-1-L) = -k_L.
 // ---------------------------------------------------------------------------
-__device__ inline float kappa_f(int j, int n, float dk) {
-  return (2 * j < n) ? (j + 0.5f) * dk : (j + 0.5f - n) * dk;
+// The half-integer k representative of index j on an axis of n points, in the
+// precision S of the evaluation (FP64 for the anchors: the interpolation
+// weight below is |k| / dk_table ~ 4e2, where an FP32 |k| would leave an
+// absolute error ~3e-5 in the weight).
+template <typename S>
+__device__ inline S kappa(int j, int n, double dk) {
+  return (2 * j < n) ? ((S)j + S(0.5)) * (S)dk : ((S)j + S(0.5) - (S)n) * (S)dk;
+}
+
+// Table position of |k|: sample m and linear weight fr (Eq 13's chi by linear
+// interpolation; beyond the table the last interval's end value).
+template <typename S>
+__device__ inline void table_pos(S kx, S ky, S kz, double inv_dkt, int m_tab, int* m, S* fr) {
+  const S x = sqrt(kx * kx + ky * ky + kz * kz) * (S)inv_dkt;
+  if (x >= (S)(m_tab - 1)) {
+    *m = m_tab - 2;
+    *fr = S(1);
+  } else {
+    *m = (int)x;
+    *fr = x - (S)(*m);
+  }
 }
 
 // The contraction of Eq 13 at one k-point with the analytic long-range term
@@ -298,12 +330,12 @@ __device__ __forceinline__ void contract_point(const C (&X)[NV], C Fk, int m,
 
 template <int NV, typename C, bool WITHF>
 __global__ __launch_bounds__(kElemThreads) void k_contract(
-    C* __restrict__ spec, int nx, int ny, int nz, float dkx, float dky, float dkz,
+    C* __restrict__ spec, int nx, int ny, int nz, double dkx, double dky, double dkz,
     const C* __restrict__ F, const typename ScalarOf<C>::type* __restrict__ chi,
-    const typename ScalarOf<C>::type* __restrict__ qtab, float inv_dkt, int m_tab,
+    const typename ScalarOf<C>::type* __restrict__ qtab, double inv_dkt, int m_tab,
     const int* __restrict__ done) {
   using S = typename ScalarOf<C>::type;
-  if (done && *done) return;
+  if (done && skip_iteration<std::is_same<C, double2>::value>(*done)) return;
   constexpr int NP = (NV + 1) / 2;
   const size_t N = (size_t)nx * ny * nz;
   const size_t half = (N + 1) / 2;
@@ -313,18 +345,10 @@ __global__ __launch_bounds__(kElemThreads) void k_contract(
   const int jx = (int)(L % nx);
   const int jy = (int)((L / nx) % ny);
   const int jz = (int)(L / ((size_t)nx * ny));
-  const float kx = kappa_f(jx, nx, dkx), ky = kappa_f(jy, ny, dky), kz = kappa_f(jz, nz, dkz);
-  const float kmag = sqrtf(kx * kx + ky * ky + kz * kz);
-  const float x = kmag * inv_dkt;
   int m;
   S fr;
-  if (x >= (float)(m_tab - 1)) {
-    m = m_tab - 2;
-    fr = S(1);
-  } else {
-    m = (int)x;
-    fr = (S)(x - (float)m);
-  }
+  table_pos<S>(kappa<S>(jx, nx, dkx), kappa<S>(jy, ny, dky), kappa<S>(jz, nz, dkz), inv_dkt,
+               m_tab, &m, &fr);
   C X[NV];
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
@@ -378,7 +402,8 @@ __device__ inline void residual_points(const float* hre, const float* him, const
                                        const float* __restrict__ w,
                                        float* __restrict__ tau_hist,
                                        float* __restrict__ res_hist, float* __restrict__ tau_ref,
-                                       float* __restrict__ r_ref, const float* __restrict__ dg,
+                                       float* __restrict__ tau_lo, float* __restrict__ r_ref,
+                                       const float* __restrict__ dg,
                                        size_t N, int nv, int p, size_t n, int dest, unsigned mask,
                                        int kind, int order, const GramW& gw, double* acc) {
   for (int s = 0; s < 2; ++s) {
@@ -389,22 +414,28 @@ __device__ inline void residual_points(const float* hre, const float* him, const
     const size_t od = (size_t)dest * nv * N + gn;
     float R[V];
     if (ANCHOR) {
-      float dl[V], tr[V], wv[V];
+      float dl[V], tr[V], tl[V], wv[V];
       double shift[V];
       ldv<V>(tau_hist + od, dl);
       ldv<V>(tau_ref + gn, tr);
+      ldv<V>(tau_lo + gn, tl);
       ldv<V>(w + gn, wv);
 #pragma unroll
       for (int v = 0; v < V; ++v) {
-        const double t = (double)tr[v] + (double)dl[v];
+        const double base = (double)tr[v] + (double)tl[v];   // exact
+        const double t = base + (double)dl[v];
         const double gg = closure_g(-(double)wv[v] + t, kind, order);
         R[v] = (float)(h64[s][v] + 1.0 - gg);
-        const float tn = (float)t;             // the new reference
-        shift[v] = (double)tn - (double)tr[v];
-        tr[v] = tn;
+        // the new reference hi + lo = t to 2^-48; hi + lo and the shift are exact
+        const float hi = (float)t;
+        const float lo = (float)(t - (double)hi);
+        shift[v] = ((double)hi + (double)lo) - base;
+        tr[v] = hi;
+        tl[v] = lo;
         dl[v] = (float)((double)dl[v] - shift[v]);
       }
       stv<V>(tau_ref + gn, tr);
+      stv<V>(tau_lo + gn, tl);
       stv<V>(r_ref + gn, R);
       stv<V>(tau_hist + od, dl);
 #pragma unroll
@@ -470,9 +501,9 @@ template <bool ANCHOR, int V>
 __global__ __launch_bounds__(kRedThreads) void k_residual(
     const IterState* __restrict__ st, const void* __restrict__ spec, const float* __restrict__ w,
     float* __restrict__ tau_hist, float* __restrict__ res_hist, float* __restrict__ tau_ref,
-    float* __restrict__ r_ref, const float* __restrict__ dg, size_t N, int nv, int npair, int M,
-    int kind, int order, double* __restrict__ partials, GramW gw) {
-  if (st->done) return;
+    float* __restrict__ tau_lo, float* __restrict__ r_ref, const float* __restrict__ dg, size_t N,
+    int nv, int npair, int M, int kind, int order, double* __restrict__ partials, GramW gw) {
+  if (skip_iteration<ANCHOR>(st->done)) return;
   __shared__ double red[kRedThreads / 64];
   const int dest = st->dest;
   const unsigned mask = other_slots(st, M, dest);
@@ -511,8 +542,8 @@ __global__ __launch_bounds__(kRedThreads) void k_residual(
         him[v] = pk[2 * v + 1];
       }
     }
-    residual_points<ANCHOR, V>(hre, him, h64, w, tau_hist, res_hist, tau_ref, r_ref, dg, N, nv, p,
-                               n, dest, mask, kind, order, gw, acc);
+    residual_points<ANCHOR, V>(hre, him, h64, w, tau_hist, res_hist, tau_ref, tau_lo, r_ref, dg,
+                               N, nv, p, n, dest, mask, kind, order, gw, acc);
   }
   write_partials(acc, M, partials, red);
 }
@@ -674,33 +705,47 @@ __device__ inline bool anderson_theta(const IterState& st, int s0, int s1, int s
 }
 
 // accel: RISM3D_MDIIS or RISM3D_ANDERSON (shifts as1, as2; mixing eta_static).
+// anchor: the evaluation just finished was the exact FP64 one.  The stopping
+// test of Eq 41 is decided on exact residuals only: an FP32 residual (R_ref +
+// dh - dg, an estimate) below tol holds its iterate in slot dest and asks for
+// the next FP64 evaluation to re-evaluate it (kDoneVerify); that evaluation
+// either finishes the solve or continues it as an ordinary step whose
+// residual is exact.
 __device__ __forceinline__ void control_step(IterState& st, const double* sums,
                                     double (*A)[kMaxDepth + 2], int M, double inv_count,
                                     double tol, int max_iter, float eta_static, int eta_dynamic,
-                                    int accel, double as1, double as2) {
+                                    int accel, double as1, double as2, int anchor) {
   const bool anderson = accel == RISM3D_ANDERSON;
   const int dest = st.dest;
   const double rr = sums[M];
   const double rms = sqrt(rr * inv_count);
+  st.hold = 0;
+  st.done = 0;
   st.iter += 1;
   st.last_rms = rms;
   st.last_rr = rr;
   if (!(rr == rr) || rr > 1.0e300) {
     st.status = RISM3D_E_NONFINITE;
     st.final_slot = dest;
-    st.done = 1;
+    st.done = kDoneFinished;
     return;
   }
   if (rms < tol) {
-    st.converged = 1;
     st.final_slot = dest;
-    st.done = 1;
+    if (anchor) {
+      st.converged = 1;
+      st.done = kDoneFinished;
+    } else {
+      st.stored[dest] = 0;   // its old pair was overwritten; the FP64 pass stores it anew
+      st.hold = 1;
+      st.done = kDoneVerify;
+    }
     return;
   }
   if (st.iter >= max_iter) {
     st.status = RISM3D_E_NOCONV;
     st.final_slot = dest;
-    st.done = 1;
+    st.done = kDoneFinished;
     return;
   }
   // The destination slot's old pair (the oldest, when the ring was full) has
@@ -807,7 +852,8 @@ struct ControlScratch {
 };
 
 // Reduce the partials of `nblocks` blocks in fixed order and run one control
-// step on the state; all threads of the calling workgroup participate.
+// step on the state (anchor: the evaluation was the FP64 one); all threads of
+// the calling workgroup participate.
 // MM bounds the history depth (M <= MM): each thread then holds MM + 1 sums
 // and stages U partial rows at a time, so their loads are in flight together
 // (the rows were just written by other CUs: every round trip costs ~2 us).
@@ -817,7 +863,7 @@ __device__ __forceinline__ void control_block(IterState* __restrict__ st_g,
                                      const double* __restrict__ partials, int nblocks, int M,
                                      double inv_count, double tol, int max_iter, float eta_static,
                                      int eta_dynamic, int accel, double as1, double as2,
-                                     ControlScratch& cs) {
+                                     int anchor, ControlScratch& cs) {
   {
     const int* src = reinterpret_cast<const int*>(st_g);
     int* dst = reinterpret_cast<int*>(&cs.st);
@@ -869,7 +915,7 @@ __device__ __forceinline__ void control_block(IterState* __restrict__ st_g,
   __syncthreads();
   if (threadIdx.x == 0)
     control_step(cs.st, cs.sums, cs.A, M, inv_count, tol, max_iter, eta_static, eta_dynamic,
-                 accel, as1, as2);
+                 accel, as1, as2, anchor);
   __syncthreads();
   {
     const int* src = reinterpret_cast<const int*>(&cs.st);
@@ -883,13 +929,13 @@ template <int MM = kMaxDepth>
 __global__ __launch_bounds__(kCtlThreads) void k_control(
     IterState* __restrict__ st_g, const double* __restrict__ partials, int nblocks, int M,
     double inv_count, double tol, int max_iter, float eta_static, int eta_dynamic,
-    int accel, double as1, double as2, size_t bstride) {
+    int accel, double as1, double as2, int anchor, size_t bstride) {
   __shared__ ControlScratch cs;
   st_g = member_ptr(st_g, bstride);
-  if (st_g->done) return;
+  if (anchor ? skip_iteration<true>(st_g->done) : skip_iteration<false>(st_g->done)) return;
   partials = member_ptr(partials, bstride);
   control_block<MM>(st_g, partials, nblocks, M, inv_count, tol, max_iter, eta_static, eta_dynamic,
-                accel, as1, as2, cs);
+                accel, as1, as2, anchor, cs);
 }
 
 // ---------------------------------------------------------------------------
@@ -897,13 +943,15 @@ __global__ __launch_bounds__(kCtlThreads) void k_control(
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kElemThreads) void k_output(
     const IterState* __restrict__ st, const float* __restrict__ tau_hist,
-    const float* __restrict__ tau_ref, const float* __restrict__ w, size_t N, int nv, int kind,
-    int order, float* __restrict__ g_out, float* __restrict__ tau_out) {
+    const float* __restrict__ tau_ref, const float* __restrict__ tau_lo,
+    const float* __restrict__ w, size_t N, int nv, int kind, int order,
+    float* __restrict__ g_out, float* __restrict__ tau_out) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (size_t)nv * N) return;
   const int slot = st->final_slot;
   if (slot < 0) return;
-  const double tau = (double)tau_ref[idx] + (double)tau_hist[(size_t)slot * nv * N + idx];
+  const double tau = ((double)tau_ref[idx] + (double)tau_lo[idx]) +
+                     (double)tau_hist[(size_t)slot * nv * N + idx];
   if (g_out) g_out[idx] = (float)closure_g(-(double)w[idx] + tau, kind, order);
   if (tau_out) tau_out[idx] = (float)tau;
 }
@@ -914,9 +962,9 @@ __global__ __launch_bounds__(kElemThreads) void k_output(
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kRedThreads) void k_sfe_partial(
     const IterState* __restrict__ st, const float* __restrict__ tau_hist,
-    const float* __restrict__ tau_ref, const float* __restrict__ w,
-    const float* __restrict__ phi_lr, size_t N, int nv, int kind, int order, SiteConsts sc,
-    double* __restrict__ partials) {
+    const float* __restrict__ tau_ref, const float* __restrict__ tau_lo,
+    const float* __restrict__ w, const float* __restrict__ phi_lr, size_t N, int nv, int kind,
+    int order, SiteConsts sc, double* __restrict__ partials) {
   // partials[block][2 nv]: the free-energy density sums, then the sums of c
   __shared__ double red[kRedThreads / 64];
   const int slot = st->final_slot;
@@ -927,10 +975,11 @@ __global__ __launch_bounds__(kRedThreads) void k_sfe_partial(
     double acc = 0.0, acc_c = 0.0;
     const float* tau = tau_hist + ((size_t)slot * nv + g) * N;
     const float* tr = tau_ref + (size_t)g * N;
+    const float* tl = tau_lo + (size_t)g * N;
     const float* wg = w + (size_t)g * N;
     for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N;
          n += (size_t)gridDim.x * blockDim.x) {
-      const double t = (double)tr[n] + (double)tau[n];
+      const double t = ((double)tr[n] + (double)tl[n]) + (double)tau[n];
       const double d = -(double)wg[n] + t;
       const double gg = closure_g(d, kind, order);
       const double h = gg - 1.0;
@@ -980,6 +1029,38 @@ __global__ __launch_bounds__(kRedThreads) void k_sfe_reduce(const double* __rest
 __global__ void k_copy_floats(const float* __restrict__ src, float* __restrict__ dst, size_t n) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = src[i];
+}
+
+// The history slot of the accepted iterate (final_slot) of n = nv N floats.
+__global__ void k_copy_final_slot(const IterState* __restrict__ st,
+                                  const float* __restrict__ hist, float* __restrict__ dst,
+                                  size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int slot = st->final_slot;
+  if (i < n && slot >= 0) dst[i] = hist[(size_t)slot * n + i];
+}
+
+// The next evaluation re-evaluates the iterate of a solved workspace (the
+// accepted slot, reference + increment, without rounding).
+__global__ void k_hold_final(IterState* st) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  st->dest = st->final_slot;
+  st->hold = 1;
+  st->done = 0;
+  st->status = RISM3D_OK;
+}
+
+// The next evaluation takes delta[n] (n = nv N) as its increment over the
+// reference: written into slot dest, which the update then leaves as it is.
+__global__ void k_set_increment(IterState* st, float* __restrict__ tau_hist,
+                                const float* __restrict__ delta, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int slot = st->dest;
+  if (i < n) tau_hist[(size_t)slot * n + i] = delta[i];
+  if (i == 0) {
+    st->hold = 1;
+    st->final_slot = slot;
+  }
 }
 
 }  // namespace rism

@@ -205,7 +205,8 @@ struct Layout {
   size_t N, half;
   double dkx, dky, dkz, beta, dv;
   AxisPlan px, py, pz;
-  size_t off_state, off_w, off_phi, off_F, off_tau, off_res, off_tref, off_rref, off_dg, off_spec,
+  size_t off_state, off_w, off_phi, off_F, off_tau, off_res, off_tref, off_tlo, off_rref, off_dg,
+      off_spec,
       off_part, off_atoms, off_lj, off_ph, off_chi32, off_chi64, off_q64, off_tw32[3], off_tw64[3],
       off_out, total;
 };
@@ -304,6 +305,7 @@ rism3d_status make_layout(const rism3d_problem* pr, const rism3d_opts* op, Layou
   L->off_tau = take(M * nv * N * sizeof(float));
   L->off_res = take(M * nv * N * sizeof(float));
   L->off_tref = take(nv * N * sizeof(float));
+  L->off_tlo = take(nv * N * sizeof(float));
   L->off_rref = take(nv * N * sizeof(float));
   L->off_dg = take(nv * N * sizeof(float));
   L->off_spec = take((size_t)L->npair * N * sizeof(double2));   // float2 in the bulk iterations
@@ -394,28 +396,28 @@ void launch_potential(const Layout& L, void* ws, double dr, const SiteConsts& sc
 }
 
 template <int NV>
-void launch_contract_nv(const Layout& L, void* ws, bool anchor, float inv_dkt, const int* done,
+void launch_contract_nv(const Layout& L, void* ws, bool anchor, double inv_dkt, const int* done,
                         hipStream_t s) {
   const dim3 grid(blocks_for(L.half, kElemThreads)), block(kElemThreads);
   if (anchor)
     {
       TIMED(F_CONTRACT64, s);
       hipLaunchKernelGGL((k_contract<NV, double2, true>), grid, block, 0, s,
-                         at<double2>(ws, L.off_spec), L.nx, L.ny, L.nz, (float)L.dkx, (float)L.dky,
-                         (float)L.dkz, at<double2>(ws, L.off_F), at<double>(ws, L.off_chi64),
+                         at<double2>(ws, L.off_spec), L.nx, L.ny, L.nz, L.dkx, L.dky,
+                         L.dkz, at<double2>(ws, L.off_F), at<double>(ws, L.off_chi64),
                          at<double>(ws, L.off_q64), inv_dkt, L.m_tab, done);
     }
   else
     {
       TIMED(F_CONTRACT32, s);
       hipLaunchKernelGGL((k_contract<NV, float2, false>), grid, block, 0, s,
-                         at<float2>(ws, L.off_spec), L.nx, L.ny, L.nz, (float)L.dkx, (float)L.dky,
-                         (float)L.dkz, (const float2*)nullptr, at<float>(ws, L.off_chi32),
+                         at<float2>(ws, L.off_spec), L.nx, L.ny, L.nz, L.dkx, L.dky,
+                         L.dkz, (const float2*)nullptr, at<float>(ws, L.off_chi32),
                          (const float*)nullptr, inv_dkt, L.m_tab, done);
     }
 }
 
-void launch_contract(const Layout& L, void* ws, bool anchor, float inv_dkt, const int* done,
+void launch_contract(const Layout& L, void* ws, bool anchor, double inv_dkt, const int* done,
                      hipStream_t s) {
   switch (L.nv) {
     case 1: launch_contract_nv<1>(L, ws, anchor, inv_dkt, done, s); break;
@@ -603,7 +605,7 @@ bool zcz_supported(const Layout& L) {
 }
 
 template <typename C, int NZ, int NV, int B = zcz_cols<C, NZ, NV>()>
-void launch_zcz_b(const Layout& L, void* ws, float inv_dkt, const int* done, hipStream_t s,
+void launch_zcz_b(const Layout& L, void* ws, double inv_dkt, const int* done, hipStream_t s,
                   Batch bt) {
   constexpr bool F64 = std::is_same<C, double2>::value;
   const int tiles_x = (L.nx + B - 1) / B;
@@ -611,8 +613,8 @@ void launch_zcz_b(const Layout& L, void* ws, float inv_dkt, const int* done, hip
   using S = typename ScalarOf<C>::type;
   TIMED(F64 ? F_ZCZ64 : F_ZCZ32, s);
   hipLaunchKernelGGL((k_zcz<C, NZ, NV, F64, B>), grid, block, 0, s, at<C>(ws, L.off_spec), L.nx,
-                     L.ny, at<C>(ws, F64 ? L.off_tw64[2] : L.off_tw32[2]), (float)L.dkx,
-                     (float)L.dky, (float)L.dkz, F64 ? at<C>(ws, L.off_F) : (const C*)nullptr,
+                     L.ny, at<C>(ws, F64 ? L.off_tw64[2] : L.off_tw32[2]), L.dkx,
+                     L.dky, L.dkz, F64 ? at<C>(ws, L.off_F) : (const C*)nullptr,
                      at<S>(ws, F64 ? L.off_chi64 : L.off_chi32),
                      F64 ? at<S>(ws, L.off_q64) : (const S*)nullptr, inv_dkt, L.m_tab, done,
                      bt.stride);
@@ -621,7 +623,7 @@ void launch_zcz_b(const Layout& L, void* ws, float inv_dkt, const int* done, hip
 // FP32 z kernel with a tuned width (cols = 0: default); widths whose tile
 // would exceed 120 KB of LDS are not compiled and fall back to the default.
 template <typename C, int NZ, int NV>
-void launch_zcz_n(const Layout& L, void* ws, float inv_dkt, const int* done, hipStream_t s,
+void launch_zcz_n(const Layout& L, void* ws, double inv_dkt, const int* done, hipStream_t s,
                   Batch bt, int cols = 0) {
   if constexpr (std::is_same<C, float2>::value) {
     constexpr int per_col = 2 * ((NV + 1) / 2) * Lds<NZ>::PITCH * (int)sizeof(C);
@@ -635,7 +637,7 @@ void launch_zcz_n(const Layout& L, void* ws, float inv_dkt, const int* done, hip
 }
 
 template <typename C, int NZ>
-void launch_zcz_nz(const Layout& L, void* ws, float inv_dkt, const int* done, hipStream_t s,
+void launch_zcz_nz(const Layout& L, void* ws, double inv_dkt, const int* done, hipStream_t s,
                    Batch bt, int cols) {
   switch (L.nv) {
     case 1: launch_zcz_n<C, NZ, 1>(L, ws, inv_dkt, done, s, bt, cols); break;
@@ -650,7 +652,7 @@ void launch_zcz_nz(const Layout& L, void* ws, float inv_dkt, const int* done, hi
 }
 
 template <typename C>
-void launch_zcz(const Layout& L, void* ws, float inv_dkt, const int* done, hipStream_t s,
+void launch_zcz(const Layout& L, void* ws, double inv_dkt, const int* done, hipStream_t s,
                 Batch bt, int cols = 0) {
   switch (L.nz) {
     case 64: launch_zcz_nz<C, 64>(L, ws, inv_dkt, done, s, bt, cols); break;
@@ -681,9 +683,9 @@ void launch_fused_l(const Layout& L, void* ws, const rism3d_opts* op, bool first
     }
     hipLaunchKernelGGL(update, grid, block, 0, s, st,
                        at<float>(ws, L.off_tau), at<float>(ws, L.off_res), at<float>(ws, L.off_w),
-                       at<float>(ws, L.off_tref), at<float>(ws, L.off_dg),
-                       at<void>(ws, L.off_spec), L.ny, L.nz, L.nv, L.npair, L.M, kind, order, tw,
-                       bt.stride);
+                       at<float>(ws, L.off_tref), at<float>(ws, L.off_tlo),
+                       at<float>(ws, L.off_dg), at<void>(ws, L.off_spec), L.ny, L.nz, L.nv,
+                       L.npair, L.M, kind, order, tw, bt.stride);
   } else {
     {
       TIMED(ANCHOR ? F_FFTRES64 : F_FFTRES32, s);
@@ -697,9 +699,10 @@ void launch_fused_l(const Layout& L, void* ws, const rism3d_opts* op, bool first
       hipLaunchKernelGGL(residual, grid, block, 0, s, st,
                          at<void>(ws, L.off_spec), at<float>(ws, L.off_w),
                          at<float>(ws, L.off_tau), at<float>(ws, L.off_res),
-                         at<float>(ws, L.off_tref), at<float>(ws, L.off_rref),
-                         at<float>(ws, L.off_dg), L.ny, L.nz, L.nv, L.npair, L.M, kind, order, tw,
-                         at<double>(ws, L.off_part), L.gw, bt.stride);
+                         at<float>(ws, L.off_tref), at<float>(ws, L.off_tlo),
+                         at<float>(ws, L.off_rref), at<float>(ws, L.off_dg), L.ny, L.nz, L.nv,
+                         L.npair, L.M, kind, order, tw, at<double>(ws, L.off_part), L.gw,
+                         bt.stride);
     }
     if (!control) return;
     TIMED(F_CONTROL, s);
@@ -708,7 +711,8 @@ void launch_fused_l(const Layout& L, void* ws, const rism3d_opts* op, bool first
                        dim3(kCtlThreads), 0, s, st,
                        at<double>(ws, L.off_part), (int)grid.x, L.M, inv_count, op->tol,
                        op->max_iter, (float)op->mdiis_eta, op->eta_dynamic,
-                       (int)op->accelerator, op->anderson_s1, op->anderson_s2, bt.stride);
+                       (int)op->accelerator, op->anderson_s1, op->anderson_s2, ANCHOR ? 1 : 0,
+                       bt.stride);
   }
 }
 
@@ -756,7 +760,7 @@ void launch_fused(const Layout& L, void* ws, const rism3d_opts* op, bool first_h
 // One evaluation of the 3D-RISM map plus the MDIIS bookkeeping: update +
 // closure, forward FFT, contraction, inverse FFT, residual + Gram row, control.
 // anchor: FP64 evaluation that re-bases the FP32 increments.
-void launch_iteration(const Layout& L, void* ws, const rism3d_opts* op, float inv_dkt,
+void launch_iteration(const Layout& L, void* ws, const rism3d_opts* op, double inv_dkt,
                       bool anchor, hipStream_t s, Batch bt = {}) {
   IterState* st = at<IterState>(ws, L.off_state);
   const int* done = &st->done;
@@ -800,8 +804,8 @@ void launch_iteration(const Layout& L, void* ws, const rism3d_opts* op, float in
   const dim3 eg(blocks_for(quads, kElemThreads)), eb(kElemThreads);
 #define RISM_UPDATE_ARGS                                                                    \
   st, at<float>(ws, L.off_tau), at<float>(ws, L.off_res), at<float>(ws, L.off_w),     \
-      at<float>(ws, L.off_tref), at<float>(ws, L.off_dg), at<void>(ws, L.off_spec), L.N, L.nv, \
-      L.npair, L.M, kind, order
+      at<float>(ws, L.off_tref), at<float>(ws, L.off_tlo), at<float>(ws, L.off_dg),           \
+      at<void>(ws, L.off_spec), L.N, L.nv, L.npair, L.M, kind, order
   {
     TIMED(anchor ? F_UPDATE64 : F_UPDATE32, s);
     if (anchor && v4) hipLaunchKernelGGL((k_update_closure<true, 4>), eg, eb, 0, s, RISM_UPDATE_ARGS);
@@ -819,9 +823,9 @@ void launch_iteration(const Layout& L, void* ws, const rism3d_opts* op, float in
   if (nblk > (unsigned)kRedBlocks) nblk = kRedBlocks;
 #define RISM_RESID_ARGS                                                                       \
   st, at<void>(ws, L.off_spec), at<float>(ws, L.off_w), at<float>(ws, L.off_tau),             \
-      at<float>(ws, L.off_res), at<float>(ws, L.off_tref), at<float>(ws, L.off_rref),         \
-      at<float>(ws, L.off_dg), L.N, L.nv, L.npair, L.M, kind, order, at<double>(ws, L.off_part), \
-      L.gw
+      at<float>(ws, L.off_res), at<float>(ws, L.off_tref), at<float>(ws, L.off_tlo),          \
+      at<float>(ws, L.off_rref), at<float>(ws, L.off_dg), L.N, L.nv, L.npair, L.M, kind, order,  \
+      at<double>(ws, L.off_part), L.gw
   {
     TIMED(anchor ? F_RESIDUAL64 : F_RESIDUAL32, s);
     const dim3 rg(nblk), rb(kRedThreads);
@@ -838,7 +842,7 @@ void launch_iteration(const Layout& L, void* ws, const rism3d_opts* op, float in
                        dim3(kCtlThreads), 0, s, st, at<double>(ws, L.off_part),
                        (int)nblk, L.M, inv_count, op->tol, op->max_iter, (float)op->mdiis_eta,
                        op->eta_dynamic, (int)op->accelerator, op->anderson_s1, op->anderson_s2,
-                       (size_t)0);
+                       anchor ? 1 : 0, (size_t)0);
   }
 }
 
@@ -888,15 +892,15 @@ hipStream_t capture_stream() {
   return streams[dev];
 }
 
-std::string graph_key(const Layout& L, const void* ws, const rism3d_opts* op, float inv_dkt,
+std::string graph_key(const Layout& L, const void* ws, const rism3d_opts* op, double inv_dkt,
                       int every, Batch bt) {
   char buf[512];
   snprintf(buf, sizeof(buf),
-           "%p|%zu|%d,%d,%d,%d,%d,%d|%d,%d,%.17g,%d,%.17g,%d,%d|%a|%d|%d,%zu|%d,%a,%a,%a",
+           "%p|%zu|%d,%d,%d,%d,%d,%d|%d,%d,%.17g,%d,%.17g,%d,%d|%a|%d|%d,%zu|%d,%a,%a|%a,%a,%a",
            ws, L.total, L.nx, L.ny, L.nz, L.nv, L.M, L.m_tab, (int)op->closure, op->pse_order,
-           op->tol, op->max_iter, op->mdiis_eta, op->eta_dynamic, every, (double)inv_dkt,
+           op->tol, op->max_iter, op->mdiis_eta, op->eta_dynamic, every, inv_dkt,
            g_timer.on ? g_timer.only : -2, bt.nb, bt.stride, (int)op->accelerator,
-           op->anderson_s1, op->anderson_s2, 0.0);
+           op->anderson_s1, op->anderson_s2, L.dkx, L.dky, L.dkz);
   std::string key = buf;
   for (int g = 0; g < kMaxSites; ++g) {   // Gram weights are kernel arguments too
     snprintf(buf, sizeof(buf), ",%a", (double)L.gw.w[g]);
@@ -914,7 +918,7 @@ void drop_graph(GraphEntry* e) {
   delete e;
 }
 
-GraphEntry* graph_for(const Layout& L, void* ws, const rism3d_opts* op, float inv_dkt, int every,
+GraphEntry* graph_for(const Layout& L, void* ws, const rism3d_opts* op, double inv_dkt, int every,
                       hipStream_t s, Batch bt = {}) {
   const std::string key = graph_key(L, ws, op, inv_dkt, every, bt);
   std::lock_guard<std::mutex> lock(g_graph_mu);
@@ -1028,8 +1032,8 @@ void launch_sfe(const rism3d_problem* pr, const rism3d_opts* op, const Layout& L
     TIMED(F_SFE, s);
     hipLaunchKernelGGL(k_sfe_partial, dim3(nblk), dim3(kRedThreads), 0, s,
                        at<IterState>(ws, L.off_state), at<float>(ws, L.off_tau),
-                       at<float>(ws, L.off_tref), at<float>(ws, L.off_w), at<float>(ws, L.off_phi),
-                       L.N, L.nv,
+                       at<float>(ws, L.off_tref), at<float>(ws, L.off_tlo), at<float>(ws, L.off_w),
+                       at<float>(ws, L.off_phi), L.N, L.nv,
                        (int)op->closure, order_of(op), sc, at<double>(ws, L.off_part));
   }
   const double scale = L.dv / L.beta;   // k_B T dV
@@ -1068,7 +1072,7 @@ void fill_thermo(const double* res, const rism3d_problem* pr, rism3d_thermo_out*
 // ---------------------------------------------------------------------------
 struct BatchGroup {
   Layout L;                  // layout of the first member, total = the stride
-  float inv_dkt = 0.0f;
+  double inv_dkt = 0.0f;
   bool batched = false;
   size_t off = 0, stride = 0;
   std::vector<int> members;  // indices into the problem array
@@ -1110,7 +1114,7 @@ rism3d_status batch_plan(int n, const rism3d_problem* prs, const rism3d_opts* op
     const rism3d_status st = make_layout(&prs[i], op, &L);
     if (st != RISM3D_OK)
       return fail(st, "batch member %d: %s", i, g_error.c_str());
-    const float inv_dkt = (float)(1.0 / prs[i].dk);
+    const double inv_dkt = (1.0 / prs[i].dk);
     BatchGroup* hit = nullptr;
     if (batchable(L))
       for (BatchGroup& g : *groups)
@@ -1163,13 +1167,15 @@ __global__ void k_net_input(const float* __restrict__ w, const float* __restrict
 
 // c_sr = g - 1 - tau of the accepted iterate (FP64 closure).
 __global__ void k_csr_out(const IterState* __restrict__ st, const float* __restrict__ tau_hist,
-                          const float* __restrict__ tau_ref, const float* __restrict__ w, size_t N,
-                          int nv, int kind, int order, float* __restrict__ c) {
+                          const float* __restrict__ tau_ref, const float* __restrict__ tau_lo,
+                          const float* __restrict__ w, size_t N, int nv, int kind, int order,
+                          float* __restrict__ c) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (size_t)nv * N) return;
   const int slot = st->final_slot;
   if (slot < 0) return;
-  const double tau = (double)tau_ref[idx] + (double)tau_hist[(size_t)slot * nv * N + idx];
+  const double tau = ((double)tau_ref[idx] + (double)tau_lo[idx]) +
+                     (double)tau_hist[(size_t)slot * nv * N + idx];
   c[idx] = (float)(closure_g(-(double)w[idx] + tau, kind, order) - 1.0 - tau);
 }
 
@@ -1214,6 +1220,7 @@ __global__ void k_tune_state(IterState* st, int M, float eta) {
   st->converged = 0;
   st->status = 0;
   st->final_slot = -1;
+  st->hold = 0;
 }
 
 template <int NV>
@@ -1269,7 +1276,7 @@ rism3d_status rism3d_solve(const rism3d_problem* pr, const rism3d_opts* op, cons
   HIP_TRY(hipStreamSynchronize(s));
   if (host.prepared != kPreparedMagic)
     return fail(RISM3D_E_WORKSPACE, "workspace not prepared: call rism3d_potential first");
-  const float inv_dkt = (float)(1.0 / pr->dk);
+  const double inv_dkt = (1.0 / pr->dk);
   // A caller's starting tau is only a starting point: if the iteration from
   // it ends on a non-finite residual, the solve is repeated from tau0 = 0.
   for (int attempt = 0; attempt < 2; ++attempt) {
@@ -1278,7 +1285,8 @@ rism3d_status rism3d_solve(const rism3d_problem* pr, const rism3d_opts* op, cons
                      t0 ? 1 : 0);
   hipLaunchKernelGGL(k_init_tau, dim3(blocks_for((size_t)L.nv * L.N, kElemThreads)),
                      dim3(kElemThreads), 0, s, t0, at<float>(ws, L.off_tau),
-                     at<float>(ws, L.off_tref), (size_t)L.nv * L.N);
+                     at<float>(ws, L.off_tref), at<float>(ws, L.off_tlo),
+                     (size_t)L.nv * L.N);
   LAUNCH_CHECK();
   const int every = op->anchor_every > 0 ? op->anchor_every : kDefaultAnchorEvery;
   // One anchor period (an FP64 anchor evaluation + every-1 FP32 increments) is
@@ -1288,15 +1296,18 @@ rism3d_status rism3d_solve(const rism3d_problem* pr, const rism3d_opts* op, cons
   const int chunk = graph ? every : (op->check_every > 0 ? op->check_every : kDefaultCheckEvery);
   int launched = 0;
   int iter_before = 0;
+  int phase = 0;   // direct launches: iterations since the last FP64 anchor
   for (;;) {
     if (graph) {
-      HIP_TRY(hipGraphLaunch(graph->exec, s));
+      HIP_TRY(hipGraphLaunch(graph->exec, s));   // an anchor period starts with the anchor
       launched += every;
     } else {
-      const int todo = (op->max_iter - launched) < chunk ? (op->max_iter - launched) : chunk;
+      int todo = (op->max_iter - launched) < chunk ? (op->max_iter - launched) : chunk;
+      if (todo < 1) todo = 1;   // past max_iter only while a verification is pending
       for (int k = 0; k < todo; ++k) {
         g_iter_tag = k;
-        launch_iteration(L, ws, op, inv_dkt, ((launched + k) % every) == 0, s);
+        launch_iteration(L, ws, op, inv_dkt, phase == 0, s);
+        phase = (phase + 1) % every;
       }
       g_iter_tag = -1;
       launched += todo;
@@ -1310,14 +1321,22 @@ rism3d_status rism3d_solve(const rism3d_problem* pr, const rism3d_opts* op, cons
       g_timer.harvest(executed);
     }
     iter_before = host.iter;
-    if (host.done || launched >= op->max_iter) break;
+    if (host.done == kDoneFinished) break;
+    // An FP32 residual passed the tolerance: the next FP64 evaluation decides
+    // (every evaluation counts towards max_iter, so this ends).
+    if (host.done == kDoneVerify) {
+      phase = 0;
+      continue;
+    }
+    if (launched >= op->max_iter) break;
   }
   if (!(t0 && host.status == RISM3D_E_NONFINITE)) break;
   }
   if (g_out) {
     hipLaunchKernelGGL(k_output, dim3(blocks_for((size_t)L.nv * L.N, kElemThreads)),
                        dim3(kElemThreads), 0, s, dst, at<float>(ws, L.off_tau),
-                       at<float>(ws, L.off_tref), at<float>(ws, L.off_w), L.N, L.nv,
+                       at<float>(ws, L.off_tref), at<float>(ws, L.off_tlo),
+                       at<float>(ws, L.off_w), L.N, L.nv,
                        (int)op->closure, order_of(op), g_out, (float*)nullptr);
     LAUNCH_CHECK();
   }
@@ -1327,7 +1346,8 @@ rism3d_status rism3d_solve(const rism3d_problem* pr, const rism3d_opts* op, cons
     info->restarts = host.restarts;
     info->warm_start_used = host.warm;
   }
-  if (!host.done) return fail(RISM3D_E_NOCONV, "no convergence in %d iterations", host.iter);
+  if (host.done != kDoneFinished)
+    return fail(RISM3D_E_NOCONV, "no convergence in %d iterations", host.iter);
   if (host.status == RISM3D_E_NONFINITE)
     return fail(RISM3D_E_NONFINITE, "non-finite residual at iteration %d", host.iter);
   if (host.status == RISM3D_E_NOCONV)
@@ -1460,7 +1480,8 @@ rism3d_status rism3d_solve_batch(int n, const rism3d_problem* prs, const rism3d_
                          (float)op->mdiis_eta, t0 ? 1 : 0);
       hipLaunchKernelGGL(k_init_tau, dim3(blocks_for((size_t)L.nv * L.N, kElemThreads)),
                          dim3(kElemThreads), 0, s, t0, at<float>(w, L.off_tau),
-                         at<float>(w, L.off_tref), (size_t)L.nv * L.N);
+                         at<float>(w, L.off_tref), at<float>(w, L.off_tlo),
+                         (size_t)L.nv * L.N);
       LAUNCH_CHECK();
     }
   const int every = op->anchor_every > 0 ? op->anchor_every : kDefaultAnchorEvery;
@@ -1474,7 +1495,7 @@ rism3d_status rism3d_solve_batch(int n, const rism3d_problem* prs, const rism3d_
       graphs[k] = graph_for(g.L, member_ws(g, 0), op, g.inv_dkt, every, s, batches[k]);
   }
   const int chunk_direct = op->check_every > 0 ? op->check_every : kDefaultCheckEvery;
-  std::vector<int> launched(ng, 0), iter_before(n, 0);
+  std::vector<int> launched(ng, 0), iter_before(n, 0), phase(ng, 0);
   std::vector<char> finished(ng, 0);
   std::vector<IterState> host(n);
   IterState* table = at<IterState>(ws, plan.off_table);
@@ -1489,11 +1510,12 @@ rism3d_status rism3d_solve_batch(int n, const rism3d_problem* prs, const rism3d_
           launched[k] += every;
         } else {
           const int left = op->max_iter - launched[k];
-          const int todo = left < chunk_direct ? left : chunk_direct;
+          int todo = left < chunk_direct ? left : chunk_direct;
+          if (todo < 1) todo = 1;   // past max_iter only while a verification is pending
           for (int j = 0; j < todo; ++j) {
             g_iter_tag = j;
-            launch_iteration(g.L, member_ws(g, 0), op, g.inv_dkt,
-                             ((launched[k] + j) % every) == 0, s, batches[k]);
+            launch_iteration(g.L, member_ws(g, 0), op, g.inv_dkt, phase[k] == 0, s, batches[k]);
+            phase[k] = (phase[k] + 1) % every;
           }
           g_iter_tag = -1;
           launched[k] += todo;
@@ -1512,15 +1534,19 @@ rism3d_status rism3d_solve_batch(int n, const rism3d_problem* prs, const rism3d_
     for (size_t k = 0; k < ng; ++k) {
       if (finished[k]) continue;
       const BatchGroup& g = plan.groups[k];
-      bool done = true;
+      bool done = true, verify = false;
       int executed = 0;
       for (int i : g.members) {
-        done = done && host[i].done;
+        done = done && host[i].done == kDoneFinished;
+        verify = verify || host[i].done == kDoneVerify;
         executed = std::max(executed, host[i].iter - iter_before[i]);
         iter_before[i] = host[i].iter;
       }
       if (g_timer.on && graphs[k]) graphs[k]->harvest(executed);
-      if (done || launched[k] >= op->max_iter) finished[k] = 1;
+      // a member whose FP32 residual passed waits for the next FP64 evaluation
+      // (the start of an anchor period), also past max_iter
+      if (verify) phase[k] = 0;
+      if (done || (launched[k] >= op->max_iter && !verify)) finished[k] = 1;
       all = all && finished[k];
     }
     if (g_timer.on) g_timer.harvest();
@@ -1541,6 +1567,7 @@ rism3d_status rism3d_solve_batch(int n, const rism3d_problem* prs, const rism3d_
         hipLaunchKernelGGL(k_output, dim3(blocks_for((size_t)L.nv * L.N, kElemThreads)),
                            dim3(kElemThreads), 0, s, at<IterState>(w, L.off_state),
                            at<float>(w, L.off_tau), at<float>(w, L.off_tref),
+                           at<float>(w, L.off_tlo),
                            at<float>(w, L.off_w), L.N, L.nv, (int)op->closure, order_of(op),
                            g_out[i], (float*)nullptr);
       if (thermo && h.final_slot >= 0) {
@@ -1550,7 +1577,7 @@ rism3d_status rism3d_solve_batch(int n, const rism3d_problem* prs, const rism3d_
       }
       LAUNCH_CHECK();
       rism3d_status ms = RISM3D_OK;
-      if (!h.done || h.status == RISM3D_E_NOCONV) ms = RISM3D_E_NOCONV;
+      if (h.done != kDoneFinished || h.status == RISM3D_E_NOCONV) ms = RISM3D_E_NOCONV;
       if (h.status == RISM3D_E_NONFINITE) ms = RISM3D_E_NONFINITE;
       if (info) {
         info[i].iterations = h.iter;
@@ -1588,7 +1615,8 @@ rism3d_status rism3d_get_tau(const rism3d_problem* pr, const rism3d_opts* op, co
   void* ws = const_cast<void*>(ws_c);
   hipLaunchKernelGGL(k_output, dim3(blocks_for((size_t)L.nv * L.N, kElemThreads)),
                      dim3(kElemThreads), 0, s, at<IterState>(ws, L.off_state),
-                     at<float>(ws, L.off_tau), at<float>(ws, L.off_tref), at<float>(ws, L.off_w),
+                     at<float>(ws, L.off_tau), at<float>(ws, L.off_tref),
+                     at<float>(ws, L.off_tlo), at<float>(ws, L.off_w),
                      L.N, L.nv, (int)op->closure, order_of(op), (float*)nullptr, d_tau);
   LAUNCH_CHECK();
   return RISM3D_OK;
@@ -1600,24 +1628,70 @@ rism3d_status rism3d_map(const rism3d_problem* pr, const rism3d_opts* op, const 
   rism3d_status st = make_layout(pr, op, &L);
   if (st != RISM3D_OK) return st;
   if ((st = check_ws(L, ws, ws_bytes)) != RISM3D_OK) return st;
-  if (!d_tau || !d_res) return fail(RISM3D_E_ARG, "null tau or residual");
+  if (!d_res) return fail(RISM3D_E_ARG, "null residual");
   IterState* dst = at<IterState>(ws, L.off_state);
   IterState host;
   HIP_TRY(hipMemcpyAsync(&host, dst, sizeof(IterState), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   if (host.prepared != kPreparedMagic)
     return fail(RISM3D_E_WORKSPACE, "workspace not prepared: call rism3d_potential first");
+  if (!d_tau && host.final_slot < 0)
+    return fail(RISM3D_E_WORKSPACE, "no solution in the workspace: call rism3d_solve first");
   rism3d_opts one = *op;
   one.max_iter = 1;
   one.tol = 0.0;   // never "converged": the single evaluation always runs to the end
-  hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1), 0, s, dst, (float)op->mdiis_eta, 1);
-  hipLaunchKernelGGL(k_init_tau, dim3(blocks_for((size_t)L.nv * L.N, kElemThreads)),
-                     dim3(kElemThreads), 0, s, d_tau, at<float>(ws, L.off_tau),
-                     at<float>(ws, L.off_tref), (size_t)L.nv * L.N);
-  launch_iteration(L, ws, &one, (float)(1.0 / pr->dk), true, s);
+  if (d_tau) {
+    hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1), 0, s, dst, (float)op->mdiis_eta, 1);
+    hipLaunchKernelGGL(k_init_tau, dim3(blocks_for((size_t)L.nv * L.N, kElemThreads)),
+                       dim3(kElemThreads), 0, s, d_tau, at<float>(ws, L.off_tau),
+                       at<float>(ws, L.off_tref), at<float>(ws, L.off_tlo),
+                       (size_t)L.nv * L.N);
+  } else {
+    // the held iterate; its evaluation re-bases the reference on that same
+    // iterate, so the solution stays in place for rism3d_thermo and the outputs
+    hipLaunchKernelGGL(k_hold_final, dim3(1), dim3(1), 0, s, dst);
+  }
+  launch_iteration(L, ws, &one, (1.0 / pr->dk), true, s);
   const size_t n = (size_t)L.nv * L.N;
-  hipLaunchKernelGGL(k_copy_floats, dim3(blocks_for(n, kElemThreads)), dim3(kElemThreads), 0, s,
-                     at<float>(ws, L.off_res), d_res, n);   // slot 0 holds R
+  hipLaunchKernelGGL(k_copy_final_slot, dim3(blocks_for(n, kElemThreads)), dim3(kElemThreads), 0,
+                     s, dst, at<float>(ws, L.off_res), d_res, n);
+  LAUNCH_CHECK();
+  HIP_TRY(hipMemcpyAsync(&host, dst, sizeof(IterState), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (rms) *rms = host.last_rms;
+  g_error.clear();
+  return RISM3D_OK;
+}
+
+rism3d_status rism3d_map_increment(const rism3d_problem* pr, const rism3d_opts* op,
+                                   const float* d_tau_ref, const float* d_delta, void* ws,
+                                   size_t ws_bytes, float* d_res, double* rms, hipStream_t s) {
+  Layout L;
+  rism3d_status st = make_layout(pr, op, &L);
+  if (st != RISM3D_OK) return st;
+  if ((st = check_ws(L, ws, ws_bytes)) != RISM3D_OK) return st;
+  if (!d_tau_ref || !d_delta || !d_res) return fail(RISM3D_E_ARG, "null tau_ref, delta or residual");
+  IterState* dst = at<IterState>(ws, L.off_state);
+  IterState host;
+  HIP_TRY(hipMemcpyAsync(&host, dst, sizeof(IterState), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (host.prepared != kPreparedMagic)
+    return fail(RISM3D_E_WORKSPACE, "workspace not prepared: call rism3d_potential first");
+  rism3d_opts two = *op;
+  two.max_iter = 3;   // neither evaluation may end the iteration
+  two.tol = 0.0;
+  const size_t n = (size_t)L.nv * L.N;
+  const double inv_dkt = 1.0 / pr->dk;
+  hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1), 0, s, dst, (float)op->mdiis_eta, 1);
+  hipLaunchKernelGGL(k_init_tau, dim3(blocks_for(n, kElemThreads)), dim3(kElemThreads), 0, s,
+                     d_tau_ref, at<float>(ws, L.off_tau), at<float>(ws, L.off_tref),
+                     at<float>(ws, L.off_tlo), n);
+  launch_iteration(L, ws, &two, inv_dkt, true, s);    // FP64: R_ref at tau_ref
+  hipLaunchKernelGGL(k_set_increment, dim3(blocks_for(n, kElemThreads)), dim3(kElemThreads), 0, s,
+                     dst, at<float>(ws, L.off_tau), d_delta, n);
+  launch_iteration(L, ws, &two, inv_dkt, false, s);   // FP32: R_ref + dh - dg
+  hipLaunchKernelGGL(k_copy_final_slot, dim3(blocks_for(n, kElemThreads)), dim3(kElemThreads), 0,
+                     s, dst, at<float>(ws, L.off_res), d_res, n);
   LAUNCH_CHECK();
   HIP_TRY(hipMemcpyAsync(&host, dst, sizeof(IterState), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -1828,7 +1902,7 @@ rism3d_status rism3d_csr(const rism3d_problem* pr, const rism3d_opts* op, const 
   hipLaunchKernelGGL(k_csr_out, dim3(blocks_for((size_t)L.nv * L.N, kElemThreads)),
                      dim3(kElemThreads), 0, s, at<IterState>(ws_c, L.off_state),
                      at<float>(ws_c, L.off_tau), at<float>(ws_c, L.off_tref),
-                     at<float>(ws_c, L.off_w), L.N, L.nv,
+                     at<float>(ws_c, L.off_tlo), at<float>(ws_c, L.off_w), L.N, L.nv,
                      (int)op->closure, order_of(op), d_c);
   LAUNCH_CHECK();
   return RISM3D_OK;
@@ -1847,7 +1921,7 @@ rism3d_status rism3d_oz_half_step(const rism3d_problem* pr, const rism3d_opts* o
                      dim3(kElemThreads), 0, s, d_c0, L.N, L.nv, (double)c_scale,
                      at<double2>(ws, L.off_spec));
   launch_fft3<double2>(L, ws, 1, nullptr, s);
-  launch_contract(L, ws, true, (float)(1.0 / pr->dk), nullptr, s);
+  launch_contract(L, ws, true, (1.0 / pr->dk), nullptr, s);
   launch_fft3<double2>(L, ws, 0, nullptr, s);
   hipLaunchKernelGGL(k_tau_from_h, dim3(blocks_for((size_t)L.nv * L.N, kElemThreads)),
                      dim3(kElemThreads), 0, s, at<double2>(ws, L.off_spec), d_c0, L.N, L.nv,
@@ -1897,7 +1971,7 @@ rism3d_status rism3d_autotune(const rism3d_problem* pr, const rism3d_opts* op, v
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
-  const float inv_dkt = (float)(1.0 / pr->dk);
+  const double inv_dkt = (1.0 / pr->dk);
   constexpr int kReps = 10;
   auto time_us = [&](auto&& launch) -> double {
     for (int r = 0; r < 2; ++r) launch();

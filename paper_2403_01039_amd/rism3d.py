@@ -96,6 +96,8 @@ def _load():
         "rism3d_get_tau": (ctypes.c_int, [P(Problem), P(Opts), vp, sz, vp, st]),
         "rism3d_map": (ctypes.c_int, [P(Problem), P(Opts), vp, vp, sz, vp,
                                       P(ctypes.c_double), st]),
+        "rism3d_map_increment": (ctypes.c_int, [P(Problem), P(Opts), vp, vp, vp, sz, vp,
+                                                P(ctypes.c_double), st]),
         "rism3d_get_potential": (ctypes.c_int, [P(Problem), P(Opts), vp, sz, vp, vp, st]),
         "rism3d_transform_workspace_bytes": (sz, [ctypes.c_int] * 3),
         "rism3d_transform": (ctypes.c_int, [ctypes.c_int] * 4 + [vp, ctypes.c_int, vp, sz, st]),
@@ -144,7 +146,7 @@ def _load():
 LIB = _load()
 EXPORTED = ("rism3d_workspace_bytes", "rism3d_potential", "rism3d_solve", "rism3d_thermo",
             "rism3d_sfe_gradient",
-            "rism3d_get_tau", "rism3d_map", "rism3d_get_potential",
+            "rism3d_get_tau", "rism3d_map", "rism3d_map_increment", "rism3d_get_potential",
             "rism3d_transform_workspace_bytes", "rism3d_transform", "rism3d_timing_enable",
             "rism3d_timing_reset", "rism3d_timing_read", "rism3d_use_graphs",
             "rism3d_release_graphs", "rism3d_timing_select",
@@ -341,10 +343,19 @@ def rism3d_get_tau(dp, opts, ws, tau_out, stream=None):
 
 
 def rism3d_map(dp, opts, ws, tau, res_out, stream=None) -> float:
+    """tau None: the iterate the last solve on ws returned, as it is held."""
     rms = ctypes.c_double()
     _check(LIB.rism3d_map(ctypes.byref(dp.struct), ctypes.byref(opts), _ptr(tau), _ptr(ws),
                           ws.numel() * ws.element_size(), _ptr(res_out), ctypes.byref(rms),
                           _stream(stream)))
+    return rms.value
+
+
+def rism3d_map_increment(dp, opts, ws, tau_ref, delta, res_out, stream=None) -> float:
+    rms = ctypes.c_double()
+    _check(LIB.rism3d_map_increment(ctypes.byref(dp.struct), ctypes.byref(opts), _ptr(tau_ref),
+                                    _ptr(delta), _ptr(ws), ws.numel() * ws.element_size(),
+                                    _ptr(res_out), ctypes.byref(rms), _stream(stream)))
     return rms.value
 
 
@@ -599,7 +610,16 @@ class Solver:
         rism3d_get_potential(self.dp, self.opts, self.ws, w, phi)
         return w, phi
 
-    def map(self, tau: torch.Tensor):
+    def map(self, tau: Optional[torch.Tensor]):
+        """Exact evaluation of the map at tau (None: at the held solution)."""
         res = torch.empty(self.dp.shape, dtype=torch.float32, device=self.ws.device)
-        rms = rism3d_map(self.dp, self.opts, self.ws, tau.contiguous(), res)
+        rms = rism3d_map(self.dp, self.opts, self.ws, None if tau is None else tau.contiguous(),
+                         res)
+        return res, rms
+
+    def map_increment(self, tau_ref: torch.Tensor, delta: torch.Tensor):
+        """The map at tau_ref + delta through the FP32 increment kernels."""
+        res = torch.empty(self.dp.shape, dtype=torch.float32, device=self.ws.device)
+        rms = rism3d_map_increment(self.dp, self.opts, self.ws, tau_ref.contiguous(),
+                                   delta.contiguous(), res)
         return res, rms
