@@ -31,11 +31,15 @@ PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 
 
 def kernel_bytes(nv: int, N: int, M: int, m_avg: float, fam: str) -> float:
-    """Algorithmic HBM bytes of one launch of a kernel family (FP32 = 4 B,
-    complex FP32 = 8 B, complex FP64 = 16 B; P = ceil(nv/2) packed pairs)."""
+    """Algorithmic HBM bytes of one launch of a kernel family: the bytes the
+    method's steps move (FP32 = 4 B, complex FP32 = 8 B, complex FP64 = 16 B;
+    P = ceil(nv/2) packed pairs).  For the fused update + closure + forward x
+    transform: read the m_avg stored tau_i and R_i and w, write the new tau and
+    the packed spectra.  The FP32 increment scheme moves more than that (see
+    increment_overhead_bytes)."""
     P = (nv + 1) // 2
-    if fam == "update_closure_f32":   # read m tau_i, m R_i, w, tau_ref; write tau, dg; write spectra
-        return nv * N * 4 * (2 * m_avg + 4) + 8 * P * N
+    if fam == "update_closure_f32":   # read m tau_i, m R_i, w; write tau; write spectra
+        return nv * N * 4 * (2 * m_avg + 2) + 8 * P * N
     if fam == "update_closure_f64":   # read m tau_i, m R_i, w, tau_ref; write tau; FP64 spectra
         return nv * N * 4 * (2 * m_avg + 3) + 16 * P * N
     if fam.startswith("fft_") and fam.endswith("_f32") or fam in ("contract_f32",
@@ -45,7 +49,7 @@ def kernel_bytes(nv: int, N: int, M: int, m_avg: float, fam: str) -> float:
                                                                    "zfft_contract_f64"):
         return 32 * P * N
     if fam == "update_fftx_f32":      # update + closure, spectra written once after the x pass
-        return nv * N * 4 * (2 * m_avg + 4) + 8 * P * N
+        return nv * N * 4 * (2 * m_avg + 2) + 8 * P * N
     if fam == "update_fftx_f64":
         return nv * N * 4 * (2 * m_avg + 3) + 16 * P * N
     if fam == "fftx_residual_f32":    # spectra read once, then the residual + Gram row
@@ -58,6 +62,35 @@ def kernel_bytes(nv: int, N: int, M: int, m_avg: float, fam: str) -> float:
         # delta, tau_ref, R_ref; read and write the other (m-1) stored deltas
         return 16 * P * N + nv * N * 4 * (7 + 3 * max(m_avg - 1, 0))
     return 0.0
+
+
+def increment_overhead_bytes(nv: int, N: int, fam: str) -> float:
+    """Bytes a launch moves beyond the method's because the FP32 iterations
+    transform increments over an FP64 anchor: the update reads the reference
+    tau_ref and writes the closure increment dg (read back by the residual in
+    place of tau and w, so the residual's count is unchanged)."""
+    if fam in ("update_fftx_f32", "update_closure_f32"):
+        return 8.0 * nv * N
+    return 0.0
+
+
+ITERATION_FAMILIES = ("update_fftx_f32", "fft_y_f32", "zfft_contract_f32", "fftx_residual_f32",
+                      "update_closure_f32", "fft_x_f32", "fft_z_f32", "contract_f32",
+                      "residual_gram_f32")
+
+
+def host_cpu():
+    """CPU model and logical CPU count of the host the benchmark runs on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
 
 
 def source_digest() -> str:
@@ -109,14 +142,30 @@ def cpu_baseline(prob, chi, dk, iterations: int):
             O.rism_map(system, t)
         t_map = (time.perf_counter() - t0) / 3
         wall = time.perf_counter() - t_start
+        # a measured point: the whole 64^3 single-site solve (potential,
+        # spectrum, chi, MDIIS iterations to rms 1e-6, SFE)
+        c0 = inputs.single_site_problem()
+        chi0, dk0 = inputs.solvent_table_for(c0.solvent)
+        t0 = time.perf_counter()
+        sol0 = O.solve(O.build_system(c0, chi0, dk0))
+        O.sfe(sol0)
+        t_c0 = time.perf_counter() - t0
     per_solve = t_pot + t_ft + t_chi + iterations * t_map
+    model, nproc = host_cpu()
     return {
         "value": 1.0 / per_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
+        "extrapolated": True,
         "sample": (f"FP64 numpy oracle, 1 thread: potential on 1/16 of the grid points (x16), "
                    f"long-range spectrum for 1/4 of the atoms (x4), chi interpolation, and the "
                    f"full-size map evaluation (mean of 3: {t_map:.2f} s) x {iterations} "
-                   f"iterations; {wall:.1f} s of CPU work"),
+                   f"iterations (the GPU's count; the oracle's MDIIS step itself not timed); "
+                   f"{wall - t_c0:.1f} s of CPU work"),
         "seconds_per_solve": per_solve,
+        "host_cpu": model, "host_nproc": nproc,
+        "measured_c0": {"workload": "single_site: 1 LJ site in 3-site water, 64^3 at 0.5 A, KH, "
+                                    "MDIIS 5, rms 1e-6, whole solve",
+                        "seconds": t_c0, "solves_per_s": 1.0 / t_c0,
+                        "iterations": int(sol0.iterations), "cores": 1},
     }
 
 
@@ -250,7 +299,35 @@ def warm_start_comparison(R, inputs, n_seeds: int):
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         out[name] = {"solves_per_s": len(dps) / el, "iterations_mean": float(np.mean(its))}
+    # the warm-started batched solver: per member the potential and the
+    # network's tau0 on a single workspace, then the members in
+    # rism3d_solve_batch calls of up to `chunk` (which repeat each potential)
+    chunk = 50
+    bws = R.alloc_workspace(R.rism3d_batch_workspace_bytes(dps[:chunk], opts))
+    taus = [torch.empty(dps[0].shape, dtype=torch.float32, device="cuda")
+            for _ in range(min(chunk, len(dps)))]
+
+    def warm_batch(group):
+        for dp, t in zip(group, taus):
+            R.rism3d_potential(dp, opts, ws)
+            net.tau0(dp, opts, ws, t)
+        infos, _ = R.rism3d_solve_batch(group, opts, bws, tau0=taus[:len(group)])
+        return [i.iterations for i in infos]
+
+    warm_batch(dps[:min(chunk, len(dps))])   # warm-up (graph capture)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = []
+    for i in range(0, len(dps), chunk):
+        its += warm_batch(dps[i:i + chunk])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out["warm_batch"] = {"solves_per_s": len(dps) / el, "iterations_mean": float(np.mean(its)),
+                         "batch_size": chunk}
+    del bws
     out["speedup"] = out["warm"]["solves_per_s"] / out["plain"]["solves_per_s"]
+    out["speedup_warm_batch_vs_plain"] = (out["warm_batch"]["solves_per_s"]
+                                          / out["plain"]["solves_per_s"])
     out["speedup_warm_anderson_vs_plain_mdiis"] = (out["warm_anderson"]["solves_per_s"]
                                                   / out["plain"]["solves_per_s"])
     out["workload"] = (f"warm_start: held-out seeds {seeds[0]}..{seeds[-1]}, 200-atom solutes in "
@@ -307,12 +384,38 @@ def batch_comparison(R, inputs, count: int):
     infos, _ = R.rism3d_solve_batch(dps, opts, ws)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    del ws
+    # the same problems one after another (potential + solve + SFE each, one
+    # workspace per grid, graphs captured in a warm-up pass)
+    one = {}
+    for dp in dps:
+        if dp.shape not in one:
+            one[dp.shape] = R.alloc_workspace(R.rism3d_workspace_bytes(dp, opts))
+
+    def single(dp):
+        w = one[dp.shape]
+        R.rism3d_potential(dp, opts, w)
+        info = R.rism3d_solve(dp, opts, w)
+        R.rism3d_thermo(dp, opts, w)
+        return info
+
+    for shape in one:
+        single(next(d for d in dps if d.shape == shape))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = [single(dp).iterations for dp in dps]
+    torch.cuda.synchronize()
+    el_seq = time.perf_counter() - t0
     sizes = [p.grid.nx for p in probs]
     return {"solves_per_s": count / el, "seconds": el,
             "iterations_mean": sum(i.iterations for i in infos) / count,
+            "sequential_solves_per_s": count / el_seq, "sequential_seconds": el_seq,
+            "sequential_iterations_mean": sum(its) / count,
+            "speedup_vs_sequential": el_seq / el,
             "workload": (f"batch_uneven: {count} solutes (seeds 1000..{999 + count}), "
                          f"{sizes.count(96)} x 96^3 + {sizes.count(128)} x 128^3, water, KH, "
-                         f"MDIIS 5, rms 1e-6, one rism3d_solve_batch call")}
+                         f"MDIIS 5, rms 1e-6, one rism3d_solve_batch call vs the same solves "
+                         f"one by one")}
 
 
 def gradient_leg(R, prob, solver, stream, reps: int):
@@ -358,7 +461,7 @@ def main():
                     help="solutes of the batched-solve leg (0: skip)")
     ap.add_argument("--anderson-steps", type=int, default=2,
                     help="solves of the headline workload with modified Anderson (0: skip)")
-    ap.add_argument("--warm-seeds", type=int, default=8,
+    ap.add_argument("--warm-seeds", type=int, default=200,
                     help="held-out seeds of the plain vs warm-start comparison (0: skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (the reference "
@@ -402,20 +505,21 @@ def main():
         sfe, _ = solver.thermo(stream)
         return info, sfe
 
-    # Warmup.  The first warmup step times every kernel family (for the
-    # per-family breakdown and to name the dominant family); the timed region
-    # then records events around that family only, since every event record
-    # also orders the stream and timing all families would slow the solve.
+    # Warmup.  One-time set-up outside the timed region: pick the tile widths
+    # of the FP32 iteration kernels for this grid (no effect on results).  One
+    # warmup step then times every kernel family (the per-family breakdown,
+    # which names the dominant family); the timed region records events around
+    # that family only, since every event record also orders the stream and
+    # timing all families would slow the solve.
+    step()
+    tuning = R.rism3d_autotune(dp, opts, solver.ws, stream)
     R.timing_reset()
     R.timing_enable(True)
     step()
     torch.cuda.synchronize()
     R.timing_enable(False)
     breakdown = R.timing_read()
-    # one-time set-up outside the timed region: pick the tile widths of the
-    # FP32 iteration kernels for this grid (no effect on results)
-    tuning = R.rism3d_autotune(dp, opts, solver.ws, stream)
-    for _ in range(max(args.warmup - 1, 0)):
+    for _ in range(max(args.warmup - 2, 0)):
         step()
     torch.cuda.synchronize()
     dominant = max((f for f, (c, ms) in breakdown.items() if c and kernel_bytes(
@@ -446,15 +550,29 @@ def main():
                 continue
             avg_s = ms / cnt * 1e-3
             b = kernel_bytes(nv, N, M, m_avg, fam)
+            ov = increment_overhead_bytes(nv, N, fam)
             out[fam] = {"launches": cnt, "total_ms": round(ms, 3),
                         "avg_us": round(avg_s * 1e6, 2), "bytes_per_launch": b,
-                        "gbps": round(b / avg_s / 1e9, 1) if b else None}
+                        "gbps": round(b / avg_s / 1e9, 1) if b else None,
+                        "frac": round(b / avg_s / 1e9 / HBM_PEAK_GBPS, 4) if b else None}
+            if ov:
+                out[fam]["increment_overhead_bytes"] = ov
+                out[fam]["gbps_incl_overhead"] = round((b + ov) / avg_s / 1e9, 1)
         return out
-
 
     kernels = table(breakdown)
     timed = table(timing)[dominant]
     achieved = timed["gbps"]
+    # the FP32 iteration's kernels together: their algorithmic bytes over
+    # their summed time (traffic-weighted fraction of the HBM peak)
+    it_fams = [f for f in ITERATION_FAMILIES if f in kernels]
+    it_bytes = sum(kernels[f]["bytes_per_launch"] * kernels[f]["launches"] for f in it_fams)
+    it_s = sum(kernels[f]["total_ms"] for f in it_fams) * 1e-3
+    fp32_iteration = {"families": it_fams,
+                      "gbps": round(it_bytes / it_s / 1e9, 1) if it_s else None,
+                      "frac": round(it_bytes / it_s / 1e9 / HBM_PEAK_GBPS, 4) if it_s else None,
+                      "control_us_per_iteration": (kernels["mdiis_control"]["avg_us"]
+                                                   if "mdiis_control" in kernels else None)}
     traffic = None
     if os.path.exists(PROFILE_TRAFFIC):
         with open(PROFILE_TRAFFIC) as f:
@@ -488,8 +606,11 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic, "kernel": dominant,
                      "launches": timed["launches"], "avg_us": timed["avg_us"],
-                     "bytes_per_launch": timed["bytes_per_launch"]},
-        "kernels_first_warmup_step": kernels,
+                     "bytes_per_launch": timed["bytes_per_launch"],
+                     "increment_overhead_bytes": timed.get("increment_overhead_bytes", 0.0),
+                     "achieved_incl_overhead": timed.get("gbps_incl_overhead", achieved)},
+        "kernels_tuned_step": kernels,
+        "fp32_iteration_kernels": fp32_iteration,
         "tuning": tuning,
     }
     th = solver.thermo_all(stream)   # the last timed solve's thermodynamics
