@@ -43,6 +43,7 @@ extern "C" {
 
 #define RISM3D_MAX_SITES 8
 #define RISM3D_MAX_DEPTH 16
+#define RISM3D_HISTORY_LEN 16384  /* residual history entries kept per workspace */
 
 typedef enum {
   RISM3D_OK = 0,
@@ -180,6 +181,23 @@ rism3d_status rism3d_solve(const rism3d_problem* problem, const rism3d_opts* opt
                            const float* d_tau0, void* d_ws, size_t ws_bytes, float* d_g,
                            rism3d_info* info, hipStream_t stream);
 
+/* A closure ladder (continuation in the closure): rism3d_solve under
+ * stages[0], then under stages[1], ... on one workspace.  Stage 0 starts
+ * from d_tau0 (or t = f when NULL); every later stage starts from the
+ * iterate the stage before returned (tau rounded to float32).  The usual
+ * ladder is KH, then PSE-2, then PSE-n with each stage's own tolerance and
+ * damping: a high-order PSE closure (Kast & Kloss) or HNC (Eq 14) started
+ * from t = f can diverge where KH (Eq 15) converges.  Every stage must give
+ * the workspace layout of stages[0] (same MDIIS depth and accelerator);
+ * closure, order, tol, max_iter and damping may differ.  info (host, may be
+ * NULL) receives n_stages entries.  The first stage that does not return
+ * RISM3D_OK ends the ladder with its status (later entries of info are not
+ * written).  d_g (may be NULL) receives g of the last stage, and
+ * rism3d_thermo with the last stage's options evaluates its free energy. */
+rism3d_status rism3d_solve_ladder(const rism3d_problem* problem, const rism3d_opts* stages,
+                                  int n_stages, const float* d_tau0, void* d_ws, size_t ws_bytes,
+                                  float* d_g, rism3d_info* info, hipStream_t stream);
+
 /* Many solutes in one call: for each of the n problems (host array; any mix
  * of solutes, grids and solvents, one set of options), the work of
  * rism3d_potential, rism3d_solve and (if thermo != NULL) rism3d_thermo.
@@ -245,6 +263,19 @@ rism3d_status rism3d_sfe_gradient(const rism3d_problem* problem, const rism3d_op
 rism3d_status rism3d_get_tau(const rism3d_problem* problem, const rism3d_opts* opts,
                              const void* d_ws, size_t ws_bytes, float* d_tau,
                              hipStream_t stream);
+
+/* Residual history of the last rism3d_solve on this workspace (Eq 41 per
+ * evaluation of the map): rms[i] is the RMS residual of evaluation i + 1 and
+ * exact[i] is 1 where that evaluation was an exact FP64 one (an anchor, or
+ * the verification of an estimate below tol) and 0 for an FP32 increment
+ * estimate.  *count receives the number of evaluations recorded, the
+ * iteration count capped at RISM3D_HISTORY_LEN; min(*count, capacity)
+ * entries are written to the host arrays rms and exact (which may be NULL
+ * when capacity is 0).  Synchronises the stream.  Solves of a batch
+ * (rism3d_solve_batch) keep no history readable here. */
+rism3d_status rism3d_get_history(const rism3d_problem* problem, const rism3d_opts* opts,
+                                 const void* d_ws, size_t ws_bytes, int capacity, double* rms,
+                                 int* exact, int* count, hipStream_t stream);
 
 /* One exact (FP64) evaluation of the discretised 3D-RISM map (steps 2-5,
  * Eq 31-33) at tau = t - f: writes the residual R = t' - t = h + 1 - g

@@ -20,6 +20,7 @@ static_assert(kScreen == 1.0, "the potential kernel evaluates (1 - e^{-d/l})/d w
 
 constexpr int kMaxSites = RISM3D_MAX_SITES;
 constexpr int kMaxDepth = RISM3D_MAX_DEPTH;
+constexpr int kHistLen = RISM3D_HISTORY_LEN;
 constexpr int kMaxRadixPasses = 12;
 
 // Solvent-site constants passed by value to kernels.
@@ -71,6 +72,7 @@ struct IterState {
   int final_slot;                     // slot of the accepted iterate
   int warm;                           // 1 if a caller tau0 seeded iteration 0
   int prepared;                       // magic set by rism3d_potential
+  unsigned layout_key;                // digest of the workspace layout it was prepared with
   int ticket;                         // workgroups of the fused residual kernel that finished
   int hold;                           // the next update re-evaluates the iterate in slot dest
 };

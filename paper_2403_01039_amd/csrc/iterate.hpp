@@ -83,9 +83,10 @@ __global__ void k_init_tau(const float* __restrict__ tau0, float* __restrict__ s
   }
 }
 
-__global__ void k_mark_prepared(IterState* st) {
+__global__ void k_mark_prepared(IterState* st, unsigned layout_key) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     st->prepared = kPreparedMagic;
+    st->layout_key = layout_key;
     st->done = 1;
     st->final_slot = -1;
   }
@@ -863,7 +864,7 @@ __device__ __forceinline__ void control_block(IterState* __restrict__ st_g,
                                      const double* __restrict__ partials, int nblocks, int M,
                                      double inv_count, double tol, int max_iter, float eta_static,
                                      int eta_dynamic, int accel, double as1, double as2,
-                                     int anchor, ControlScratch& cs) {
+                                     int anchor, double2* __restrict__ hist, ControlScratch& cs) {
   {
     const int* src = reinterpret_cast<const int*>(st_g);
     int* dst = reinterpret_cast<int*>(&cs.st);
@@ -913,9 +914,13 @@ __device__ __forceinline__ void control_block(IterState* __restrict__ st_g,
     cs.sums[threadIdx.x] = t;
   }
   __syncthreads();
-  if (threadIdx.x == 0)
+  if (threadIdx.x == 0) {
     control_step(cs.st, cs.sums, cs.A, M, inv_count, tol, max_iter, eta_static, eta_dynamic,
                  accel, as1, as2, anchor);
+    // residual history: the RMS of evaluation i (1-based) and whether it was exact
+    const int it = cs.st.iter;
+    if (it >= 1 && it <= kHistLen) hist[it - 1] = make_double2(cs.st.last_rms, anchor ? 1.0 : 0.0);
+  }
   __syncthreads();
   {
     const int* src = reinterpret_cast<const int*>(&cs.st);
@@ -929,13 +934,14 @@ template <int MM = kMaxDepth>
 __global__ __launch_bounds__(kCtlThreads) void k_control(
     IterState* __restrict__ st_g, const double* __restrict__ partials, int nblocks, int M,
     double inv_count, double tol, int max_iter, float eta_static, int eta_dynamic,
-    int accel, double as1, double as2, int anchor, size_t bstride) {
+    int accel, double as1, double as2, int anchor, double2* __restrict__ hist, size_t bstride) {
   __shared__ ControlScratch cs;
   st_g = member_ptr(st_g, bstride);
   if (anchor ? skip_iteration<true>(st_g->done) : skip_iteration<false>(st_g->done)) return;
   partials = member_ptr(partials, bstride);
+  hist = member_ptr(hist, bstride);
   control_block<MM>(st_g, partials, nblocks, M, inv_count, tol, max_iter, eta_static, eta_dynamic,
-                accel, as1, as2, anchor, cs);
+                accel, as1, as2, anchor, hist, cs);
 }
 
 // ---------------------------------------------------------------------------

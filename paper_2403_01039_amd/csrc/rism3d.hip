@@ -208,10 +208,39 @@ struct Layout {
   size_t off_state, off_w, off_phi, off_F, off_tau, off_res, off_tref, off_tlo, off_rref, off_dg,
       off_spec,
       off_part, off_atoms, off_lj, off_ph, off_chi32, off_chi64, off_q64, off_tw32[3], off_tw64[3],
-      off_out, total;
+      off_out, off_hist, total;
 };
 
 constexpr int kDefaultCheckEvery = 8;
+
+// FNV-1a digest of what fixes the workspace offsets (grid, sites, stored
+// pairs, table length, atom count, size): a workspace prepared under one
+// layout and read under another (for example other MDIIS depth options) is
+// refused instead of read at the wrong offsets.
+unsigned layout_key(const Layout& L) {
+  const unsigned long long v[8] = {(unsigned long long)L.nx, (unsigned long long)L.ny,
+                                   (unsigned long long)L.nz, (unsigned long long)L.nv,
+                                   (unsigned long long)L.M, (unsigned long long)L.m_tab,
+                                   (unsigned long long)L.n_atoms, (unsigned long long)L.total};
+  unsigned h = 2166136261u;
+  for (unsigned long long x : v)
+    for (int b = 0; b < 8; ++b) {
+      h ^= (unsigned)((x >> (8 * b)) & 0xffu);
+      h *= 16777619u;
+    }
+  return h;
+}
+
+rism3d_status check_prepared(const IterState& host, const Layout& L) {
+  if (host.prepared != kPreparedMagic)
+    return fail(RISM3D_E_WORKSPACE, "workspace not prepared: call rism3d_potential first");
+  if (host.layout_key != layout_key(L))
+    return fail(RISM3D_E_WORKSPACE,
+                "workspace was prepared for another layout (grid, sites, MDIIS depth or "
+                "accelerator, table length or atom count): call rism3d_potential with these "
+                "options first");
+  return RISM3D_OK;
+}
 // thermodynamic results left in the workspace by launch_sfe: per-site free
 // energies, their total, per-site rho_g \int c_g
 constexpr int kOutDoubles = 2 * kMaxSites + 1;
@@ -328,6 +357,7 @@ rism3d_status make_layout(const rism3d_problem* pr, const rism3d_opts* op, Layou
     L->off_tw64[a] = take(2 * (size_t)dims[a] * sizeof(double2));
   }
   L->off_out = take(kOutDoubles * sizeof(double));
+  L->off_hist = take(kHistLen * sizeof(double2));
   // Solute-size dependent regions last: every offset above depends only on the
   // grid, the sites, the MDIIS depth and the table length, so solves of
   // different solutes on one grid share the offsets the iteration reads.
@@ -712,7 +742,7 @@ void launch_fused_l(const Layout& L, void* ws, const rism3d_opts* op, bool first
                        at<double>(ws, L.off_part), (int)grid.x, L.M, inv_count, op->tol,
                        op->max_iter, (float)op->mdiis_eta, op->eta_dynamic,
                        (int)op->accelerator, op->anderson_s1, op->anderson_s2, ANCHOR ? 1 : 0,
-                       bt.stride);
+                       at<double2>(ws, L.off_hist), bt.stride);
   }
 }
 
@@ -842,7 +872,7 @@ void launch_iteration(const Layout& L, void* ws, const rism3d_opts* op, double i
                        dim3(kCtlThreads), 0, s, st, at<double>(ws, L.off_part),
                        (int)nblk, L.M, inv_count, op->tol, op->max_iter, (float)op->mdiis_eta,
                        op->eta_dynamic, (int)op->accelerator, op->anderson_s1, op->anderson_s2,
-                       anchor ? 1 : 0, (size_t)0);
+                       anchor ? 1 : 0, at<double2>(ws, L.off_hist), (size_t)0);
   }
 }
 
@@ -1016,7 +1046,8 @@ rism3d_status prepare(const rism3d_problem* pr, const Layout& L, void* ws, hipSt
   for (int a = 0; a < 3; ++a)
     hipLaunchKernelGGL(k_twiddles, dim3(blocks_for(2 * dims[a], 256)), dim3(256), 0, s, dims[a],
                        at<float2>(ws, L.off_tw32[a]), at<double2>(ws, L.off_tw64[a]));
-  hipLaunchKernelGGL(k_mark_prepared, dim3(1), dim3(1), 0, s, at<IterState>(ws, L.off_state));
+  hipLaunchKernelGGL(k_mark_prepared, dim3(1), dim3(1), 0, s, at<IterState>(ws, L.off_state),
+                     layout_key(L));
   LAUNCH_CHECK();
   return RISM3D_OK;
 }
@@ -1274,8 +1305,7 @@ rism3d_status rism3d_solve(const rism3d_problem* pr, const rism3d_opts* op, cons
   IterState host;
   HIP_TRY(hipMemcpyAsync(&host, dst, sizeof(IterState), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  if (host.prepared != kPreparedMagic)
-    return fail(RISM3D_E_WORKSPACE, "workspace not prepared: call rism3d_potential first");
+  if ((st = check_prepared(host, L)) != RISM3D_OK) return st;
   const double inv_dkt = (1.0 / pr->dk);
   // A caller's starting tau is only a starting point: if the iteration from
   // it ends on a non-finite residual, the solve is repeated from tau0 = 0.
@@ -1357,6 +1387,44 @@ rism3d_status rism3d_solve(const rism3d_problem* pr, const rism3d_opts* op, cons
   return RISM3D_OK;
 }
 
+rism3d_status rism3d_solve_ladder(const rism3d_problem* pr, const rism3d_opts* stages,
+                                  int n_stages, const float* tau0, void* ws, size_t ws_bytes,
+                                  float* g_out, rism3d_info* info, hipStream_t s) {
+  if (n_stages < 1 || !stages) return fail(RISM3D_E_ARG, "n_stages must be >= 1");
+  Layout L0;
+  rism3d_status st = make_layout(pr, &stages[0], &L0);
+  if (st != RISM3D_OK) return st;
+  const unsigned key = layout_key(L0);
+  for (int k = 1; k < n_stages; ++k) {
+    Layout Lk;
+    if ((st = make_layout(pr, &stages[k], &Lk)) != RISM3D_OK) return st;
+    if (layout_key(Lk) != key)
+      return fail(RISM3D_E_ARG,
+                  "ladder stage %d changes the workspace layout (MDIIS depth or accelerator)", k);
+  }
+  // Between stages the returned iterate, rounded to float32, is the next
+  // start; it is staged in the closure-increment section, which the first
+  // kernel of a solve reads before any kernel writes it.
+  float* start = at<float>(ws, L0.off_dg);
+  for (int k = 0; k < n_stages; ++k) {
+    const rism3d_opts* op = &stages[k];
+    const float* t0 = tau0;
+    if (k > 0) {
+      hipLaunchKernelGGL(k_output, dim3(blocks_for((size_t)L0.nv * L0.N, kElemThreads)),
+                         dim3(kElemThreads), 0, s, at<IterState>(ws, L0.off_state),
+                         at<float>(ws, L0.off_tau), at<float>(ws, L0.off_tref),
+                         at<float>(ws, L0.off_tlo), at<float>(ws, L0.off_w), L0.N, L0.nv,
+                         (int)op->closure, order_of(op), (float*)nullptr, start);
+      LAUNCH_CHECK();
+      t0 = start;
+    }
+    st = rism3d_solve(pr, op, t0, ws, ws_bytes, k + 1 == n_stages ? g_out : nullptr,
+                      info ? &info[k] : nullptr, s);
+    if (st != RISM3D_OK) return st;
+  }
+  return RISM3D_OK;
+}
+
 rism3d_status rism3d_thermo(const rism3d_problem* pr, const rism3d_opts* op, const void* ws_c,
                             size_t ws_bytes, rism3d_thermo_out* out, hipStream_t s) {
   Layout L;
@@ -1369,7 +1437,8 @@ rism3d_status rism3d_thermo(const rism3d_problem* pr, const rism3d_opts* op, con
   IterState host;
   HIP_TRY(hipMemcpyAsync(&host, dst, sizeof(IterState), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  if (host.prepared != kPreparedMagic || host.final_slot < 0)
+  if ((st = check_prepared(host, L)) != RISM3D_OK) return st;
+  if (host.final_slot < 0)
     return fail(RISM3D_E_WORKSPACE, "no solution in the workspace: call rism3d_solve first");
   launch_sfe(pr, op, L, ws, s);
   LAUNCH_CHECK();
@@ -1394,8 +1463,7 @@ rism3d_status rism3d_sfe_gradient(const rism3d_problem* pr, const rism3d_opts* o
   HIP_TRY(hipMemcpyAsync(&host, at<IterState>(ws, L.off_state), sizeof(IterState),
                          hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  if (host.prepared != kPreparedMagic)
-    return fail(RISM3D_E_WORKSPACE, "workspace not prepared: call rism3d_potential first");
+  if ((st = check_prepared(host, L)) != RISM3D_OK) return st;
   if (L.n_atoms == 0) {
     g_error.clear();
     return RISM3D_OK;
@@ -1622,6 +1690,37 @@ rism3d_status rism3d_get_tau(const rism3d_problem* pr, const rism3d_opts* op, co
   return RISM3D_OK;
 }
 
+rism3d_status rism3d_get_history(const rism3d_problem* pr, const rism3d_opts* op,
+                                 const void* ws_c, size_t ws_bytes, int capacity, double* rms,
+                                 int* exact, int* count, hipStream_t s) {
+  Layout L;
+  rism3d_status st = make_layout(pr, op, &L);
+  if (st != RISM3D_OK) return st;
+  if ((st = check_ws(L, ws_c, ws_bytes)) != RISM3D_OK) return st;
+  if (!count || capacity < 0 || (capacity > 0 && (!rms || !exact)))
+    return fail(RISM3D_E_ARG, "null count, or null rms/exact with capacity > 0");
+  void* ws = const_cast<void*>(ws_c);
+  IterState host;
+  HIP_TRY(hipMemcpyAsync(&host, at<IterState>(ws, L.off_state), sizeof(IterState),
+                         hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if ((st = check_prepared(host, L)) != RISM3D_OK) return st;
+  const int n = host.iter < kHistLen ? (host.iter > 0 ? host.iter : 0) : kHistLen;
+  *count = n;
+  const int take_n = n < capacity ? n : capacity;
+  if (take_n > 0) {
+    std::vector<double2> buf((size_t)take_n);
+    HIP_TRY(hipMemcpyAsync(buf.data(), at<double2>(ws, L.off_hist),
+                           (size_t)take_n * sizeof(double2), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int i = 0; i < take_n; ++i) {
+      rms[i] = buf[i].x;
+      exact[i] = buf[i].y != 0.0;
+    }
+  }
+  return RISM3D_OK;
+}
+
 rism3d_status rism3d_map(const rism3d_problem* pr, const rism3d_opts* op, const float* d_tau,
                          void* ws, size_t ws_bytes, float* d_res, double* rms, hipStream_t s) {
   Layout L;
@@ -1633,8 +1732,7 @@ rism3d_status rism3d_map(const rism3d_problem* pr, const rism3d_opts* op, const 
   IterState host;
   HIP_TRY(hipMemcpyAsync(&host, dst, sizeof(IterState), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  if (host.prepared != kPreparedMagic)
-    return fail(RISM3D_E_WORKSPACE, "workspace not prepared: call rism3d_potential first");
+  if ((st = check_prepared(host, L)) != RISM3D_OK) return st;
   if (!d_tau && host.final_slot < 0)
     return fail(RISM3D_E_WORKSPACE, "no solution in the workspace: call rism3d_solve first");
   rism3d_opts one = *op;
@@ -1675,8 +1773,7 @@ rism3d_status rism3d_map_increment(const rism3d_problem* pr, const rism3d_opts* 
   IterState host;
   HIP_TRY(hipMemcpyAsync(&host, dst, sizeof(IterState), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  if (host.prepared != kPreparedMagic)
-    return fail(RISM3D_E_WORKSPACE, "workspace not prepared: call rism3d_potential first");
+  if ((st = check_prepared(host, L)) != RISM3D_OK) return st;
   rism3d_opts two = *op;
   two.max_iter = 3;   // neither evaluation may end the iteration
   two.tol = 0.0;

@@ -91,6 +91,8 @@ def _load():
         "rism3d_workspace_bytes": (sz, [P(Problem), P(Opts)]),
         "rism3d_potential": (ctypes.c_int, [P(Problem), P(Opts), vp, sz, st]),
         "rism3d_solve": (ctypes.c_int, [P(Problem), P(Opts), vp, vp, sz, vp, P(Info), st]),
+        "rism3d_solve_ladder": (ctypes.c_int, [P(Problem), vp, ctypes.c_int, vp, vp, sz, vp,
+                                               vp, st]),
         "rism3d_thermo": (ctypes.c_int, [P(Problem), P(Opts), vp, sz, P(ThermoOut), st]),
         "rism3d_sfe_gradient": (ctypes.c_int, [P(Problem), P(Opts), vp, vp, sz, vp, st]),
         "rism3d_get_tau": (ctypes.c_int, [P(Problem), P(Opts), vp, sz, vp, st]),
@@ -99,6 +101,9 @@ def _load():
         "rism3d_map_increment": (ctypes.c_int, [P(Problem), P(Opts), vp, vp, vp, sz, vp,
                                                 P(ctypes.c_double), st]),
         "rism3d_get_potential": (ctypes.c_int, [P(Problem), P(Opts), vp, sz, vp, vp, st]),
+        "rism3d_get_history": (ctypes.c_int, [P(Problem), P(Opts), vp, sz, ctypes.c_int,
+                                              P(ctypes.c_double), P(ctypes.c_int),
+                                              P(ctypes.c_int), st]),
         "rism3d_transform_workspace_bytes": (sz, [ctypes.c_int] * 3),
         "rism3d_transform": (ctypes.c_int, [ctypes.c_int] * 4 + [vp, ctypes.c_int, vp, sz, st]),
         "rism3d_timing_enable": (None, [ctypes.c_int]),
@@ -144,9 +149,10 @@ def _load():
 
 
 LIB = _load()
-EXPORTED = ("rism3d_workspace_bytes", "rism3d_potential", "rism3d_solve", "rism3d_thermo",
+EXPORTED = ("rism3d_workspace_bytes", "rism3d_potential", "rism3d_solve", "rism3d_solve_ladder",
+            "rism3d_thermo",
             "rism3d_sfe_gradient",
-            "rism3d_get_tau", "rism3d_map", "rism3d_map_increment", "rism3d_get_potential",
+            "rism3d_get_tau", "rism3d_get_history", "rism3d_map", "rism3d_map_increment", "rism3d_get_potential",
             "rism3d_transform_workspace_bytes", "rism3d_transform", "rism3d_timing_enable",
             "rism3d_timing_reset", "rism3d_timing_read", "rism3d_use_graphs",
             "rism3d_release_graphs", "rism3d_timing_select",
@@ -299,6 +305,24 @@ def rism3d_solve(dp, opts, ws, tau0=None, g_out=None, stream=None, allow_noconv=
     return info
 
 
+def rism3d_solve_ladder(dp, stages, ws, tau0=None, g_out=None, stream=None):
+    """Closure ladder: a list of Opts run in order, each stage from the last
+    one's iterate; returns the list of Info of the stages that ran (the
+    failing stage's status raises)."""
+    n = len(stages)
+    arr = (Opts * n)(*stages)
+    infos = (Info * n)()
+    status = LIB.rism3d_solve_ladder(ctypes.byref(dp.struct), ctypes.cast(arr, ctypes.c_void_p), n,
+                                     _ptr(tau0), _ptr(ws), ws.numel() * ws.element_size(),
+                                     _ptr(g_out), ctypes.cast(infos, ctypes.c_void_p),
+                                     _stream(stream))
+    _check(status)
+    out = list(infos)
+    for inf in out:
+        inf.status = 0
+    return out
+
+
 def rism3d_thermo(dp, opts, ws, stream=None):
     out = ThermoOut()
     _check(LIB.rism3d_thermo(ctypes.byref(dp.struct), ctypes.byref(opts), _ptr(ws),
@@ -340,6 +364,24 @@ def _thermo_dict(out, nv: int) -> dict:
 def rism3d_get_tau(dp, opts, ws, tau_out, stream=None):
     _check(LIB.rism3d_get_tau(ctypes.byref(dp.struct), ctypes.byref(opts), _ptr(ws),
                               ws.numel() * ws.element_size(), _ptr(tau_out), _stream(stream)))
+
+
+def rism3d_get_history(dp, opts, ws, stream=None):
+    """(rms [n] float64, exact [n] bool) of every evaluation of the last solve."""
+    count = ctypes.c_int()
+    _check(LIB.rism3d_get_history(ctypes.byref(dp.struct), ctypes.byref(opts), _ptr(ws),
+                                  ws.numel() * ws.element_size(), 0, None, None,
+                                  ctypes.byref(count), _stream(stream)))
+    n = count.value
+    rms = np.zeros(n, dtype=np.float64)
+    exact = np.zeros(n, dtype=np.int32)
+    if n:
+        _check(LIB.rism3d_get_history(
+            ctypes.byref(dp.struct), ctypes.byref(opts), _ptr(ws), ws.numel() * ws.element_size(),
+            n, rms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            exact.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), ctypes.byref(count),
+            _stream(stream)))
+    return rms, exact.astype(bool)
 
 
 def rism3d_map(dp, opts, ws, tau, res_out, stream=None) -> float:
@@ -590,6 +632,13 @@ class Solver:
     def solve(self, tau0=None, g_out=None, stream=None, allow_noconv=False) -> Info:
         return rism3d_solve(self.dp, self.opts, self.ws, tau0, g_out, stream, allow_noconv)
 
+    def solve_ladder(self, stages, tau0=None, g_out=None, stream=None):
+        """Runs the stages (Opts) in order; self.opts becomes the last stage's
+        (for thermo and map calls that follow)."""
+        infos = rism3d_solve_ladder(self.dp, stages, self.ws, tau0, g_out, stream)
+        self.opts = stages[-1]
+        return infos
+
     def thermo(self, stream=None):
         return rism3d_thermo(self.dp, self.opts, self.ws, stream)
 
@@ -598,6 +647,9 @@ class Solver:
 
     def sfe_gradient(self, g: torch.Tensor, stream=None) -> torch.Tensor:
         return rism3d_sfe_gradient(self.dp, self.opts, self.ws, g, stream=stream)
+
+    def history(self, stream=None):
+        return rism3d_get_history(self.dp, self.opts, self.ws, stream)
 
     def tau(self) -> torch.Tensor:
         t = torch.empty(self.dp.shape, dtype=torch.float32, device=self.ws.device)

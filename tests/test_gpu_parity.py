@@ -91,11 +91,12 @@ def test_potential_matches_oracle(R, O, name):
 # (saline, (nz, ny, nx)): the generic path, the fused x kernels with the fused
 # z transform + contraction, and every fused instantiation the workloads reach
 # at full size: x and z lengths 96 (96^3 batch members), x 256 and z 256 (the
-# 256^3 globule), x 512 (the 512^3 stand-in), y 512, and z 512 (separate z
-# passes and contraction).
+# 256^3 globule), x 512 (the 512^3 stand-in), y 128, 256 and 512, and z 512
+# (separate z passes and contraction).
 MAP_SHAPES = [(False, (18, 20, 24)), (True, (18, 20, 24)), (True, (64, 24, 32)),
               (False, (32, 16, 64)), (True, (512, 8, 32)), (False, (256, 8, 256)),
-              (False, (96, 96, 96)), (True, (64, 8, 512)), (False, (64, 512, 32))]
+              (False, (96, 96, 96)), (True, (64, 8, 512)), (False, (64, 512, 32)),
+              (False, (16, 256, 16)), (True, (16, 128, 16))]
 
 
 def _map_case(R, O, saline, shape, closure="kh"):
@@ -319,17 +320,19 @@ def test_full_size_golden(R, name):
 
 
 def test_globule_4000_at_256(R, O):
-    """The 4000-atom globule (net +4, water, 256^3 at 0.4 A) at full size:
-    the potential at 2000 sampled points against the oracle's pair sums, a
-    KH solve with MDIIS depth 10 to the paper's rms 1e-6, and the returned
-    tau's residual under one FP64 evaluation of the map (the returned tau is
-    rounded to FP32, which adds a few 1e-7).  (The workload's PSE-3 closure
-    diverges on this densely charged globule, from zero and from the KH
-    solution alike: its cubic branch turns the strong Coulomb wells into
-    g ~ d^3/6.  PSE-3 with depth 10 is checked against the oracle on the
-    small parity cases.)"""
+    """The 4000-atom globule (net +4, water, 256^3 at 0.4 A) as specified:
+    PSE-3, MDIIS depth 10, rms 1e-6.  The potential at 2000 sampled points
+    against the oracle's pair sums; then the closure ladder KH -> PSE-2 ->
+    PSE-3 (PSE-3 started from t = f diverges on this densely charged globule:
+    its cubic branch turns the strong Coulomb wells into g ~ d^3/6, and the
+    first Picard step overshoots by orders of magnitude).  Damping 0.3 for KH
+    and PSE-2 and 0.4 for PSE-3 (the paper advises b <= 0.4 for closures
+    stiffer than KH).  The PSE-3 iterate returned has an exact FP64 residual
+    below 1e-6: one FP64 evaluation of the map at it reproduces info.rms."""
     import time
     prob = inputs.globule_4000_problem()
+    assert prob.options.closure == "pse" and prob.options.pse_order == 3
+    assert prob.options.mdiis_depth == 10
     print("globule_4000 256^3", flush=True)
     s, chi, dk = _run(R, prob)
     w, phi = s.fields()
@@ -344,19 +347,25 @@ def test_globule_4000_at_256(R, O):
     rel = np.abs(w_s - w_ref) / np.maximum(1.0, np.abs(w_ref))
     soft = w_ref < 5.0
     assert rel[soft].max() < 2e-5 and rel[~soft].max() < 1e-3
-    s.opts = R.make_opts(prob.options, closure="kh", max_iter=3000, tol=1e-6)
+    stages = [R.make_opts(prob.options, closure="kh", tol=1e-5, mdiis_eta=0.3, max_iter=4000),
+              R.make_opts(prob.options, pse_order=2, tol=1e-6, mdiis_eta=0.3, max_iter=4000),
+              R.make_opts(prob.options, tol=1e-6, mdiis_eta=0.4, max_iter=6000)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    info = s.solve()
+    infos = s.solve_ladder(stages)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    sfe, _ = s.thermo()
+    th = s.thermo_all()
     res, rms = s.map(None)
-    print(f"  KH: {info.iterations} iterations, rms {info.rms:.2e}, {el:.2f} s; FP64 map rms "
-          f"at the returned iterate {rms:.2e}; sfe {sfe:.2f}", flush=True)
-    assert info.rms < 1e-6 and info.status == 0
-    assert rms < 1e-6
-    assert np.isfinite(sfe)
+    del res
+    its = [i.iterations for i in infos]
+    print(f"  KH -> PSE-2 -> PSE-3: {its} iterations, rms {[f'{i.rms:.2e}' for i in infos]}, "
+          f"{el:.2f} s; FP64 map rms at the returned iterate {rms:.3e}; sfe {th['sfe']:.2f}",
+          flush=True)
+    assert all(i.status == 0 for i in infos)
+    assert infos[-1].rms < 1e-6 and rms < 1e-6
+    assert abs(rms - infos[-1].rms) <= 1e-6 * infos[-1].rms
+    assert np.isfinite(th["sfe"])
 
 
 def test_globule_12877_at_512(R, O):
@@ -466,3 +475,36 @@ def test_noconv_and_bad_args(R):
     with pytest.raises(R.RismError) as e:
         R.rism3d_workspace_bytes(s.dp, bad)
     assert e.value.status == 1
+
+
+def test_workspace_prepared_under_other_options_is_refused(R):
+    """A workspace laid out for MDIIS depth 10 and prepared under it is large
+    enough for depth 5, but its offsets differ: a solve with depth-5 options
+    must be refused rather than read the potential at the wrong offsets."""
+    prob = inputs.small_problem(13, n_atoms=8, shape=(20, 20, 20), radius=2.5)
+    s, _, _ = _run(R, prob, mdiis_depth=10)
+    s.opts = R.make_opts(prob.options, mdiis_depth=5)
+    assert R.rism3d_workspace_bytes(s.dp, s.opts) < s.nbytes
+    with pytest.raises(R.RismError) as e:
+        s.solve()
+    assert e.value.status == 5 and "another layout" in str(e.value)
+    s.potential()
+    info = s.solve()
+    assert info.status == 0
+
+
+def test_residual_history(R):
+    """The recorded history: one RMS per evaluation, the last one exact (FP64)
+    and equal to info.rms, every anchor_every-th evaluation exact."""
+    prob = inputs.small_problem(13, n_atoms=8, shape=(20, 20, 20), radius=2.5)
+    s, _, _ = _run(R, prob, anchor_every=4)
+    info = s.solve()
+    rms, exact = s.history()
+    print(f"history: {info.iterations} iterations, {exact.sum()} exact", flush=True)
+    assert len(rms) == info.iterations
+    assert exact[-1] and rms[-1] == info.rms and rms[-1] < prob.options.tol
+    # an exact evaluation below tol ends the solve, so no earlier one is
+    assert (rms[:-1][exact[:-1]] >= prob.options.tol).all()
+    pos = np.nonzero(exact)[0]
+    assert pos[0] == 0 and np.diff(pos).max() <= 4
+    assert np.isfinite(rms).all() and (rms > 0).all()
