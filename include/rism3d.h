@@ -321,6 +321,22 @@ size_t rism3d_transform_workspace_bytes(int nx, int ny, int nz);
 rism3d_status rism3d_transform(int nx, int ny, int nz, int count, void* d_data, int forward,
                                void* d_ws, size_t ws_bytes, hipStream_t stream);
 
+/* rism3d_transform without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc): the twiddle tables live in a static
+ * device array of the library, RISM3D_NOALLOC_SCRATCH_BYTES bytes per GPU,
+ * held until the process ends.  Same transform, kernels and results as
+ * rism3d_transform.  Axes of up to 512 points (every grid rism3d_transform
+ * accepts fits the array).  Allocates nothing and calls no allocating
+ * routine.  Runs on the current device, which must be the stream's device.
+ * Every call on one GPU rewrites that GPU's tables before its transform, so
+ * calls that overlap on one GPU (concurrent streams or threads) race and
+ * must be ordered by the caller.  Returns RISM3D_E_ARG for unsupported grids
+ * and RISM3D_E_DEVICE when the array's device address cannot be obtained. */
+#define RISM3D_NOALLOC_SCRATCH_BYTES (3 * 2 * 512 * 8)
+rism3d_status rism3d_transform_noalloc(int nx, int ny, int nz, int count, void* d_data,
+                                       int forward, hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Learned warm start (not in the paper, which starts every solve at t = f):
  * a 3D convolutional encoder-decoder maps the solute potential of each

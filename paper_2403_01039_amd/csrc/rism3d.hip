@@ -26,6 +26,15 @@
 
 using namespace rism;
 
+// Device scratch of rism3d_transform_noalloc: the twiddle tables of the three
+// axes (2 n float2 per axis, each table 256-byte aligned), for axes of up to
+// kFftMaxN points.  Every GPU the library runs on holds one copy until the
+// process ends; host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kNoAllocScratchBytes = 3 * 2 * (size_t)kFftMaxN * sizeof(float2);
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+static_assert(kNoAllocScratchBytes == RISM3D_NOALLOC_SCRATCH_BYTES, "header size");
+
 namespace {
 
 thread_local std::string g_error;
@@ -1266,6 +1275,59 @@ void launch_sfe_grad_nv(const Layout& L, const void* ws, const float* g, double 
                      dr, sc, dst, scale);
 }
 
+// The shifted 3D transform of rism3d_transform with its twiddle tables in ws
+// (rism3d_transform_workspace_bytes(nx, ny, nz) bytes, 256-byte aligned).
+rism3d_status transform_on(int nx, int ny, int nz, int count, void* d_data, int forward, void* ws,
+                           hipStream_t s) {
+  Layout L;
+  memset(&L, 0, sizeof(L));
+  plan_axis(nx, &L.px);
+  plan_axis(ny, &L.py);
+  plan_axis(nz, &L.pz);
+  L.nx = nx;
+  L.ny = ny;
+  L.nz = nz;
+  L.npair = count;
+  L.N = (size_t)nx * ny * nz;
+  const size_t offs[3] = {0, align_up(2 * (size_t)nx * sizeof(float2)),
+                          align_up(2 * (size_t)nx * sizeof(float2)) +
+                              align_up(2 * (size_t)ny * sizeof(float2))};
+  const int dims[3] = {nx, ny, nz};
+  const float2* tw[3];
+  for (int a = 0; a < 3; ++a) {
+    hipLaunchKernelGGL(k_twiddles, dim3(blocks_for(2 * dims[a], 256)), dim3(256), 0, s, dims[a],
+                       at<float2>(ws, offs[a]), (double2*)nullptr);
+    tw[a] = at<float2>(ws, offs[a]);
+  }
+  launch_fft3_on(L, static_cast<float2*>(d_data), tw, forward, (const int*)nullptr, s);
+  LAUNCH_CHECK();
+  return RISM3D_OK;
+}
+
+// Address of the file-scope scratch array on the current device, looked up
+// once per device (hipGetSymbolAddress) and kept: the array's name in host
+// code is not a device address.
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+void* g_scratch_dev[kMaxDevices] = {};
+
+rism3d_status scratch_address(void** out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(RISM3D_E_DEVICE, "device index %d", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(RISM3D_E_DEVICE, "hipGetSymbolAddress(scratch) failed: %s",
+                  hipGetErrorString(e));
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return RISM3D_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1825,32 +1887,30 @@ size_t rism3d_transform_workspace_bytes(int nx, int ny, int nz) {
 
 rism3d_status rism3d_transform(int nx, int ny, int nz, int count, void* d_data, int forward,
                                void* ws, size_t ws_bytes, hipStream_t s) {
-  Layout L;
-  memset(&L, 0, sizeof(L));
-  if (!plan_axis(nx, &L.px) || !plan_axis(ny, &L.py) || !plan_axis(nz, &L.pz))
+  AxisPlan p;
+  if (!plan_axis(nx, &p) || !plan_axis(ny, &p) || !plan_axis(nz, &p))
     return fail(RISM3D_E_ARG, "grid %dx%dx%d unsupported", nx, ny, nz);
   if (count < 1 || !d_data) return fail(RISM3D_E_ARG, "count < 1 or null data");
   const size_t need = rism3d_transform_workspace_bytes(nx, ny, nz);
   if (!ws || (((uintptr_t)ws) & 255) || ws_bytes < need)
     return fail(RISM3D_E_WORKSPACE, "transform workspace must hold %zu aligned bytes", need);
-  L.nx = nx;
-  L.ny = ny;
-  L.nz = nz;
-  L.npair = count;
-  L.N = (size_t)nx * ny * nz;
-  const size_t offs[3] = {0, align_up(2 * (size_t)nx * sizeof(float2)),
-                          align_up(2 * (size_t)nx * sizeof(float2)) +
-                              align_up(2 * (size_t)ny * sizeof(float2))};
-  const int dims[3] = {nx, ny, nz};
-  const float2* tw[3];
-  for (int a = 0; a < 3; ++a) {
-    hipLaunchKernelGGL(k_twiddles, dim3(blocks_for(2 * dims[a], 256)), dim3(256), 0, s, dims[a],
-                       at<float2>(ws, offs[a]), (double2*)nullptr);
-    tw[a] = at<float2>(ws, offs[a]);
-  }
-  launch_fft3_on(L, static_cast<float2*>(d_data), tw, forward, (const int*)nullptr, s);
-  LAUNCH_CHECK();
-  return RISM3D_OK;
+  return transform_on(nx, ny, nz, count, d_data, forward, ws, s);
+}
+
+rism3d_status rism3d_transform_noalloc(int nx, int ny, int nz, int count, void* d_data,
+                                       int forward, hipStream_t s) {
+  AxisPlan p;
+  if (!plan_axis(nx, &p) || !plan_axis(ny, &p) || !plan_axis(nz, &p))
+    return fail(RISM3D_E_ARG, "grid %dx%dx%d unsupported", nx, ny, nz);
+  if (count < 1 || !d_data) return fail(RISM3D_E_ARG, "count < 1 or null data");
+  const size_t need = rism3d_transform_workspace_bytes(nx, ny, nz);
+  if (need > kNoAllocScratchBytes)
+    return fail(RISM3D_E_ARG, "twiddle tables of %zu bytes exceed the static scratch of %zu",
+                need, kNoAllocScratchBytes);
+  void* ws = nullptr;
+  const rism3d_status st = scratch_address(&ws);
+  if (st != RISM3D_OK) return st;
+  return transform_on(nx, ny, nz, count, d_data, forward, ws, s);
 }
 
 void rism3d_timing_enable(int on) { g_timer.on = on != 0; }

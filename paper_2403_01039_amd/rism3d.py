@@ -106,6 +106,7 @@ def _load():
                                               P(ctypes.c_int), st]),
         "rism3d_transform_workspace_bytes": (sz, [ctypes.c_int] * 3),
         "rism3d_transform": (ctypes.c_int, [ctypes.c_int] * 4 + [vp, ctypes.c_int, vp, sz, st]),
+        "rism3d_transform_noalloc": (ctypes.c_int, [ctypes.c_int] * 4 + [vp, ctypes.c_int, st]),
         "rism3d_timing_enable": (None, [ctypes.c_int]),
         "rism3d_timing_reset": (None, []),
         "rism3d_timing_read": (ctypes.c_int, [ctypes.c_int, P(ctypes.c_char_p), P(ctypes.c_long),
@@ -153,7 +154,8 @@ EXPORTED = ("rism3d_workspace_bytes", "rism3d_potential", "rism3d_solve", "rism3
             "rism3d_thermo",
             "rism3d_sfe_gradient",
             "rism3d_get_tau", "rism3d_get_history", "rism3d_map", "rism3d_map_increment", "rism3d_get_potential",
-            "rism3d_transform_workspace_bytes", "rism3d_transform", "rism3d_timing_enable",
+            "rism3d_transform_workspace_bytes", "rism3d_transform", "rism3d_transform_noalloc",
+            "rism3d_timing_enable",
             "rism3d_timing_reset", "rism3d_timing_read", "rism3d_use_graphs",
             "rism3d_release_graphs", "rism3d_timing_select",
             "rism3d_batch_workspace_bytes", "rism3d_solve_batch", "rism3d_unet_param_count",
@@ -419,6 +421,15 @@ def rism3d_transform(data: torch.Tensor, forward: bool, ws: Optional[torch.Tenso
         ws = torch.empty(need, dtype=torch.uint8, device=data.device)
     _check(LIB.rism3d_transform(nx, ny, nz, count, _ptr(data), int(bool(forward)), _ptr(ws),
                                 ws.numel(), _stream(stream)))
+    return data
+
+
+def rism3d_transform_noalloc(data: torch.Tensor, forward: bool, stream=None):
+    """rism3d_transform with the library's static twiddle scratch (no workspace)."""
+    assert data.dtype == torch.complex64 and data.is_contiguous() and data.dim() == 4
+    count, nz, ny, nx = data.shape
+    _check(LIB.rism3d_transform_noalloc(nx, ny, nz, count, _ptr(data), int(bool(forward)),
+                                        _stream(stream)))
     return data
 
 
