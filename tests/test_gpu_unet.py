@@ -51,8 +51,31 @@ def _site_major(a):
                         device="cuda")
 
 
-@pytest.mark.parametrize("levels,shape", [(3, (16, 16, 16)), (4, (32, 16, 24))])
-def test_forward_matches_oracle(R, levels, shape):
+# Element-wise bars.  Against the plain FP64 oracle the BF16 storage of every
+# activation (relative rounding 2^-9) compounds over the layers: 2e-2 of the
+# largest output (4.4e-3 measured).  Against the oracle with the kernels' BF16 roundings applied
+# (leaky outputs and pooled tensors stored as BF16) only FP32 summation order
+# differs, which flips a BF16 rounding now and then (one BF16 ulp of one
+# activation, diluted by the following convolutions): 5e-3 of the largest
+# output (1.0e-3 measured).  A wrong halo, edge tile or skip slice moves the affected voxels by
+# the order of the output itself and fails both.
+ELEM = 2e-2
+ELEM_BF16 = 5e-3
+
+
+def _forward_bf16_oracle(U, ocfg, theta, x, monkeypatch):
+    leaky, pool2 = U.leaky, U.pool2
+    r = lambda a: bf16_round(a).astype(np.float64)
+    with monkeypatch.context() as mp:
+        mp.setattr(U, "leaky", lambda v, sl: r(leaky(v, sl)))
+        mp.setattr(U, "pool2", lambda v: r(pool2(v)))
+        ref, _ = U.forward(ocfg, theta.astype(np.float64), x.astype(np.float64))
+    return ref
+
+
+@pytest.mark.parametrize("levels,shape", [(3, (16, 16, 16)), (4, (32, 16, 24)),
+                                          (4, (64, 64, 64))])
+def test_forward_matches_oracle(R, levels, shape, monkeypatch):
     from oracle import unet as U
     print(f"unet forward levels={levels} shape={shape}", flush=True)
     cfg, ocfg, theta, x = _setup(R, levels, 16, shape, 11)
@@ -60,10 +83,18 @@ def test_forward_matches_oracle(R, levels, shape):
     out = torch.empty((3,) + tuple(shape), dtype=torch.float32, device="cuda")
     ws = R.alloc_workspace(R.unet_workspace_bytes(cfg, shape, False))
     R.unet_forward(cfg, params, _site_major(x), out, ws)
-    ref, _ = U.forward(ocfg, theta.astype(np.float64), x.astype(np.float64))
-    err = rel_l2(out.cpu().numpy(), np.moveaxis(ref, -1, 0))
-    print(f"  rel L2 {err:.2e}", flush=True)
+    got = out.cpu().numpy()
+    ref = np.moveaxis(U.forward(ocfg, theta.astype(np.float64), x.astype(np.float64))[0], -1, 0)
+    ref_b = np.moveaxis(_forward_bf16_oracle(U, ocfg, theta, x, monkeypatch), -1, 0)
+    err = rel_l2(got, ref)
+    scale = np.abs(ref).max()
+    e_max = np.abs(got - ref).max() / scale
+    e_max_b = np.abs(got - ref_b).max() / scale
+    print(f"  rel L2 {err:.2e}; max|d| / max|ref| {e_max:.2e} (FP64 oracle), {e_max_b:.2e} "
+          f"(BF16-rounded oracle)", flush=True)
     assert err <= REL_L2
+    assert e_max <= ELEM
+    assert e_max_b <= ELEM_BF16
 
 
 def test_gradient_matches_oracle(R):
@@ -124,10 +155,19 @@ def test_gradient_matches_oracle_with_bf16_rounding(R, monkeypatch):
     off = 0
     for name, ci, co in ocfg.layers():
         nw = co * 27 * ci
-        ew = rel_l2(g[off:off + nw], ref_grad[off:off + nw])
-        eb = rel_l2(g[off + nw:off + nw + co], ref_grad[off + nw:off + nw + co])
-        print(f"  {name} (BF16-rounded oracle): W {ew:.2e} b {eb:.2e}", flush=True)
+        gw, rw = g[off:off + nw], ref_grad[off:off + nw]
+        gb, rb = g[off + nw:off + nw + co], ref_grad[off + nw:off + nw + co]
+        ew = rel_l2(gw, rw)
+        eb = rel_l2(gb, rb)
+        # element-wise: every weight and bias gradient within 1e-2 of the
+        # layer's largest (the rounding flips of the BF16 operands, see ELEM_BF16,
+        # summed over the voxels of one tap; 1.3e-3 measured)
+        mw = np.abs(gw - rw).max() / np.abs(rw).max()
+        mb = np.abs(gb - rb).max() / np.abs(rb).max()
+        print(f"  {name} (BF16-rounded oracle): W {ew:.2e} b {eb:.2e}; element-wise "
+              f"{mw:.2e} / {mb:.2e}", flush=True)
         assert ew <= 5e-3 and eb <= 5e-3, name
+        assert mw <= 1e-2 and mb <= 1e-2, name
         off += nw + co
 
 
