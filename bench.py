@@ -388,9 +388,9 @@ def batch_comparison(R, inputs, count: int):
     # the same problems one after another (potential + solve + SFE each, one
     # workspace per grid, graphs captured in a warm-up pass)
     one = {}
-    for dp in dps:
-        if dp.shape not in one:
-            one[dp.shape] = R.alloc_workspace(R.rism3d_workspace_bytes(dp, opts))
+    for shape in {dp.shape for dp in dps}:   # sized for the largest solute of the grid
+        one[shape] = R.alloc_workspace(max(R.rism3d_workspace_bytes(dp, opts)
+                                           for dp in dps if dp.shape == shape))
 
     def single(dp):
         w = one[dp.shape]

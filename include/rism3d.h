@@ -189,11 +189,14 @@ rism3d_status rism3d_solve(const rism3d_problem* problem, const rism3d_opts* opt
  * damping: a high-order PSE closure (Kast & Kloss) or HNC (Eq 14) started
  * from t = f can diverge where KH (Eq 15) converges.  Every stage must give
  * the workspace layout of stages[0] (same MDIIS depth and accelerator);
- * closure, order, tol, max_iter and damping may differ.  info (host, may be
- * NULL) receives n_stages entries.  The first stage that does not return
- * RISM3D_OK ends the ladder with its status (later entries of info are not
- * written).  d_g (may be NULL) receives g of the last stage, and
- * rism3d_thermo with the last stage's options evaluates its free energy. */
+ * closure, order, tol, max_iter and damping may differ; a stage may repeat
+ * the one before (the next stage starts with an empty MDIIS history).  info
+ * (host, may be NULL) receives n_stages entries.  A stage that reaches its
+ * max_iter (RISM3D_E_NOCONV) still hands its last iterate to the next stage;
+ * any other failing status ends the ladder with it (later entries of info
+ * are not written).  The ladder's status is the last stage's.  d_g (may be
+ * NULL) receives g of the last stage, and rism3d_thermo with the last
+ * stage's options evaluates its free energy. */
 rism3d_status rism3d_solve_ladder(const rism3d_problem* problem, const rism3d_opts* stages,
                                   int n_stages, const float* d_tau0, void* d_ws, size_t ws_bytes,
                                   float* d_g, rism3d_info* info, hipStream_t stream);

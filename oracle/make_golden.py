@@ -102,7 +102,9 @@ def make(name: str, out_dir: str = OUT_DIR, log=print) -> str:
     q_v = prob.solvent.site_arrays()[0]
     k = int(np.argmax(np.abs(q_v)))
     phi_ref = (sys_.f[k] / (sys_.beta * rism3d.COULOMB * q_v[k])).reshape(-1)[idx]
-    meta = dict(name=name, tol=tol, rms_tol=sol_tol.rms, rms_tight=sol_tight.rms, rms_ref=sol.rms,
+    meta = dict(name=name, tol=tol, mdiis_eta=prob.options.mdiis_eta,
+                mdiis_depth=prob.options.mdiis_depth, rms_tol=sol_tol.rms,
+                rms_tight=sol_tight.rms, rms_ref=sol.rms,
                 restarts=sol_tol.restarts, seconds=time.time() - t0,
                 iterations_tight_from_tol=sol_tight.iterations,
                 iterations_ref_from_tight=sol.iterations)

@@ -83,7 +83,8 @@ __global__ void k_init_tau(const float* __restrict__ tau0, float* __restrict__ s
   }
 }
 
-__global__ void k_mark_prepared(IterState* st, unsigned layout_key) {
+__global__ void k_mark_prepared(IterState* st, unsigned layout_key, int* tickets, int n_tickets) {
+  for (int i = threadIdx.x; i < n_tickets; i += blockDim.x) tickets[i] = 0;
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     st->prepared = kPreparedMagic;
     st->layout_key = layout_key;
@@ -712,10 +713,14 @@ __device__ inline bool anderson_theta(const IterState& st, int s0, int s1, int s
 // the next FP64 evaluation to re-evaluate it (kDoneVerify); that evaluation
 // either finishes the solve or continues it as an ordinary step whose
 // residual is exact.
+// slot and c: scratch for kMaxDepth entries each (shared memory in the fused
+// residual kernel, which keeps its registers for the residual itself).
+template <bool REG_SOLVE = true>
 __device__ __forceinline__ void control_step(IterState& st, const double* sums,
                                     double (*A)[kMaxDepth + 2], int M, double inv_count,
                                     double tol, int max_iter, float eta_static, int eta_dynamic,
-                                    int accel, double as1, double as2, int anchor) {
+                                    int accel, double as1, double as2, int anchor, int* slot,
+                                    double* c) {
   const bool anderson = accel == RISM3D_ANDERSON;
   const int dest = st.dest;
   const double rr = sums[M];
@@ -778,7 +783,6 @@ __device__ __forceinline__ void control_step(IterState& st, const double* sums,
     st.gram[dest][dest] = anderson ? sums[dest] : rr;   // weighted for Anderson (Eq 38)
   }
   // Stored slots, oldest first.
-  int slot[kMaxDepth];
   int m = 0;
   for (int i = 0; i < M; ++i)
     if (st.stored[i]) slot[m++] = i;
@@ -791,7 +795,6 @@ __device__ __forceinline__ void control_step(IterState& st, const double* sums,
     }
     slot[b + 1] = v;
   }
-  double c[kMaxDepth];
   double theta[2];
   if (anderson) {
     // Picard for the first two steps (and for a singular theta system), then
@@ -807,7 +810,8 @@ __device__ __forceinline__ void control_step(IterState& st, const double* sums,
     }
   } else if (m == 1) {
     c[0] = 1.0;
-  } else if (!bordered_dispatch(st, slot, m, M, c, A)) {
+  } else if (!(REG_SOLVE ? bordered_dispatch(st, slot, m, M, c, A)
+                         : bordered_solve_lds(st, slot, m, c, A))) {
     // ill-conditioned subspace: restart from the best stored pair
     int b = slot[0];
     for (int i = 1; i < m; ++i)
@@ -850,6 +854,8 @@ struct ControlScratch {
   double wsum[kCtlThreads / 64][kMaxDepth + 1];
   double sums[kMaxDepth + 1];
   double A[kMaxDepth + 1][kMaxDepth + 2];
+  double c[kMaxDepth];
+  int slot[kMaxDepth];
 };
 
 // Reduce the partials of `nblocks` blocks in fixed order and run one control
@@ -915,9 +921,98 @@ __device__ __forceinline__ void control_block(IterState* __restrict__ st_g,
   }
   __syncthreads();
   if (threadIdx.x == 0) {
+    int slot[kMaxDepth];
+    double c[kMaxDepth];
     control_step(cs.st, cs.sums, cs.A, M, inv_count, tol, max_iter, eta_static, eta_dynamic,
-                 accel, as1, as2, anchor);
+                 accel, as1, as2, anchor, slot, c);
     // residual history: the RMS of evaluation i (1-based) and whether it was exact
+    const int it = cs.st.iter;
+    if (it >= 1 && it <= kHistLen) hist[it - 1] = make_double2(cs.st.last_rms, anchor ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  {
+    const int* src = reinterpret_cast<const int*>(&cs.st);
+    int* dst = reinterpret_cast<int*>(st_g);
+    for (int i = threadIdx.x; i < (int)(sizeof(IterState) / sizeof(int)); i += blockDim.x)
+      dst[i] = src[i];
+  }
+}
+
+// Options of the control step, passed by value to the fused residual kernel.
+// on = 0 leaves the reduction and the control step out (the autotuner times
+// the residual kernel alone).
+struct CtlArgs {
+  double inv_count, tol, as1, as2;
+  int max_iter, eta_dynamic, accel, on;
+  float eta_static;
+};
+
+// Workgroups per chunk of the two-level reduction below.
+constexpr int kChunkBlocks = 64;
+
+__device__ __forceinline__ double load_agent(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The end of an iteration inside the kernel that wrote the partial rows (one
+// row of M + 1 sums per workgroup, written by thread 0 of each): a two-level
+// reduction with the control step in the last workgroup to finish.  The last
+// workgroup to arrive within each chunk of kChunkBlocks consecutive
+// workgroups sums the chunk's rows in workgroup order into a chunk row; the
+// last chunk to finish sums the chunk rows in chunk order and runs the
+// control step on the state.  Every addition has a fixed order, so the result
+// does not depend on which workgroup finishes last.  tickets holds one
+// counter per chunk plus one for the chunks (zero between launches: each
+// last arriver resets the counter it consumed).  Every workgroup of the
+// launch calls this after its row is written; the state is rewritten only
+// after every workgroup has passed its start (where it reads the state).
+__device__ void finish_iteration(IterState* __restrict__ st_g, const double* partials,
+                                 double* chunk_rows, int* tickets, int M, int anchor,
+                                 const CtlArgs& a, double2* __restrict__ hist,
+                                 ControlScratch& cs, int* flag) {
+  const int nblocks = (int)gridDim.x;
+  const int nchunks = (nblocks + kChunkBlocks - 1) / kChunkBlocks;
+  const int c = (int)blockIdx.x / kChunkBlocks;
+  const int first = c * kChunkBlocks;
+  const int cnt = nblocks - first < kChunkBlocks ? nblocks - first : kChunkBlocks;
+  if (threadIdx.x == 0) {
+    __threadfence();   // this workgroup's row before its ticket
+    *flag = atomicAdd(&tickets[c], 1) == cnt - 1;
+  }
+  __syncthreads();
+  if (!*flag) return;
+  __threadfence();
+  if ((int)threadIdx.x <= M) {
+    double sum = 0.0;
+    for (int b = first; b < first + cnt; ++b)
+      sum += load_agent(&partials[(size_t)b * (M + 1) + threadIdx.x]);
+    chunk_rows[(size_t)c * (M + 1) + threadIdx.x] = sum;
+    __threadfence();
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    tickets[c] = 0;
+    *flag = atomicAdd(&tickets[nchunks], 1) == nchunks - 1;
+  }
+  __syncthreads();
+  if (!*flag) return;
+  __threadfence();
+  {
+    const int* src = reinterpret_cast<const int*>(st_g);
+    int* dst = reinterpret_cast<int*>(&cs.st);
+    for (int i = threadIdx.x; i < (int)(sizeof(IterState) / sizeof(int)); i += blockDim.x)
+      dst[i] = src[i];
+  }
+  if ((int)threadIdx.x <= M) {
+    double sum = 0.0;
+    for (int k = 0; k < nchunks; ++k) sum += load_agent(&chunk_rows[(size_t)k * (M + 1) + threadIdx.x]);
+    cs.sums[threadIdx.x] = sum;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    tickets[nchunks] = 0;
+    control_step<false>(cs.st, cs.sums, cs.A, M, a.inv_count, a.tol, a.max_iter, a.eta_static,
+                        a.eta_dynamic, a.accel, a.as1, a.as2, anchor, cs.slot, cs.c);
     const int it = cs.st.iter;
     if (it >= 1 && it <= kHistLen) hist[it - 1] = make_double2(cs.st.last_rms, anchor ? 1.0 : 0.0);
   }

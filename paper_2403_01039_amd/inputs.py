@@ -171,7 +171,7 @@ class Options:
     tol: float = 1e-6
     max_iter: int = 5000
     mdiis_depth: int = 5
-    mdiis_eta: float = 0.7         # MDIIS damping, or the modified-Anderson mixing b
+    mdiis_eta: float = 0.6         # MDIIS damping, or the modified-Anderson mixing b
     eta_dynamic: bool = False
     accelerator: str = "mdiis"     # "mdiis" | "anderson" (modified Anderson, two histories)
     anderson_s1: float = 0.2

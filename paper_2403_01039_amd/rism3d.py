@@ -309,8 +309,8 @@ def rism3d_solve(dp, opts, ws, tau0=None, g_out=None, stream=None, allow_noconv=
 
 def rism3d_solve_ladder(dp, stages, ws, tau0=None, g_out=None, stream=None):
     """Closure ladder: a list of Opts run in order, each stage from the last
-    one's iterate; returns the list of Info of the stages that ran (the
-    failing stage's status raises)."""
+    one's iterate; returns the list of Info of the stages (a failing last
+    stage, or a stage failing otherwise than by reaching max_iter, raises)."""
     n = len(stages)
     arr = (Opts * n)(*stages)
     infos = (Info * n)()
@@ -320,8 +320,8 @@ def rism3d_solve_ladder(dp, stages, ws, tau0=None, g_out=None, stream=None):
                                      _stream(stream))
     _check(status)
     out = list(infos)
-    for inf in out:
-        inf.status = 0
+    for inf, op in zip(out, stages):   # a stage short of its tolerance hands on (E_NOCONV)
+        inf.status = 0 if inf.rms < op.tol else 3
     return out
 
 
