@@ -90,6 +90,39 @@ def test_uneven_batch_64_solutes(R):
     assert all(inf.rms < 1e-6 for inf in infos)
 
 
+@pytest.mark.parametrize("tol", [1e-6, 1e-8])
+def test_batch_members_against_the_oracle(R, tol):
+    """Members of the uneven batch against stored FP64 oracle values (seed
+    1000 on 96^3, seed 1001 on 128^3; oracle at rms 1e-10, sampled at a
+    seeded choice, the contact peaks and its worst stopping-error points), in
+    one batched call with four more members of both grids.  At rms 1e-6 the
+    allowance is 1.5 x the oracle's own stopping error over the whole grid
+    and the iteration count is within 25% of the oracle's; at rms 1e-8 the
+    bar is 1e-4 with no allowance."""
+    import os
+    probs = [inputs.batch_member_problem(sd) for sd in (1000, 1001, 1002, 1003, 1004, 1005)]
+    opts = R.make_opts(probs[0].options, tol=tol)
+    gs, infos, sfe = _batch(R, probs, opts)
+    for k, sd in enumerate((1000, 1001)):
+        ref = np.load(os.path.join(os.path.dirname(__file__), "golden", f"batch_{sd}.npz"))
+        idx = torch.as_tensor(ref["idx"], device="cuda")
+        got = gs[k].reshape(gs[k].shape[0], -1)[:, idx].cpu().numpy()
+        err = np.abs(got - ref["g_ref"]).max()
+        stop = float(ref["stop_err_tol"])
+        it_ref = int(ref["iterations_tol"])
+        print(f"  batch member {sd} ({probs[k].grid.nx}^3, {probs[k].solute.n_atoms} atoms) at "
+              f"rms {tol}: it {infos[k].iterations} (oracle {it_ref} at 1e-6) max|dg| {err:.2e} "
+              f"(oracle stopping error {stop:.2e}) sfe {sfe[k][0]:.4f} vs "
+              f"{float(ref['sfe_ref']):.4f}", flush=True)
+        assert infos[k].rms < tol
+        assert abs(sfe[k][0] - ref["sfe_ref"]) <= 1e-3 * abs(ref["sfe_ref"])
+        if tol == 1e-6:
+            assert err <= max(1e-4, 1.5 * stop)
+            assert abs(infos[k].iterations - it_ref) <= 0.25 * it_ref
+        else:
+            assert err <= 1e-4
+
+
 def test_anderson_batch_equals_single_solves(R):
     """Modified Anderson in a batch: members in water and in saline (different
     Gram weights, so different groups) equal their single solves bit for bit."""

@@ -281,10 +281,16 @@ def test_single_site_64_golden(R):
 def test_full_size_golden(R, name):
     """The 128^3 workloads (200-atom solute in water + 0.1 M NaCl, and in
     water) at full size, in the launch configuration the benchmark times
-    (graph replay of anchor periods), against stored oracle values on 6000+
-    sampled points: the potential w and phi, the converged g (oracle at rms
-    1e-10) and the SFE.  The stopping-rule allowance is the oracle's own
-    distance between its rms-1e-6 and rms-1e-10 solutions."""
+    (graph replay of anchor periods), against stored oracle values on the
+    sampled points (a seeded choice, the centre line, the oracle's contact
+    peaks and the points where its own rms-1e-6 solution is furthest from the
+    fixed point): the potential w and phi, the SFE, and g.
+      * At the paper's rms 1e-6 the oracle's own iterate is up to
+        stop_err_tol (a few 1e-3, over the whole grid) from its rms-1e-10
+        solution; the GPU's must be within 1.5 x that, and its iteration
+        count within 25% of the oracle's (same MDIIS depth and damping).
+      * At rms 1e-8 both are close to the one fixed point: max |dg| <= 1e-4,
+        the bar of the benchmark spec, with no allowance."""
     import os
     ref = np.load(os.path.join(os.path.dirname(__file__), "golden", f"{name}.npz"))
     seed = 1 if name == "solute_200_saline" else int(name.split("_")[1])
@@ -308,15 +314,25 @@ def test_full_size_golden(R, name):
     sfe, _ = s.thermo()
     gs = g.reshape(g.shape[0], -1)[:, idx].cpu().numpy()
     err = np.abs(gs - ref["g_ref"]).max()
-    stop = np.abs(ref["g_tol"] - ref["g_ref"]).max()
+    stop = float(ref["stop_err_tol"])
     it_ref = int(ref["iterations_tol"])
-    print(f"  it {info.iterations} (oracle {it_ref}) rms {info.rms:.2e} max|dg| {err:.2e} "
-          f"(oracle stopping error {stop:.2e}) sfe {sfe:.4f} vs {float(ref['sfe_ref']):.4f}",
-          flush=True)
+    print(f"  rms 1e-6: it {info.iterations} (oracle {it_ref}) rms {info.rms:.2e} max|dg| "
+          f"{err:.2e} (oracle stopping error {stop:.2e}) sfe {sfe:.4f} vs "
+          f"{float(ref['sfe_ref']):.4f}", flush=True)
     assert info.rms < 1e-6
     assert err <= max(G_TOL, 1.5 * stop)
     assert abs(sfe - ref["sfe_ref"]) <= SFE_RTOL * abs(ref["sfe_ref"])
     assert abs(info.iterations - it_ref) <= 0.25 * it_ref
+    s.opts = R.make_opts(prob.options, tol=1e-8)
+    info = s.solve(g_out=g)
+    sfe, _ = s.thermo()
+    gs = g.reshape(g.shape[0], -1)[:, idx].cpu().numpy()
+    err = np.abs(gs - ref["g_ref"]).max()
+    print(f"  rms 1e-8: it {info.iterations} rms {info.rms:.2e} max|dg| {err:.2e} sfe "
+          f"{sfe:.4f}", flush=True)
+    assert info.rms < 1e-8
+    assert err <= G_TOL
+    assert abs(sfe - ref["sfe_ref"]) <= SFE_RTOL * abs(ref["sfe_ref"])
 
 
 def test_globule_4000_at_256(R, O):

@@ -46,13 +46,12 @@ def _solve(R, net, prob, warm):
 def test_warm_start_meets_the_oracle_bar_on_held_out_seed(R, net):
     """Both solves stop at rms 1e-6, each somewhere in the same tolerance ball
     around the fixed point; the oracle's own rms-1e-6 iterate is one sample of
-    how far that is (its stopping error).  The plain solve gets the parity
-    tests' 1.5x allowance; the warm-started trajectory, which reaches the
-    ball from another direction, 3x."""
+    how far that is (its stopping error, the largest over the whole grid).
+    Both solves get the parity tests' 1.5x allowance."""
     ref = np.load(GOLDEN)
     prob = inputs.warmstart_problem(20000)
     idx = torch.as_tensor(ref["idx"], device="cuda")
-    stop = np.abs(ref["g_tol"] - ref["g_ref"]).max()
+    stop = float(ref["stop_err_tol"])
     res = {}
     for warm in (False, True):
         g, info, sfe = _solve(R, net, prob, warm)
@@ -62,7 +61,7 @@ def test_warm_start_meets_the_oracle_bar_on_held_out_seed(R, net):
               f"max|dg| vs oracle {err:.2e} (oracle stopping error {stop:.2e}), "
               f"sfe {sfe:.4f} vs {float(ref['sfe_ref']):.4f}", flush=True)
         assert info.rms < 1e-6
-        assert err <= max(1e-4, (3.0 if warm else 1.5) * stop)
+        assert err <= max(1e-4, 1.5 * stop)
         assert abs(sfe - ref["sfe_ref"]) <= 1e-3 * abs(ref["sfe_ref"])
         if warm:
             assert info.warm_start_used == 1
@@ -85,21 +84,25 @@ def test_warm_start_saves_iterations_on_held_out_seeds(R, net):
 
 
 def test_warm_and_plain_meet_at_a_tighter_tolerance(R, net):
-    """At rms 4e-7 both trajectories are closer to the fixed point: the warm
-    start meets the plain solve's 1.5x bar as well, and the two g move
-    towards each other."""
+    """At rms 1e-8 both trajectories are at the one fixed point: each g is
+    within the benchmark spec's 1e-4 of the oracle's on the sampled points
+    (which include the oracle's worst stopping-error points and the contact
+    peaks), and the two g agree to 2e-4 on every grid point.  The warm start
+    changes only the iteration count."""
     ref = np.load(GOLDEN)
     prob = inputs.warmstart_problem(20000)
-    prob.options.tol = 4e-7
+    prob.options.tol = 1e-8
     idx = torch.as_tensor(ref["idx"], device="cuda")
-    stop = np.abs(ref["g_tol"] - ref["g_ref"]).max()
     gs = {}
     for warm in (False, True):
-        g, info, _ = _solve(R, net, prob, warm)
+        g, info, sfe = _solve(R, net, prob, warm)
         err = np.abs(g.reshape(3, -1)[:, idx].cpu().numpy() - ref["g_ref"]).max()
-        print(f"seed 20000 at rms 4e-7, {'warm' if warm else 'plain'}: {info.iterations} "
-              f"iterations, max|dg| vs oracle {err:.2e}", flush=True)
-        assert info.rms < 4e-7
-        assert err <= max(1e-4, 1.5 * stop)
+        print(f"seed 20000 at rms 1e-8, {'warm' if warm else 'plain'}: {info.iterations} "
+              f"iterations, max|dg| vs oracle {err:.2e}, sfe {sfe:.4f}", flush=True)
+        assert info.rms < 1e-8
+        assert err <= 1e-4
+        assert abs(sfe - ref["sfe_ref"]) <= 1e-3 * abs(ref["sfe_ref"])
         gs[warm] = g
-    print(f"  max|g_warm - g_plain| {(gs[True] - gs[False]).abs().max().item():.2e}", flush=True)
+    d = (gs[True] - gs[False]).abs().max().item()
+    print(f"  max|g_warm - g_plain| over the whole grid {d:.2e}", flush=True)
+    assert d <= 2e-4
