@@ -78,12 +78,12 @@ __global__ __launch_bounds__(kFftThreads) void k_update_fftx(
 // thread); the launch picks the smallest instantiated bound >= M.
 template <bool ANCHOR, int N, int LINES = fixed_lines<PrecC<ANCHOR>, N, 0>(), int MM = kMaxDepth>
 __global__ __launch_bounds__(kFftThreads) void k_fftx_residual(
-    IterState* st, const void* __restrict__ spec_v,
+    const IterState* __restrict__ st, const void* __restrict__ spec_v,
     const float* __restrict__ w, float* __restrict__ tau_hist, float* __restrict__ res_hist,
     float* __restrict__ tau_ref, float* __restrict__ tau_lo, float* __restrict__ r_ref,
     const float* __restrict__ dg, int ny, int nz, int nv, int npair, int M, int kind, int order,
-    const PrecC<ANCHOR>* __restrict__ tw2_g, double* partials, GramW gw, double* chunk_rows,
-    int* tickets, CtlArgs ctl, double2* __restrict__ hist, size_t bstride) {
+    const PrecC<ANCHOR>* __restrict__ tw2_g, double* __restrict__ partials, GramW gw,
+    size_t bstride) {
   using C = PrecC<ANCHOR>;
   using S = typename ScalarOf<C>::type;
   constexpr int Q = N / 4;
@@ -99,16 +99,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fftx_residual(
   dg = member_ptr(dg, bstride);
   tw2_g = member_ptr(tw2_g, bstride);
   partials = member_ptr(partials, bstride);
-  chunk_rows = member_ptr(chunk_rows, bstride);
-  tickets = member_ptr(tickets, bstride);
-  hist = member_ptr(hist, bstride);
-  // the line tile, and after the residual the control scratch of the last
-  // workgroup, share one shared-memory block
-  constexpr size_t kBufBytes = (size_t)LINES * Lds<N>::PITCH * sizeof(C);
-  constexpr size_t kRawBytes =
-      kBufBytes > sizeof(ControlScratch) ? kBufBytes : sizeof(ControlScratch);
-  __shared__ __align__(16) unsigned char raw[kRawBytes];
-  C* buf = reinterpret_cast<C*>(raw);
+  __shared__ C buf[LINES * Lds<N>::PITCH];
   __shared__ C tw2[2 * N];
   __shared__ double red[kFftThreads / 64];
   for (int i = threadIdx.x; i < 2 * N; i += kFftThreads) tw2[i] = tw2_g[i];
@@ -169,13 +160,6 @@ __global__ __launch_bounds__(kFftThreads) void k_fftx_residual(
                                    dg, N3, nv, p, n, dest, mask, kind, order, gw, acc);
   }
   write_partials<MM>(acc, M, partials, red);
-  if (ctl.on) {
-    // every thread is past its last read of the tile (write_partials ends
-    // with a barrier), so the tile's memory can hold the control scratch
-    __shared__ int flag;
-    finish_iteration(st, partials, chunk_rows, tickets, M, ANCHOR ? 1 : 0, ctl, hist,
-                     *reinterpret_cast<ControlScratch*>(raw), &flag);
-  }
 }
 
 }  // namespace rism

@@ -83,8 +83,7 @@ __global__ void k_init_tau(const float* __restrict__ tau0, float* __restrict__ s
   }
 }
 
-__global__ void k_mark_prepared(IterState* st, unsigned layout_key, int* tickets, int n_tickets) {
-  for (int i = threadIdx.x; i < n_tickets; i += blockDim.x) tickets[i] = 0;
+__global__ void k_mark_prepared(IterState* st, unsigned layout_key) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     st->prepared = kPreparedMagic;
     st->layout_key = layout_key;
@@ -485,18 +484,21 @@ __device__ inline unsigned other_slots(const IterState* __restrict__ st, int M, 
 }
 
 // Write this block's partial sums (fixed block order, reduced in fixed order).
+// Partials are column-major: quantity i of workgroup b at i * gridDim.x + b,
+// so the control kernel reads each quantity as one contiguous run.
 template <int MM = kMaxDepth>
 __device__ inline void write_partials(const double* acc, int M, double* __restrict__ partials,
                                       double* red) {
+  const size_t nb = gridDim.x;
 #pragma unroll
   for (int i = 0; i < MM; ++i) {
     if (i < M) {   // M is uniform: every thread takes the same branches
       const double s = block_sum(acc[i], red);
-      if (threadIdx.x == 0) partials[(size_t)blockIdx.x * (M + 1) + i] = s;
+      if (threadIdx.x == 0) partials[i * nb + blockIdx.x] = s;
     }
   }
   const double s = block_sum(acc[MM], red);
-  if (threadIdx.x == 0) partials[(size_t)blockIdx.x * (M + 1) + M] = s;
+  if (threadIdx.x == 0) partials[(size_t)M * nb + blockIdx.x] = s;
 }
 
 template <bool ANCHOR, int V>
@@ -550,145 +552,6 @@ __global__ __launch_bounds__(kRedThreads) void k_residual(
   write_partials(acc, M, partials, red);
 }
 
-// Bordered MDIIS system of the m stored slots, embedded in a fixed (MM+1) x
-// (MM+1) system so every index is a compile-time constant and the matrix lives
-// in registers: rows/columns 0..m-1 hold B / max diag(B) with the -1 border in
-// column/row MM; rows m..MM-1 are identity rows (their c_i = 0).  Gaussian
-// elimination with partial pivoting in FP64.  Returns false (restart) when a
-// pivot falls below 1e-12.
-template <int MM>
-__device__ inline bool bordered_solve(const IterState& st, const int* slot, int m, double* c) {
-  constexpr int n = MM + 1;
-  double A[n][n + 1];
-  double scale = 0.0;
-#pragma unroll
-  for (int i = 0; i < MM; ++i)
-    if (i < m) scale = fmax(scale, st.gram[slot[i]][slot[i]]);
-  const double inv = 1.0 / scale;
-#pragma unroll
-  for (int i = 0; i < n; ++i) {
-#pragma unroll
-    for (int j = 0; j <= n; ++j) {
-      double a = 0.0;
-      if (i < MM && j < MM) {
-        if (i < m && j < m) a = st.gram[slot[i]][slot[j]] * inv;
-        else if (i == j) a = 1.0;
-      } else if (i < MM && j == MM) {
-        a = i < m ? -1.0 : 0.0;
-      } else if (i == MM && j < MM) {
-        a = j < m ? -1.0 : 0.0;
-      } else if (i == MM && j == n) {
-        a = -1.0;   // right-hand side of the constraint row
-      }
-      A[i][j] = a;
-    }
-  }
-  double min_piv = 1.0e300;
-#pragma unroll
-  for (int col = 0; col < n; ++col) {
-    int piv = col;
-    double best = fabs(A[col][col]);
-#pragma unroll
-    for (int r = col + 1; r < n; ++r)
-      if (fabs(A[r][col]) > best) {
-        best = fabs(A[r][col]);
-        piv = r;
-      }
-#pragma unroll
-    for (int r = col + 1; r < n; ++r) {
-      if (r == piv) {
-#pragma unroll
-        for (int j = 0; j <= n; ++j) {
-          const double t = A[col][j];
-          A[col][j] = A[r][j];
-          A[r][j] = t;
-        }
-      }
-    }
-    const double pv = A[col][col];
-    min_piv = fmin(min_piv, fabs(pv));
-    if (!(fabs(pv) >= 1.0e-300)) return false;
-#pragma unroll
-    for (int r = col + 1; r < n; ++r) {
-      const double f = A[r][col] / pv;
-#pragma unroll
-      for (int j = col; j <= n; ++j) A[r][j] -= f * A[col][j];
-    }
-  }
-  if (min_piv < 1.0e-12) return false;
-  double x[n];
-#pragma unroll
-  for (int r = n - 1; r >= 0; --r) {
-    double t = A[r][n];
-#pragma unroll
-    for (int j = r + 1; j < n; ++j) t -= A[r][j] * x[j];
-    x[r] = t / A[r][r];
-  }
-#pragma unroll
-  for (int i = 0; i < MM; ++i)
-    if (i < m) c[i] = x[i];
-  return true;
-}
-
-// LDS-resident fallback for depths beyond the register version.
-__device__ inline bool bordered_solve_lds(const IterState& st, const int* slot, int m, double* c,
-                                          double (*A)[kMaxDepth + 2]) {
-  double scale = 0.0;
-  for (int i = 0; i < m; ++i) scale = fmax(scale, st.gram[slot[i]][slot[i]]);
-  const int n = m + 1;
-  for (int i = 0; i < m; ++i) {
-    for (int j = 0; j < m; ++j) A[i][j] = st.gram[slot[i]][slot[j]] / scale;
-    A[i][m] = -1.0;
-    A[m][i] = -1.0;
-    A[i][n] = 0.0;
-  }
-  A[m][m] = 0.0;
-  A[m][n] = -1.0;
-  double min_piv = 1.0e300;
-  for (int col = 0; col < n; ++col) {
-    int piv = col;
-    for (int r = col + 1; r < n; ++r)
-      if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
-    if (piv != col) {
-      for (int j = 0; j <= n; ++j) {
-        const double t = A[col][j];
-        A[col][j] = A[piv][j];
-        A[piv][j] = t;
-      }
-    }
-    const double pv = A[col][col];
-    min_piv = fmin(min_piv, fabs(pv));
-    if (fabs(pv) < 1.0e-300) return false;
-    for (int r = col + 1; r < n; ++r) {
-      const double f = A[r][col] / pv;
-      for (int j = col; j <= n; ++j) A[r][j] -= f * A[col][j];
-    }
-  }
-  if (min_piv < 1.0e-12) return false;
-  for (int r = n - 1; r >= 0; --r) {
-    double s = A[r][n];
-    for (int j = r + 1; j < n; ++j) s -= A[r][j] * A[j][n];
-    A[r][n] = s / A[r][r];
-  }
-  for (int i = 0; i < m; ++i) c[i] = A[i][n];
-  return true;
-}
-
-__device__ inline bool bordered_dispatch(const IterState& st, const int* slot, int m, int M,
-                                         double* c, double (*A)[kMaxDepth + 2]) {
-  switch (M) {
-    case 1: return bordered_solve<1>(st, slot, m, c);
-    case 2: return bordered_solve<2>(st, slot, m, c);
-    case 3: return bordered_solve<3>(st, slot, m, c);
-    case 4: return bordered_solve<4>(st, slot, m, c);
-    case 5: return bordered_solve<5>(st, slot, m, c);
-    case 6: return bordered_solve<6>(st, slot, m, c);
-    // deeper histories solve in LDS: a register-resident system of 8 or more
-    // unknowns would cap the control workgroup at 256 threads
-    default: return bordered_solve_lds(st, slot, m, c, A);
-  }
-}
-
 // One control step on a (shared-memory) copy of the state; single thread.
 // theta of Eq 36 from the stored weighted Gram entries of the newest (0) and
 // the two previous (1, 2) residuals; false when the 2x2 system is singular.
@@ -707,164 +570,257 @@ __device__ inline bool anderson_theta(const IterState& st, int s0, int s1, int s
 }
 
 // accel: RISM3D_MDIIS or RISM3D_ANDERSON (shifts as1, as2; mixing eta_static).
-// anchor: the evaluation just finished was the exact FP64 one.  The stopping
-// test of Eq 41 is decided on exact residuals only: an FP32 residual (R_ref +
-// dh - dg, an estimate) below tol holds its iterate in slot dest and asks for
-// the next FP64 evaluation to re-evaluate it (kDoneVerify); that evaluation
-// either finishes the solve or continues it as an ordinary step whose
-// residual is exact.
-// slot and c: scratch for kMaxDepth entries each (shared memory in the fused
-// residual kernel, which keeps its registers for the residual itself).
-template <bool REG_SOLVE = true>
-__device__ __forceinline__ void control_step(IterState& st, const double* sums,
-                                    double (*A)[kMaxDepth + 2], int M, double inv_count,
-                                    double tol, int max_iter, float eta_static, int eta_dynamic,
-                                    int accel, double as1, double as2, int anchor, int* slot,
-                                    double* c) {
-  const bool anderson = accel == RISM3D_ANDERSON;
-  const int dest = st.dest;
-  const double rr = sums[M];
-  const double rms = sqrt(rr * inv_count);
-  st.hold = 0;
-  st.done = 0;
-  st.iter += 1;
-  st.last_rms = rms;
-  st.last_rr = rr;
-  if (!(rr == rr) || rr > 1.0e300) {
-    st.status = RISM3D_E_NONFINITE;
-    st.final_slot = dest;
-    st.done = kDoneFinished;
-    return;
-  }
-  if (rms < tol) {
-    st.final_slot = dest;
-    if (anchor) {
-      st.converged = 1;
-      st.done = kDoneFinished;
-    } else {
-      st.stored[dest] = 0;   // its old pair was overwritten; the FP64 pass stores it anew
-      st.hold = 1;
-      st.done = kDoneVerify;
-    }
-    return;
-  }
-  if (st.iter >= max_iter) {
-    st.status = RISM3D_E_NOCONV;
-    st.final_slot = dest;
-    st.done = kDoneFinished;
-    return;
-  }
-  // The destination slot's old pair (the oldest, when the ring was full) has
-  // been overwritten by the new iterate: drop it.
-  st.stored[dest] = 0;
-  int best = -1;
-  double best_rms = 0.0;
-  for (int i = 0; i < M; ++i) {
-    if (st.stored[i] && (best < 0 || st.rms_slot[i] < best_rms)) {
-      best = i;
-      best_rms = st.rms_slot[i];
-    }
-  }
-  if (!anderson && best >= 0 && rms > 10.0 * best_rms) {
-    for (int i = 0; i < M; ++i) st.stored[i] = (i == best);
-    st.newest = best;
-    st.restarts += 1;
-  } else {
-    st.stored[dest] = 1;
-    st.newest = dest;
-    st.rms_slot[dest] = rms;
-    st.stamp[dest] = ++st.stamp_counter;
-    for (int i = 0; i < M; ++i) {
-      if (st.stored[i] && i != dest) {
-        st.gram[dest][i] = sums[i];
-        st.gram[i][dest] = sums[i];
-      }
-    }
-    st.gram[dest][dest] = anderson ? sums[dest] : rr;   // weighted for Anderson (Eq 38)
-  }
-  // Stored slots, oldest first.
-  int m = 0;
-  for (int i = 0; i < M; ++i)
-    if (st.stored[i]) slot[m++] = i;
-  for (int a = 1; a < m; ++a) {
-    const int v = slot[a];
-    int b = a - 1;
-    while (b >= 0 && st.stamp[slot[b]] > st.stamp[v]) {
-      slot[b + 1] = slot[b];
-      --b;
-    }
-    slot[b + 1] = v;
-  }
-  double theta[2];
-  if (anderson) {
-    // Picard for the first two steps (and for a singular theta system), then
-    // X = sum c_k (X_k + b R_k) with c = (theta_2 + s_2, theta_1 + s_1,
-    // 1 - sum(theta + s)) on the three pairs oldest first (Eq 34-39)
-    for (int i = 0; i < m; ++i) c[i] = 0.0;
-    c[m - 1] = 1.0;
-    if (m == 3 && anderson_theta(st, slot[2], slot[1], slot[0], theta)) {
-      const double k1 = theta[0] + as1, k2 = theta[1] + as2;
-      c[2] = 1.0 - k1 - k2;
-      c[1] = k1;
-      c[0] = k2;
-    }
-  } else if (m == 1) {
-    c[0] = 1.0;
-  } else if (!(REG_SOLVE ? bordered_dispatch(st, slot, m, M, c, A)
-                         : bordered_solve_lds(st, slot, m, c, A))) {
-    // ill-conditioned subspace: restart from the best stored pair
-    int b = slot[0];
-    for (int i = 1; i < m; ++i)
-      if (st.rms_slot[slot[i]] < st.rms_slot[b]) b = slot[i];
-    for (int i = 0; i < M; ++i) st.stored[i] = (i == b);
-    st.newest = b;
-    slot[0] = b;
-    m = 1;
-    c[0] = 1.0;
-    st.restarts += 1;
-  }
-  for (int i = 0; i < M; ++i) st.coef[i] = 0.0f;
-  for (int i = 0; i < m; ++i) st.coef[slot[i]] = (float)c[i];
-  float eta = eta_static;
-  if (eta_dynamic && !anderson) eta = (float)fmin(fmax(-0.2 * log(rms), 0.1), 1.0);
-  st.eta = eta;
-  // Next destination: a free slot while the ring is not full, else the oldest.
-  int next = -1;
-  if (m < M) {
-    for (int i = 0; i < M; ++i)
-      if (!st.stored[i]) {
-        next = i;
-        break;
-      }
-  } else {
-    next = slot[0];
-  }
-  st.dest = next;
-}
-
-// Shared-memory scratch of the control step.
 // The control workgroup: 1024 threads, so the thousands of per-workgroup
-// partial rows of the fused residual are summed in a few rounds (the Gram
-// solve keeps to 128 registers: systems beyond depth 6 solve in LDS).
+// partial rows of the residual kernels are summed in a few rounds.
 constexpr int kCtlThreads = 1024;
+constexpr int kCtlN = kMaxDepth + 1;   // largest bordered system
 
 struct ControlScratch {
   IterState st;
-  double red[kCtlThreads / 64];
   double wsum[kCtlThreads / 64][kMaxDepth + 1];
   double sums[kMaxDepth + 1];
-  double A[kMaxDepth + 1][kMaxDepth + 2];
+  double A[kCtlN][kCtlN + 1];   // bordered MDIIS system, right-hand side in column n
+  double f[kCtlN];              // elimination factors of one column
   double c[kMaxDepth];
+  double rms;
+  double min_piv;
   int slot[kMaxDepth];
+  int m;                        // stored pairs
+  int mode;                     // what the rest of the step does (kCtl*)
+  int piv;
 };
 
+constexpr int kCtlDone = 0;      // the step ended (finished, verify, or max_iter)
+constexpr int kCtlSolve = 1;     // MDIIS with m > 1: bordered solve, then coefficients
+constexpr int kCtlDirect = 2;    // Anderson, or MDIIS with one pair: coefficients directly
+
+// Orders the shared-memory accesses of the lanes of one wavefront (the lanes
+// run in lockstep; the fences keep the compiler from moving accesses across).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One control step (steps 6-7, Eq 40-41; Eq 34-39 for modified Anderson) on
+// the state held in shared memory, by the 64 lanes of the first wavefront of
+// the control workgroup (only they call it): lane 0 does the bookkeeping,
+// the lanes order the stored slots and solve the bordered MDIIS system.  anchor: the evaluation just
+// finished was the exact FP64 one.  The stopping test of Eq 41 is decided on
+// exact residuals only: an FP32 residual (R_ref + dh - dg, an estimate) below
+// tol holds its iterate in slot dest and asks for the next FP64 evaluation
+// to re-evaluate it (kDoneVerify); that evaluation either finishes the solve
+// or continues it as an ordinary step whose residual is exact.
+//
+// MDIIS (Eq 40, with the history policy of the design notes): minimise
+// |sum c_i R_i|^2 subject to sum c_i = 1 over the stored pairs, oldest
+// first: the bordered system [[B, -1], [-1^T, 0]] [c; lambda] = [0; -1] with
+// B_ij = <R_i, R_j> / max_i B_ii, Gaussian elimination with partial
+// pivoting (first row of largest magnitude) in FP64.  A pivot below 1e-12
+// restarts from the stored pair of smallest RMS, and so does a new RMS above
+// 10x the smallest stored one (the new pair is then dropped).
+__device__ void control_step(ControlScratch& cs, const double* sums, int M, double inv_count,
+                             double tol, int max_iter, float eta_static, int eta_dynamic,
+                             int accel, double as1, double as2, int anchor) {
+  IterState& st = cs.st;
+  const int t = threadIdx.x;
+  const bool anderson = accel == RISM3D_ANDERSON;
+  if (t == 0) {
+    const int dest = st.dest;
+    const double rr = sums[M];
+    const double rms = sqrt(rr * inv_count);
+    cs.rms = rms;
+    cs.mode = kCtlDone;
+    st.hold = 0;
+    st.done = 0;
+    st.iter += 1;
+    st.last_rms = rms;
+    st.last_rr = rr;
+    if (!(rr == rr) || rr > 1.0e300) {
+      st.status = RISM3D_E_NONFINITE;
+      st.final_slot = dest;
+      st.done = kDoneFinished;
+    } else if (rms < tol) {
+      st.final_slot = dest;
+      if (anchor) {
+        st.converged = 1;
+        st.done = kDoneFinished;
+      } else {
+        st.stored[dest] = 0;   // its old pair was overwritten; the FP64 pass stores it anew
+        st.hold = 1;
+        st.done = kDoneVerify;
+      }
+    } else if (st.iter >= max_iter) {
+      st.status = RISM3D_E_NOCONV;
+      st.final_slot = dest;
+      st.done = kDoneFinished;
+    } else {
+      // The destination slot's old pair (the oldest, when the ring was full)
+      // has been overwritten by the new iterate: drop it.
+      st.stored[dest] = 0;
+      int best = -1;
+      double best_rms = 0.0;
+      for (int i = 0; i < M; ++i) {
+        if (st.stored[i] && (best < 0 || st.rms_slot[i] < best_rms)) {
+          best = i;
+          best_rms = st.rms_slot[i];
+        }
+      }
+      if (!anderson && best >= 0 && rms > 10.0 * best_rms) {
+        for (int i = 0; i < M; ++i) st.stored[i] = (i == best);
+        st.newest = best;
+        st.restarts += 1;
+      } else {
+        st.stored[dest] = 1;
+        st.newest = dest;
+        st.rms_slot[dest] = rms;
+        st.stamp[dest] = ++st.stamp_counter;
+        for (int i = 0; i < M; ++i) {
+          if (st.stored[i] && i != dest) {
+            st.gram[dest][i] = sums[i];
+            st.gram[i][dest] = sums[i];
+          }
+        }
+        st.gram[dest][dest] = anderson ? sums[dest] : rr;   // weighted for Anderson (Eq 38)
+      }
+      int m = 0;
+      for (int i = 0; i < M; ++i) m += st.stored[i] != 0;
+      cs.m = m;
+      cs.mode = (!anderson && m > 1) ? kCtlSolve : kCtlDirect;
+    }
+  }
+  wave_sync();
+  if (cs.mode == kCtlDone) return;
+  const int m = cs.m;
+  // stored slots, oldest first: a slot's rank is the number of older ones
+  if (t < M && st.stored[t]) {
+    int r = 0;
+    for (int j = 0; j < M; ++j) r += st.stored[j] && st.stamp[j] < st.stamp[t];
+    cs.slot[r] = t;
+  }
+  wave_sync();
+  bool solved = true;
+  if (cs.mode == kCtlSolve) {
+    const int n = m + 1;
+    {
+      double scale = 0.0;
+      for (int i = 0; i < m; ++i) scale = fmax(scale, st.gram[cs.slot[i]][cs.slot[i]]);
+      for (int e = t; e < n * (n + 1); e += 64) {
+        const int i = e / (n + 1), j = e - i * (n + 1);
+        double a;
+        if (j == n) a = i == m ? -1.0 : 0.0;               // right-hand side
+        else if (i < m && j < m) a = st.gram[cs.slot[i]][cs.slot[j]] / scale;
+        else if (i == m && j == m) a = 0.0;
+        else a = -1.0;                                    // the border
+        cs.A[i][j] = a;
+      }
+    }
+    if (t == 0) cs.min_piv = 1.0e300;
+    wave_sync();
+    for (int col = 0; col < n; ++col) {
+      if (t == 0) {   // partial pivoting: the first row of largest magnitude
+        int piv = col;
+        double best = fabs(cs.A[col][col]);
+        for (int r = col + 1; r < n; ++r)
+          if (fabs(cs.A[r][col]) > best) {
+            best = fabs(cs.A[r][col]);
+            piv = r;
+          }
+        cs.piv = piv;
+        cs.min_piv = fmin(cs.min_piv, best);
+      }
+      wave_sync();
+      const int piv = cs.piv;
+      if (piv != col && t <= n) {
+        const double tmp = cs.A[col][t];
+        cs.A[col][t] = cs.A[piv][t];
+        cs.A[piv][t] = tmp;
+      }
+      wave_sync();
+      const double pv = cs.A[col][col];
+      if (!(fabs(pv) >= 1.0e-300)) {
+        solved = false;
+        break;   // uniform: every thread reads the same pivot
+      }
+      if (t > col && t < n) cs.f[t] = cs.A[t][col] / pv;
+      wave_sync();
+      const int w = n + 1 - col;
+      for (int e = t; e < (n - 1 - col) * w; e += 64) {
+        const int r = col + 1 + e / w, j = col + e % w;
+        cs.A[r][j] -= cs.f[r] * cs.A[col][j];
+      }
+      wave_sync();
+    }
+    if (solved && cs.min_piv < 1.0e-12) solved = false;
+    if (solved) {
+      // back substitution, column by column: x_r = b_r / A_rr, then every
+      // row above drops its A_ir x_r
+      for (int r = n - 1; r >= 0; --r) {
+        if (t == 0) cs.A[r][n] = cs.A[r][n] / cs.A[r][r];
+        wave_sync();
+        if (t < r) cs.A[t][n] -= cs.A[t][r] * cs.A[r][n];
+        wave_sync();
+      }
+      if (t < m) cs.c[t] = cs.A[t][n];
+    }
+    wave_sync();
+  }
+  if (t == 0) {
+    int* slot = cs.slot;
+    double* c = cs.c;
+    int mm = m;
+    if (anderson) {
+      // Picard for the first two steps (and for a singular theta system), then
+      // X = sum c_k (X_k + b R_k) with c = (theta_2 + s_2, theta_1 + s_1,
+      // 1 - sum(theta + s)) on the three pairs oldest first (Eq 34-39)
+      double theta[2];
+      for (int i = 0; i < mm; ++i) c[i] = 0.0;
+      c[mm - 1] = 1.0;
+      if (mm == 3 && anderson_theta(st, slot[2], slot[1], slot[0], theta)) {
+        const double k1 = theta[0] + as1, k2 = theta[1] + as2;
+        c[2] = 1.0 - k1 - k2;
+        c[1] = k1;
+        c[0] = k2;
+      }
+    } else if (mm == 1) {
+      c[0] = 1.0;
+    } else if (!solved) {
+      // ill-conditioned subspace: restart from the best stored pair
+      int b = slot[0];
+      for (int i = 1; i < mm; ++i)
+        if (st.rms_slot[slot[i]] < st.rms_slot[b]) b = slot[i];
+      for (int i = 0; i < M; ++i) st.stored[i] = (i == b);
+      st.newest = b;
+      slot[0] = b;
+      mm = 1;
+      c[0] = 1.0;
+      st.restarts += 1;
+    }
+    for (int i = 0; i < M; ++i) st.coef[i] = 0.0f;
+    for (int i = 0; i < mm; ++i) st.coef[slot[i]] = (float)c[i];
+    float eta = eta_static;
+    if (eta_dynamic && !anderson) eta = (float)fmin(fmax(-0.2 * log(cs.rms), 0.1), 1.0);
+    st.eta = eta;
+    // Next destination: a free slot while the ring is not full, else the oldest.
+    int next = -1;
+    if (mm < M) {
+      for (int i = 0; i < M; ++i)
+        if (!st.stored[i]) {
+          next = i;
+          break;
+        }
+    } else {
+      next = slot[0];
+    }
+    st.dest = next;
+  }
+}
+
+// Shared-memory scratch of the control step.
 // Reduce the partials of `nblocks` blocks in fixed order and run one control
 // step on the state (anchor: the evaluation was the FP64 one); all threads of
 // the calling workgroup participate.
-// MM bounds the history depth (M <= MM): each thread then holds MM + 1 sums
-// and stages U partial rows at a time, so their loads are in flight together
-// (the rows were just written by other CUs: every round trip costs ~2 us).
-// The per-thread order of the additions is the same for every U.
+// MM bounds the history depth (M <= MM): each thread holds MM + 1 sums.
 template <int MM = kMaxDepth>
 __device__ __forceinline__ void control_block(IterState* __restrict__ st_g,
                                      const double* __restrict__ partials, int nblocks, int M,
@@ -877,34 +833,34 @@ __device__ __forceinline__ void control_block(IterState* __restrict__ st_g,
     for (int i = threadIdx.x; i < (int)(sizeof(IterState) / sizeof(int)); i += blockDim.x)
       dst[i] = src[i];
   }
-  // Each thread sums its strided blocks for all M+1 quantities at once (loads
-  // in flight together), then one LDS pass combines the per-wave sums in
-  // fixed order.
-  constexpr int U = MM <= 5 ? 6 : 1;
+  // Each thread sums its strided workgroups b = t, t + T, ... for every
+  // quantity (quantity q is the contiguous run partials[q * nblocks + b]).
+  // The loads of U workgroups and all quantities are issued before any
+  // addition and without branches (quantities past M re-read quantity M,
+  // workgroups past the end re-read the last one; both add zero), so the
+  // round trip to rows just written by other CUs is paid once per U
+  // workgroups.  Then one LDS pass combines the per-wave sums in fixed order.
+  constexpr int U = MM <= 5 ? 6 : 2;
   double v[MM + 1];
 #pragma unroll
   for (int q = 0; q <= MM; ++q) v[q] = 0.0;
-  int b = threadIdx.x;
-  if constexpr (U > 1) {
-    for (; b + (U - 1) * (int)blockDim.x < nblocks; b += U * (int)blockDim.x) {
-      double r[U][MM + 1];
+  const int T = (int)blockDim.x;
+  for (int b = threadIdx.x; b < nblocks; b += U * T) {
+    double r[U][MM + 1];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const double* pb = partials + (size_t)(b + u * (int)blockDim.x) * (M + 1);
+    for (int u = 0; u < U; ++u) {
+      const int bb = b + u * T;
+      const size_t bc = (size_t)(bb < nblocks ? bb : nblocks - 1);
 #pragma unroll
-        for (int q = 0; q <= MM; ++q) r[u][q] = q <= M ? pb[q] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-#pragma unroll
-        for (int q = 0; q <= MM; ++q) v[q] += r[u][q];
+      for (int q = 0; q <= MM; ++q)
+        r[u][q] = partials[(size_t)(q <= M ? q : M) * (size_t)nblocks + bc];
     }
-  }
-  for (; b < nblocks; b += blockDim.x) {
-    const double* pb = partials + (size_t)b * (M + 1);
 #pragma unroll
-    for (int q = 0; q <= MM; ++q)
-      if (q <= M) v[q] += pb[q];
+    for (int u = 0; u < U; ++u) {
+      const bool in = b + u * T < nblocks;
+#pragma unroll
+      for (int q = 0; q <= MM; ++q) v[q] += (in && q <= M) ? r[u][q] : 0.0;
+    }
   }
 #pragma unroll
   for (int q = 0; q <= MM; ++q) {
@@ -920,103 +876,15 @@ __device__ __forceinline__ void control_block(IterState* __restrict__ st_g,
     cs.sums[threadIdx.x] = t;
   }
   __syncthreads();
+  if (threadIdx.x < 64)
+    control_step(cs, cs.sums, M, inv_count, tol, max_iter, eta_static, eta_dynamic, accel, as1,
+                 as2, anchor);
+  __syncthreads();
   if (threadIdx.x == 0) {
-    int slot[kMaxDepth];
-    double c[kMaxDepth];
-    control_step(cs.st, cs.sums, cs.A, M, inv_count, tol, max_iter, eta_static, eta_dynamic,
-                 accel, as1, as2, anchor, slot, c);
     // residual history: the RMS of evaluation i (1-based) and whether it was exact
     const int it = cs.st.iter;
     if (it >= 1 && it <= kHistLen) hist[it - 1] = make_double2(cs.st.last_rms, anchor ? 1.0 : 0.0);
   }
-  __syncthreads();
-  {
-    const int* src = reinterpret_cast<const int*>(&cs.st);
-    int* dst = reinterpret_cast<int*>(st_g);
-    for (int i = threadIdx.x; i < (int)(sizeof(IterState) / sizeof(int)); i += blockDim.x)
-      dst[i] = src[i];
-  }
-}
-
-// Options of the control step, passed by value to the fused residual kernel.
-// on = 0 leaves the reduction and the control step out (the autotuner times
-// the residual kernel alone).
-struct CtlArgs {
-  double inv_count, tol, as1, as2;
-  int max_iter, eta_dynamic, accel, on;
-  float eta_static;
-};
-
-// Workgroups per chunk of the two-level reduction below.
-constexpr int kChunkBlocks = 64;
-
-__device__ __forceinline__ double load_agent(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// The end of an iteration inside the kernel that wrote the partial rows (one
-// row of M + 1 sums per workgroup, written by thread 0 of each): a two-level
-// reduction with the control step in the last workgroup to finish.  The last
-// workgroup to arrive within each chunk of kChunkBlocks consecutive
-// workgroups sums the chunk's rows in workgroup order into a chunk row; the
-// last chunk to finish sums the chunk rows in chunk order and runs the
-// control step on the state.  Every addition has a fixed order, so the result
-// does not depend on which workgroup finishes last.  tickets holds one
-// counter per chunk plus one for the chunks (zero between launches: each
-// last arriver resets the counter it consumed).  Every workgroup of the
-// launch calls this after its row is written; the state is rewritten only
-// after every workgroup has passed its start (where it reads the state).
-__device__ void finish_iteration(IterState* __restrict__ st_g, const double* partials,
-                                 double* chunk_rows, int* tickets, int M, int anchor,
-                                 const CtlArgs& a, double2* __restrict__ hist,
-                                 ControlScratch& cs, int* flag) {
-  const int nblocks = (int)gridDim.x;
-  const int nchunks = (nblocks + kChunkBlocks - 1) / kChunkBlocks;
-  const int c = (int)blockIdx.x / kChunkBlocks;
-  const int first = c * kChunkBlocks;
-  const int cnt = nblocks - first < kChunkBlocks ? nblocks - first : kChunkBlocks;
-  if (threadIdx.x == 0) {
-    __threadfence();   // this workgroup's row before its ticket
-    *flag = atomicAdd(&tickets[c], 1) == cnt - 1;
-  }
-  __syncthreads();
-  if (!*flag) return;
-  __threadfence();
-  if ((int)threadIdx.x <= M) {
-    double sum = 0.0;
-    for (int b = first; b < first + cnt; ++b)
-      sum += load_agent(&partials[(size_t)b * (M + 1) + threadIdx.x]);
-    chunk_rows[(size_t)c * (M + 1) + threadIdx.x] = sum;
-    __threadfence();
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    tickets[c] = 0;
-    *flag = atomicAdd(&tickets[nchunks], 1) == nchunks - 1;
-  }
-  __syncthreads();
-  if (!*flag) return;
-  __threadfence();
-  {
-    const int* src = reinterpret_cast<const int*>(st_g);
-    int* dst = reinterpret_cast<int*>(&cs.st);
-    for (int i = threadIdx.x; i < (int)(sizeof(IterState) / sizeof(int)); i += blockDim.x)
-      dst[i] = src[i];
-  }
-  if ((int)threadIdx.x <= M) {
-    double sum = 0.0;
-    for (int k = 0; k < nchunks; ++k) sum += load_agent(&chunk_rows[(size_t)k * (M + 1) + threadIdx.x]);
-    cs.sums[threadIdx.x] = sum;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    tickets[nchunks] = 0;
-    control_step<false>(cs.st, cs.sums, cs.A, M, a.inv_count, a.tol, a.max_iter, a.eta_static,
-                        a.eta_dynamic, a.accel, a.as1, a.as2, anchor, cs.slot, cs.c);
-    const int it = cs.st.iter;
-    if (it >= 1 && it <= kHistLen) hist[it - 1] = make_double2(cs.st.last_rms, anchor ? 1.0 : 0.0);
-  }
-  __syncthreads();
   {
     const int* src = reinterpret_cast<const int*>(&cs.st);
     int* dst = reinterpret_cast<int*>(st_g);

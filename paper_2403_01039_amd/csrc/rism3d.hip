@@ -217,8 +217,7 @@ struct Layout {
   size_t off_state, off_w, off_phi, off_F, off_tau, off_res, off_tref, off_tlo, off_rref, off_dg,
       off_spec,
       off_part, off_atoms, off_lj, off_ph, off_chi32, off_chi64, off_q64, off_tw32[3], off_tw64[3],
-      off_out, off_hist, off_chunk, off_tick, total;
-  int n_tickets;   // chunk counters of the two-level residual reduction, plus one
+      off_out, off_hist, total;
 };
 
 constexpr int kDefaultCheckEvery = 8;
@@ -358,10 +357,6 @@ rism3d_status make_layout(const rism3d_problem* pr, const rism3d_opts* op, Layou
     if (b > part_blocks) part_blocks = b;
   }
   L->off_part = take(part_blocks * part_q * sizeof(double));
-  const size_t chunks = (part_blocks + kChunkBlocks - 1) / kChunkBlocks;
-  L->off_chunk = take(chunks * part_q * sizeof(double));
-  L->n_tickets = (int)chunks + 1;
-  L->off_tick = take((size_t)L->n_tickets * sizeof(int));
   L->off_chi32 = take((size_t)L->m_tab * chi_row<float>((int)nv) * sizeof(float));
   L->off_chi64 = take((size_t)L->m_tab * chi_row<double>((int)nv) * sizeof(double));
   L->off_q64 = take((size_t)L->m_tab * nv * sizeof(double));
@@ -740,27 +735,23 @@ void launch_fused_l(const Layout& L, void* ws, const rism3d_opts* op, bool first
         if (L.M <= 3) residual = &k_fftx_residual<false, N, LINES, 3>;
         else if (L.M <= 5) residual = &k_fftx_residual<false, N, LINES, 5>;
       }
-      // the reduction of the Gram row and RMS and the control step run in
-      // the residual kernel's last workgroup (no separate control launch)
-      CtlArgs ctl;
-      ctl.inv_count = 1.0 / ((double)L.N * (double)L.nv);
-      ctl.tol = op->tol;
-      ctl.as1 = op->anderson_s1;
-      ctl.as2 = op->anderson_s2;
-      ctl.max_iter = op->max_iter;
-      ctl.eta_dynamic = op->eta_dynamic;
-      ctl.accel = (int)op->accelerator;
-      ctl.on = control ? 1 : 0;
-      ctl.eta_static = (float)op->mdiis_eta;
       hipLaunchKernelGGL(residual, grid, block, 0, s, st,
                          at<void>(ws, L.off_spec), at<float>(ws, L.off_w),
                          at<float>(ws, L.off_tau), at<float>(ws, L.off_res),
                          at<float>(ws, L.off_tref), at<float>(ws, L.off_tlo),
                          at<float>(ws, L.off_rref), at<float>(ws, L.off_dg), L.ny, L.nz, L.nv,
                          L.npair, L.M, kind, order, tw, at<double>(ws, L.off_part), L.gw,
-                         at<double>(ws, L.off_chunk), at<int>(ws, L.off_tick), ctl,
-                         at<double2>(ws, L.off_hist), bt.stride);
+                         bt.stride);
     }
+    if (!control) return;
+    TIMED(F_CONTROL, s);
+    const double inv_count = 1.0 / ((double)L.N * (double)L.nv);
+    hipLaunchKernelGGL(L.M <= 5 ? &k_control<5> : &k_control<kMaxDepth>, dim3(1, bt.nb),
+                       dim3(kCtlThreads), 0, s, st,
+                       at<double>(ws, L.off_part), (int)grid.x, L.M, inv_count, op->tol,
+                       op->max_iter, (float)op->mdiis_eta, op->eta_dynamic,
+                       (int)op->accelerator, op->anderson_s1, op->anderson_s2, ANCHOR ? 1 : 0,
+                       at<double2>(ws, L.off_hist), bt.stride);
   }
 }
 
@@ -1064,8 +1055,8 @@ rism3d_status prepare(const rism3d_problem* pr, const Layout& L, void* ws, hipSt
   for (int a = 0; a < 3; ++a)
     hipLaunchKernelGGL(k_twiddles, dim3(blocks_for(2 * dims[a], 256)), dim3(256), 0, s, dims[a],
                        at<float2>(ws, L.off_tw32[a]), at<double2>(ws, L.off_tw64[a]));
-  hipLaunchKernelGGL(k_mark_prepared, dim3(1), dim3(256), 0, s, at<IterState>(ws, L.off_state),
-                     layout_key(L), at<int>(ws, L.off_tick), L.n_tickets);
+  hipLaunchKernelGGL(k_mark_prepared, dim3(1), dim3(1), 0, s, at<IterState>(ws, L.off_state),
+                     layout_key(L));
   LAUNCH_CHECK();
   return RISM3D_OK;
 }
