@@ -186,11 +186,13 @@ __global__ __launch_bounds__(kConvThreads) void k_conv3(ConvArgs p) {
 // over the voxel chunks of this workgroup; the tiles go through LDS
 // transposed ([channel][voxel]) so each lane reads 8 consecutive voxels of
 // one channel as one 16-byte operand.  Waves share the 16x16 (o, i) tiles
-// round-robin and add their sums to the FP32 gradient with atomics.
+// round-robin; each workgroup stores its sums in its own slab of the FP32
+// partial buffer (every element of the slab, zeros where it saw no voxel),
+// which k_sum_slabs adds up in workgroup order (deterministic).
 struct WgradArgs {
   ConvIn in;
   const uint16_t* dy;   // BF16 [N][cout_pad]
-  float* dw;            // FP32 [cout][27][cin_real]
+  float* dw;            // FP32 partial slabs [gridDim.x][cout][27][cin_real]
   int cin_real;         // real input channels (the packed input may carry zero padding)
   int cout, cout_pad;
   int nz, ny, nx;
@@ -270,27 +272,48 @@ __global__ __launch_bounds__(kConvThreads) void k_conv3_wgrad(WgradArgs p) {
     if (t < ntiles) {
       const int to = t / cit, ti = t - to * cit;
       const int i = ti * 16 + j;
+      float* slab = p.dw + (size_t)blockIdx.x * p.cout * 27 * p.cin_real;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int o = to * 16 + 4 * g + e;
         if (o < p.cout && i < p.cin_real)
-          atomicAdd(p.dw + ((size_t)o * 27 + tap) * p.cin_real + i, acc[k][e]);
+          slab[((size_t)o * 27 + tap) * p.cin_real + i] = acc[k][e];
       }
     }
   }
 }
 
-// db[o] += sum_v dy[v][o] (BF16 dy, FP32 sums, one atomic per channel and workgroup).
+// Partial bias gradients: slab b (this workgroup) of part receives
+// sum_v dy[v][o] over the workgroup's voxels (BF16 dy, FP32 sums), the lanes
+// of one channel added in lane order; k_sum_slabs adds the slabs up.
 __global__ __launch_bounds__(kConvThreads) void k_bias_grad(const uint16_t* __restrict__ dy,
                                                             int N, int cout, int cout_pad,
-                                                            float* __restrict__ db) {
+                                                            float* __restrict__ part) {
+  __shared__ float red[kConvThreads];
   const int c = threadIdx.x % cout_pad;
   const int lanes_per_voxel = kConvThreads / cout_pad;   // cout_pad divides 256
   const int sub = threadIdx.x / cout_pad;
   float s = 0.0f;
   for (int v = (int)blockIdx.x * lanes_per_voxel + sub; v < N; v += (int)gridDim.x * lanes_per_voxel)
     s += bf2f(dy[(size_t)v * cout_pad + c]);
-  if (c < cout) atomicAdd(db + c, s);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if ((int)threadIdx.x < cout) {
+    float t = 0.0f;
+    for (int k = 0; k < lanes_per_voxel; ++k) t += red[k * cout_pad + threadIdx.x];
+    part[(size_t)blockIdx.x * cout + threadIdx.x] = t;
+  }
+}
+
+// dst[e] += sum_b part[b][e] over the n_slab slabs of n elements, in slab
+// order (the fixed-order end of the weight and bias gradients).
+__global__ void k_sum_slabs(const float* __restrict__ part, int n_slab, size_t n,
+                            float* __restrict__ dst) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  float t = 0.0f;
+  for (int b = 0; b < n_slab; ++b) t += part[(size_t)b * n + e];
+  dst[e] += t;
 }
 
 // Average over 2x2x2 blocks (BF16 in and out, FP32 sums); one thread per

@@ -32,12 +32,29 @@ struct NetPlan {
   size_t x0 = 0, a[kNetMaxLevels] = {}, e[kNetMaxLevels] = {}, p[kNetMaxLevels] = {},
          da[kNetMaxLevels] = {}, db[kNetMaxLevels] = {};
   size_t out = 0, ge[kNetMaxLevels] = {}, gd[kNetMaxLevels] = {}, gtmp = 0, gdx = 0, dyp = 0,
-         partials = 0, loss = 0;
+         partials = 0, loss = 0, slabs = 0;
   size_t total_infer = 0, total_train = 0;
   int c(int l) const { return cfg.base << l; }
 };
 
 constexpr int kMsePartials = 1024;
+
+// Workgroups per tap of the weight gradient over N voxels (chunks of
+// kWgradChunk voxels, about 96 workgroups x 27 taps at full size), and the
+// voxel chunks each one takes.
+size_t wgrad_per(size_t N) {
+  const size_t chunks_total = (N + net::kWgradChunk - 1) / net::kWgradChunk;
+  const size_t wg_target = 96;
+  return std::max<size_t>(1, (chunks_total + wg_target - 1) / wg_target);
+}
+size_t wgrad_blocks(size_t N) {
+  const size_t chunks_total = (N + net::kWgradChunk - 1) / net::kWgradChunk;
+  return (chunks_total + wgrad_per(N) - 1) / wgrad_per(N);
+}
+size_t bias_blocks(size_t N, int cout_pad) {
+  const size_t per_block = (size_t)(net::kConvThreads / cout_pad);
+  return std::min<size_t>(1024, (N + per_block - 1) / per_block);
+}
 
 rism3d_status net_plan(const rism3d_unet_config* cfg, int nx, int ny, int nz, NetPlan* P) {
   if (!cfg) return fail(RISM3D_E_ARG, "null network configuration");
@@ -130,6 +147,13 @@ rism3d_status net_plan(const rism3d_unet_config* cfg, int nx, int ny, int nz, Ne
   P->dyp = take(max_cout_pad * 2);
   P->partials = take(kMsePartials * sizeof(double));
   P->loss = take(sizeof(double));
+  size_t slab_floats = 0;   // partial slabs of the largest weight (or bias) gradient
+  for (const NetLayer& ly : P->layers) {
+    const size_t w = wgrad_blocks(P->nvox[ly.level]) * (size_t)ly.cout * 27 * ly.cin;
+    const size_t b = bias_blocks(P->nvox[ly.level], ly.cout_pad) * (size_t)ly.cout;
+    slab_floats = std::max(slab_floats, std::max(w, b));
+  }
+  P->slabs = take(slab_floats * sizeof(float));
   P->total_train = off;
   return RISM3D_OK;
 }
@@ -268,13 +292,13 @@ void net_conv_dx(const NetPlan& P, const NetLayer& ly, void* ws, const uint16_t*
 void net_conv_dw(const NetPlan& P, const NetLayer& ly, const net::ConvIn& in, void* ws,
                  const uint16_t* dyp, float* grad, hipStream_t s) {
   const size_t N = P.nvox[ly.level];
-  const size_t chunks_total = (N + net::kWgradChunk - 1) / net::kWgradChunk;
-  const size_t wg_target = 96;   // x 27 taps ~ 2600 workgroups at full size
-  const size_t per = std::max<size_t>(1, (chunks_total + wg_target - 1) / wg_target);
+  const size_t per = wgrad_per(N);
+  const size_t nbx = wgrad_blocks(N);
+  float* slabs = wsp<float>(ws, P.slabs);
   net::WgradArgs w;
   w.in = in;
   w.dy = dyp;
-  w.dw = grad + ly.w_off;
+  w.dw = slabs;
   w.cin_real = ly.cin;
   w.cout = ly.cout;
   w.cout_pad = ly.cout_pad;
@@ -284,11 +308,16 @@ void net_conv_dw(const NetPlan& P, const NetLayer& ly, const net::ConvIn& in, vo
   w.chunks = (int)per;
   const int cit = (ly.cin_pad + 15) / 16;
   const size_t lds = ((size_t)ly.cout_pad + (size_t)cit * 16) * net::kWgradPitch * 2;
-  hipLaunchKernelGGL(net::k_conv3_wgrad, dim3((unsigned)((chunks_total + per - 1) / per), 27),
-                     dim3(net::kConvThreads), lds, s, w);
-  const unsigned nb = std::min<unsigned>(1024, net_blocks(N, net::kConvThreads / ly.cout_pad));
+  hipLaunchKernelGGL(net::k_conv3_wgrad, dim3((unsigned)nbx, 27), dim3(net::kConvThreads), lds,
+                     s, w);
+  const size_t nw = (size_t)ly.cout * 27 * ly.cin;
+  hipLaunchKernelGGL(net::k_sum_slabs, dim3(net_blocks(nw, 256)), dim3(256), 0, s, slabs,
+                     (int)nbx, nw, grad + ly.w_off);
+  const unsigned nb = (unsigned)bias_blocks(N, ly.cout_pad);
   hipLaunchKernelGGL(net::k_bias_grad, dim3(nb), dim3(net::kConvThreads), 0, s, dyp, (int)N,
-                     ly.cout, ly.cout_pad, grad + ly.b_off);
+                     ly.cout, ly.cout_pad, slabs);
+  hipLaunchKernelGGL(net::k_sum_slabs, dim3(net_blocks(ly.cout, 256)), dim3(256), 0, s, slabs,
+                     (int)nb, (size_t)ly.cout, grad + ly.b_off);
 }
 
 void net_leaky_bwd(const NetPlan& P, size_t y_off, const float* g, int level, int C, void* ws,

@@ -171,6 +171,25 @@ def test_gradient_matches_oracle_with_bf16_rounding(R, monkeypatch):
         off += nw + co
 
 
+def test_gradient_is_bitwise_reproducible(R):
+    """The weight and bias gradients are summed over workgroups in a fixed
+    order (per-workgroup slabs, then a slab sum), so two evaluations agree
+    bit for bit."""
+    shape = (32, 16, 24)
+    cfg, ocfg, theta, x = _setup(R, 4, 16, shape, 41)
+    rng = np.random.default_rng(42)
+    target = rng.standard_normal(shape + (3,))
+    params = torch.tensor(theta, device="cuda")
+    ws = R.alloc_workspace(R.unet_workspace_bytes(cfg, shape, True))
+    grads = []
+    for _ in range(2):
+        g = torch.empty_like(params)
+        R.unet_gradient(cfg, params, _site_major(x), _site_major(target), g, ws)
+        grads.append(g)
+    torch.cuda.synchronize()
+    assert torch.equal(grads[0], grads[1])
+
+
 def test_adam_matches_oracle(R):
     from oracle import unet as U
     rng = np.random.default_rng(31)
