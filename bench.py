@@ -449,6 +449,67 @@ def gradient_leg(R, prob, solver, stream, reps: int):
                         "(128^3, 5 sites), FP64 pair terms"}
 
 
+def network_leg(R, inputs, steps: int):
+    """The warm-start network of the learned part (4 levels, 16-128 channels,
+    3^3 convolutions, BF16 on the matrix cores with FP32 accumulation) at the
+    128^3 grid: one training step (forward, loss, backward, Adam) and one
+    inference, on seeded He-normal parameters and seeded synthetic input and
+    target.  TFLOP/s counts the convolutions' multiply-adds (2 flops each):
+    forward 2 N 27 C_in C_out per layer at its level's N voxels, backward
+    twice that (data and weight gradients); the peak is the dense BF16 MFMA
+    rate."""
+    import numpy as np
+    import torch
+    shape = (128, 128, 128)
+    cfg = R.unet_config(3, 3, levels=4, base=16)
+    layers = R.unet_layers(cfg)
+    theta = torch.tensor(inputs.unet_init_params(layers, 7), dtype=torch.float32, device="cuda")
+    rng = np.random.default_rng(8)
+    x = torch.tensor(rng.standard_normal((3,) + shape), dtype=torch.float32, device="cuda")
+    y = torch.tensor(rng.standard_normal((3,) + shape), dtype=torch.float32, device="cuda")
+    grad = torch.empty_like(theta)
+    m = torch.zeros_like(theta)
+    v = torch.zeros_like(theta)
+    out = torch.empty_like(x)
+    ws_t = R.alloc_workspace(R.unet_workspace_bytes(cfg, shape, True))
+    scratch = R.unet_adam_scratch()
+    n0 = shape[0] * shape[1] * shape[2]
+    level = {}
+    for name, ci, co in layers:
+        lv = int(name[3]) if name.startswith(("enc", "dec")) else 0
+        level[name] = n0 >> (3 * lv)
+    fwd = sum(2.0 * level[n] * 27 * ci * co for n, ci, co in layers)
+
+    def train_step(k):
+        R.unet_gradient(cfg, theta, x, y, grad, ws_t)
+        R.unet_adam(theta, m, v, grad, k + 1, 1e-4, clip_norm=1.0, scratch=scratch)
+
+    train_step(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        train_step(k + 1)
+    torch.cuda.synchronize()
+    t_train = (time.perf_counter() - t0) / steps
+    R.unet_forward(cfg, theta, x, out, ws_t)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        R.unet_forward(cfg, theta, x, out, ws_t)
+    torch.cuda.synchronize()
+    t_fwd = (time.perf_counter() - t0) / steps
+    peak = 2500.0
+    return {"train_step_ms": t_train * 1e3, "forward_ms": t_fwd * 1e3,
+            "forward_tflop": fwd / 1e12, "train_step_tflop": 3.0 * fwd / 1e12,
+            "train_tflops": 3.0 * fwd / t_train / 1e12, "forward_tflops": fwd / t_fwd / 1e12,
+            "bf16_mfma_peak_tflops": peak,
+            "train_frac": 3.0 * fwd / t_train / 1e12 / peak,
+            "forward_frac": fwd / t_fwd / 1e12 / peak,
+            "parameters": int(theta.numel()),
+            "workload": "warm-start network, 4 levels, 16-128 channels, 3 -> 3 channels, 128^3 "
+                        "voxels, seeded synthetic input and target, one solute per step"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -463,6 +524,8 @@ def main():
                     help="solves of the headline workload with modified Anderson (0: skip)")
     ap.add_argument("--warm-seeds", type=int, default=200,
                     help="held-out seeds of the plain vs warm-start comparison (0: skip)")
+    ap.add_argument("--network-steps", type=int, default=5,
+                    help="timed training steps and inferences of the warm-start network (0: skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (the reference "
                          "dispatch for scaling HBM counters)")
@@ -624,6 +687,8 @@ def main():
         out["anderson"] = anderson_comparison(R, prob, dp, stream, args.anderson_steps)
     if args.warm_seeds > 0:
         out["warm_start"] = warm_start_comparison(R, inputs, args.warm_seeds)
+    if args.network_steps > 0:
+        out["network"] = network_leg(R, inputs, args.network_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, chi, dk, int(round(it_mean)))
     print(json.dumps(out), flush=True)
