@@ -54,23 +54,24 @@ def kernel_bytes(nv: int, N: int, M: int, m_avg: float, fam: str) -> float:
         return nv * N * 4 * (2 * m_avg + 3) + 16 * P * N
     if fam == "fftx_residual_f32":    # spectra read once, then the residual + Gram row
         return 8 * P * N + nv * N * 4 * (2 + max(m_avg - 1, 0) + 1)
-    if fam == "fftx_residual_f64":    # as below, plus the re-base of the other stored deltas
-        return 16 * P * N + nv * N * 4 * (7 + 3 * max(m_avg - 1, 0))
+    if fam == "fftx_residual_f64":    # as residual_gram_f64 below, spectra read once
+        return 16 * P * N + nv * N * 4 * (8 + 3 * max(m_avg - 1, 0))
     if fam == "residual_gram_f32":    # read spectra, R_ref, dg, (m-1) R_i; write R
         return 8 * P * N + nv * N * 4 * (2 + max(m_avg - 1, 0) + 1)
     if fam == "residual_gram_f64":    # read FP64 spectra, delta, tau_ref, w, (m-1) R_i; write R,
-        # delta, tau_ref, R_ref; read and write the other (m-1) stored deltas
-        return 16 * P * N + nv * N * 4 * (7 + 3 * max(m_avg - 1, 0))
+        # delta, tau_ref, R_ref, d_ref; read and write the other (m-1) stored deltas
+        return 16 * P * N + nv * N * 4 * (8 + 3 * max(m_avg - 1, 0))
     return 0.0
 
 
 def increment_overhead_bytes(nv: int, N: int, fam: str) -> float:
     """Bytes a launch moves beyond the method's because the FP32 iterations
-    transform increments over an FP64 anchor: the update reads the reference
-    tau_ref and writes the closure increment dg (read back by the residual in
-    place of tau and w, so the residual's count is unchanged)."""
+    transform increments over an FP64 anchor: the update writes the closure
+    increment dg (read back by the residual in place of tau and w, so the
+    residual's count is unchanged; the update reads the anchor's closure
+    argument d_ref in place of w)."""
     if fam in ("update_fftx_f32", "update_closure_f32"):
-        return 8.0 * nv * N
+        return 4.0 * nv * N
     return 0.0
 
 

@@ -23,8 +23,9 @@ __global__ __launch_bounds__(kFftThreads) void k_update_fftx(
     const IterState* __restrict__ st, float* __restrict__ tau_hist,
     const float* __restrict__ res_hist, const float* __restrict__ w,
     const float* __restrict__ tau_ref, const float* __restrict__ tau_lo,
-    float* __restrict__ dg_out, void* __restrict__ spec_v, int ny, int nz, int nv, int npair,
-    int M, int kind, int order, const PrecC<ANCHOR>* __restrict__ tw2_g, size_t bstride) {
+    const float* __restrict__ dref, float* __restrict__ dg_out, void* __restrict__ spec_v,
+    int ny, int nz, int nv, int npair, int M, int kind, int order,
+    const PrecC<ANCHOR>* __restrict__ tw2_g, size_t bstride) {
   using C = PrecC<ANCHOR>;
   using S = typename ScalarOf<C>::type;
   constexpr int Q = N / 4;
@@ -35,6 +36,7 @@ __global__ __launch_bounds__(kFftThreads) void k_update_fftx(
   w = member_ptr(w, bstride);
   tau_ref = member_ptr(tau_ref, bstride);
   tau_lo = member_ptr(tau_lo, bstride);
+  dref = member_ptr(dref, bstride);
   dg_out = member_ptr(dg_out, bstride);
   spec_v = member_ptr(spec_v, bstride);
   tw2_g = member_ptr(tw2_g, bstride);
@@ -57,8 +59,8 @@ __global__ __launch_bounds__(kFftThreads) void k_update_fftx(
     const size_t n = (row - (size_t)p * plane) * N + i0;
     double o64[2][4];
     float o32[2][4];
-    update_points<ANCHOR, 4, MM>(u, tau_hist, res_hist, w, tau_ref, tau_lo, dg_out, N3, nv, p, n,
-                                 kind, order, o64, o32);
+    update_points<ANCHOR, 4, MM>(u, tau_hist, res_hist, w, tau_ref, tau_lo, dref, dg_out, N3, nv,
+                                 p, n, kind, order, o64, o32);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const C val = ANCHOR ? make_c((S)o64[0][v], (S)o64[1][v]) : make_c((S)o32[0][v], (S)o32[1][v]);
@@ -81,7 +83,8 @@ __global__ __launch_bounds__(kFftThreads) void k_fftx_residual(
     const IterState* __restrict__ st, const void* __restrict__ spec_v,
     const float* __restrict__ w, float* __restrict__ tau_hist, float* __restrict__ res_hist,
     float* __restrict__ tau_ref, float* __restrict__ tau_lo, float* __restrict__ r_ref,
-    const float* __restrict__ dg, int ny, int nz, int nv, int npair, int M, int kind, int order,
+    float* __restrict__ dref, const float* __restrict__ dg, int ny, int nz, int nv, int npair,
+    int M, int kind, int order,
     const PrecC<ANCHOR>* __restrict__ tw2_g, double* __restrict__ partials, GramW gw,
     size_t bstride) {
   using C = PrecC<ANCHOR>;
@@ -96,6 +99,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fftx_residual(
   tau_ref = member_ptr(tau_ref, bstride);
   tau_lo = member_ptr(tau_lo, bstride);
   r_ref = member_ptr(r_ref, bstride);
+  dref = member_ptr(dref, bstride);
   dg = member_ptr(dg, bstride);
   tw2_g = member_ptr(tw2_g, bstride);
   partials = member_ptr(partials, bstride);
@@ -157,7 +161,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fftx_residual(
       h64[1][v] = (double)h.y;
     }
     residual_points<ANCHOR, 4, MM>(hre, him, h64, w, tau_hist, res_hist, tau_ref, tau_lo, r_ref,
-                                   dg, N3, nv, p, n, dest, mask, kind, order, gw, acc);
+                                   dref, dg, N3, nv, p, n, dest, mask, kind, order, gw, acc);
   }
   write_partials<MM>(acc, M, partials, red);
 }

@@ -144,12 +144,16 @@ __device__ inline UpdateCtl load_update_ctl(const IterState* __restrict__ st, in
 // The update + closure of V consecutive points n.. of pair p: stores the new tau
 // (and dg in the FP32 path) and returns the two sites' FFT inputs.
 // ANCHOR: c_sr = g - 1 - tau (FP64).  Otherwise dc = dg - delta.
+// The FP32 path takes the closure argument of the reference, d_ref = -w +
+// tau_ref + tau_lo, from dref (written by the last anchor) instead of w and
+// tau_ref.
 template <bool ANCHOR, int V, int MM = kMaxDepth>
 __device__ inline void update_points(const UpdateCtl& u, float* __restrict__ tau_hist,
                                      const float* __restrict__ res_hist,
                                      const float* __restrict__ w,
                                      const float* __restrict__ tau_ref,
-                                     const float* __restrict__ tau_lo, float* __restrict__ dg_out,
+                                     const float* __restrict__ tau_lo,
+                                     const float* __restrict__ dref, float* __restrict__ dg_out,
                                      size_t N, int nv, int p, size_t n, int kind, int order,
                                      double (*o64)[V], float (*o32)[V]) {
 #pragma unroll
@@ -189,11 +193,10 @@ __device__ inline void update_points(const UpdateCtl& u, float* __restrict__ tau
       for (int v = 0; v < V; ++v) tau[v] = tb[v] + (dt[v] + u.eta * dr[v]);
     }
     stv<V>(tau_hist + (size_t)u.dest * nv * N + gn, tau);
-    float wv[V], tr[V];
-    ldv<V>(w + gn, wv);
-    ldv<V>(tau_ref + gn, tr);
     if (ANCHOR) {
-      float tl[V];
+      float wv[V], tr[V], tl[V];
+      ldv<V>(w + gn, wv);
+      ldv<V>(tau_ref + gn, tr);
       ldv<V>(tau_lo + gn, tl);
 #pragma unroll
       for (int v = 0; v < V; ++v) {
@@ -201,10 +204,11 @@ __device__ inline void update_points(const UpdateCtl& u, float* __restrict__ tau
         o64[s][v] = closure_g(-(double)wv[v] + t, kind, order) - 1.0 - t;
       }
     } else {
-      float dg[V];
+      float dr[V], dg[V];
+      ldv<V>(dref + gn, dr);
 #pragma unroll
       for (int v = 0; v < V; ++v) {
-        dg[v] = closure_dg(-wv[v] + tr[v], tau[v], kind, order);
+        dg[v] = closure_dg(dr[v], tau[v], kind, order);
         o32[s][v] = dg[v] - tau[v];
       }
       stv<V>(dg_out + gn, dg);
@@ -217,8 +221,8 @@ __global__ __launch_bounds__(kElemThreads) void k_update_closure(
     const IterState* __restrict__ st, float* __restrict__ tau_hist,
     const float* __restrict__ res_hist, const float* __restrict__ w,
     const float* __restrict__ tau_ref, const float* __restrict__ tau_lo,
-    float* __restrict__ dg_out, void* __restrict__ spec, size_t N, int nv, int npair, int M,
-    int kind, int order) {
+    const float* __restrict__ dref, float* __restrict__ dg_out, void* __restrict__ spec, size_t N,
+    int nv, int npair, int M, int kind, int order) {
   if (skip_iteration<ANCHOR>(st->done)) return;
   const size_t NQ = N / V;
   const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -228,8 +232,8 @@ __global__ __launch_bounds__(kElemThreads) void k_update_closure(
   const UpdateCtl u = load_update_ctl(st, M);
   double o64[2][V];
   float o32[2][V];
-  update_points<ANCHOR, V>(u, tau_hist, res_hist, w, tau_ref, tau_lo, dg_out, N, nv, p, n, kind,
-                           order, o64, o32);
+  update_points<ANCHOR, V>(u, tau_hist, res_hist, w, tau_ref, tau_lo, dref, dg_out, N, nv, p, n,
+                           kind, order, o64, o32);
   const size_t o = (size_t)p * N + n;
   if (ANCHOR) {
     double2* sp = static_cast<double2*>(spec) + o;
@@ -404,7 +408,7 @@ __device__ inline void residual_points(const float* hre, const float* him, const
                                        float* __restrict__ tau_hist,
                                        float* __restrict__ res_hist, float* __restrict__ tau_ref,
                                        float* __restrict__ tau_lo, float* __restrict__ r_ref,
-                                       const float* __restrict__ dg,
+                                       float* __restrict__ dref, const float* __restrict__ dg,
                                        size_t N, int nv, int p, size_t n, int dest, unsigned mask,
                                        int kind, int order, const GramW& gw, double* acc) {
   for (int s = 0; s < 2; ++s) {
@@ -415,7 +419,7 @@ __device__ inline void residual_points(const float* hre, const float* him, const
     const size_t od = (size_t)dest * nv * N + gn;
     float R[V];
     if (ANCHOR) {
-      float dl[V], tr[V], tl[V], wv[V];
+      float dl[V], tr[V], tl[V], wv[V], dv[V];
       double shift[V];
       ldv<V>(tau_hist + od, dl);
       ldv<V>(tau_ref + gn, tr);
@@ -434,9 +438,12 @@ __device__ inline void residual_points(const float* hre, const float* him, const
         tr[v] = hi;
         tl[v] = lo;
         dl[v] = (float)((double)dl[v] - shift[v]);
+        // the closure argument at the new reference, for the FP32 updates
+        dv[v] = (float)(-(double)wv[v] + ((double)hi + (double)lo));
       }
       stv<V>(tau_ref + gn, tr);
       stv<V>(tau_lo + gn, tl);
+      stv<V>(dref + gn, dv);
       stv<V>(r_ref + gn, R);
       stv<V>(tau_hist + od, dl);
 #pragma unroll
@@ -505,8 +512,9 @@ template <bool ANCHOR, int V>
 __global__ __launch_bounds__(kRedThreads) void k_residual(
     const IterState* __restrict__ st, const void* __restrict__ spec, const float* __restrict__ w,
     float* __restrict__ tau_hist, float* __restrict__ res_hist, float* __restrict__ tau_ref,
-    float* __restrict__ tau_lo, float* __restrict__ r_ref, const float* __restrict__ dg, size_t N,
-    int nv, int npair, int M, int kind, int order, double* __restrict__ partials, GramW gw) {
+    float* __restrict__ tau_lo, float* __restrict__ r_ref, float* __restrict__ dref,
+    const float* __restrict__ dg, size_t N, int nv, int npair, int M, int kind, int order,
+    double* __restrict__ partials, GramW gw) {
   if (skip_iteration<ANCHOR>(st->done)) return;
   __shared__ double red[kRedThreads / 64];
   const int dest = st->dest;
@@ -546,7 +554,8 @@ __global__ __launch_bounds__(kRedThreads) void k_residual(
         him[v] = pk[2 * v + 1];
       }
     }
-    residual_points<ANCHOR, V>(hre, him, h64, w, tau_hist, res_hist, tau_ref, tau_lo, r_ref, dg,
+    residual_points<ANCHOR, V>(hre, him, h64, w, tau_hist, res_hist, tau_ref, tau_lo, r_ref, dref,
+                               dg,
                                N, nv, p, n, dest, mask, kind, order, gw, acc);
   }
   write_partials(acc, M, partials, red);

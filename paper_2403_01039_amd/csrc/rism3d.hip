@@ -214,7 +214,8 @@ struct Layout {
   size_t N, half;
   double dkx, dky, dkz, beta, dv;
   AxisPlan px, py, pz;
-  size_t off_state, off_w, off_phi, off_F, off_tau, off_res, off_tref, off_tlo, off_rref, off_dg,
+  size_t off_state, off_w, off_phi, off_F, off_tau, off_res, off_tref, off_tlo, off_rref, off_dref,
+      off_dg,
       off_spec,
       off_part, off_atoms, off_lj, off_ph, off_chi32, off_chi64, off_q64, off_tw32[3], off_tw64[3],
       off_out, off_hist, total;
@@ -345,6 +346,7 @@ rism3d_status make_layout(const rism3d_problem* pr, const rism3d_opts* op, Layou
   L->off_tref = take(nv * N * sizeof(float));
   L->off_tlo = take(nv * N * sizeof(float));
   L->off_rref = take(nv * N * sizeof(float));
+  L->off_dref = take(nv * N * sizeof(float));
   L->off_dg = take(nv * N * sizeof(float));
   L->off_spec = take((size_t)L->npair * N * sizeof(double2));   // float2 in the bulk iterations
   const size_t part_q = (size_t)((M + 1) > 2 * nv ? (M + 1) : 2 * nv);
@@ -723,8 +725,9 @@ void launch_fused_l(const Layout& L, void* ws, const rism3d_opts* op, bool first
     hipLaunchKernelGGL(update, grid, block, 0, s, st,
                        at<float>(ws, L.off_tau), at<float>(ws, L.off_res), at<float>(ws, L.off_w),
                        at<float>(ws, L.off_tref), at<float>(ws, L.off_tlo),
-                       at<float>(ws, L.off_dg), at<void>(ws, L.off_spec), L.ny, L.nz, L.nv,
-                       L.npair, L.M, kind, order, tw, bt.stride);
+                       at<float>(ws, L.off_dref), at<float>(ws, L.off_dg),
+                       at<void>(ws, L.off_spec), L.ny, L.nz, L.nv, L.npair, L.M, kind, order, tw,
+                       bt.stride);
   } else {
     {
       TIMED(ANCHOR ? F_FFTRES64 : F_FFTRES32, s);
@@ -739,9 +742,9 @@ void launch_fused_l(const Layout& L, void* ws, const rism3d_opts* op, bool first
                          at<void>(ws, L.off_spec), at<float>(ws, L.off_w),
                          at<float>(ws, L.off_tau), at<float>(ws, L.off_res),
                          at<float>(ws, L.off_tref), at<float>(ws, L.off_tlo),
-                         at<float>(ws, L.off_rref), at<float>(ws, L.off_dg), L.ny, L.nz, L.nv,
-                         L.npair, L.M, kind, order, tw, at<double>(ws, L.off_part), L.gw,
-                         bt.stride);
+                         at<float>(ws, L.off_rref), at<float>(ws, L.off_dref),
+                         at<float>(ws, L.off_dg), L.ny, L.nz, L.nv, L.npair, L.M, kind, order, tw,
+                         at<double>(ws, L.off_part), L.gw, bt.stride);
     }
     if (!control) return;
     TIMED(F_CONTROL, s);
@@ -843,8 +846,8 @@ void launch_iteration(const Layout& L, void* ws, const rism3d_opts* op, double i
   const dim3 eg(blocks_for(quads, kElemThreads)), eb(kElemThreads);
 #define RISM_UPDATE_ARGS                                                                    \
   st, at<float>(ws, L.off_tau), at<float>(ws, L.off_res), at<float>(ws, L.off_w),     \
-      at<float>(ws, L.off_tref), at<float>(ws, L.off_tlo), at<float>(ws, L.off_dg),           \
-      at<void>(ws, L.off_spec), L.N, L.nv, L.npair, L.M, kind, order
+      at<float>(ws, L.off_tref), at<float>(ws, L.off_tlo), at<float>(ws, L.off_dref),         \
+      at<float>(ws, L.off_dg), at<void>(ws, L.off_spec), L.N, L.nv, L.npair, L.M, kind, order
   {
     TIMED(anchor ? F_UPDATE64 : F_UPDATE32, s);
     if (anchor && v4) hipLaunchKernelGGL((k_update_closure<true, 4>), eg, eb, 0, s, RISM_UPDATE_ARGS);
@@ -863,7 +866,8 @@ void launch_iteration(const Layout& L, void* ws, const rism3d_opts* op, double i
 #define RISM_RESID_ARGS                                                                       \
   st, at<void>(ws, L.off_spec), at<float>(ws, L.off_w), at<float>(ws, L.off_tau),             \
       at<float>(ws, L.off_res), at<float>(ws, L.off_tref), at<float>(ws, L.off_tlo),          \
-      at<float>(ws, L.off_rref), at<float>(ws, L.off_dg), L.N, L.nv, L.npair, L.M, kind, order,  \
+      at<float>(ws, L.off_rref), at<float>(ws, L.off_dref), at<float>(ws, L.off_dg), L.N, L.nv,  \
+      L.npair, L.M, kind, order,                                                                \
       at<double>(ws, L.off_part), L.gw
   {
     TIMED(anchor ? F_RESIDUAL64 : F_RESIDUAL32, s);
