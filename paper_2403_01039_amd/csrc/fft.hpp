@@ -12,7 +12,7 @@
 // One workgroup owns a tile of whole lines: for the x axis several contiguous
 // rows, for the y and z axes a run of consecutive x columns (so each row of the
 // tile is a coalesced 128 B segment).  The tile is loaded into LDS, transformed
-// by Stockham autosort passes (radix 2/3/4/5/8, ping-pong between two LDS
+// by Stockham autosort passes (radix 2/3/4/5/8/16, ping-pong between two LDS
 // buffers, natural-order output) and written back in place.  The bulk
 // iterations run it on float2; the periodic FP64 anchor evaluations on double2.
 #pragma once
@@ -77,6 +77,37 @@ struct Dft<8, C, S> {
     v[6] = csub(e[2], o2);
     v[3] = cadd(e[3], o3);
     v[7] = csub(e[3], o3);
+  }
+};
+
+// 16 = 2 x 8: the even and odd halves by radix 8, then the twiddles
+// exp(sgn 2 pi i q / 16), q < 8, and the final radix-2 step.
+template <typename C, typename S>
+struct Dft<16, C, S> {
+  __device__ static inline void run(C* v, S sgn) {
+    const S h = S(0.70710678118654752440);    // cos(pi/4) = sin(pi/4)
+    const S c1 = S(0.92387953251128675613);   // cos(pi/8)
+    const S s1 = S(0.38268343236508977173);   // sin(pi/8)
+    C e[8], o[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      e[r] = v[2 * r];
+      o[r] = v[2 * r + 1];
+    }
+    Dft<8, C, S>::run(e, sgn);
+    Dft<8, C, S>::run(o, sgn);
+    o[1] = cmul(o[1], make_c(c1, sgn * s1));
+    o[2] = cmul(o[2], make_c(h, sgn * h));
+    o[3] = cmul(o[3], make_c(s1, sgn * c1));
+    o[4] = cmul_i(o[4], sgn);
+    o[5] = cmul(o[5], make_c(-s1, sgn * c1));
+    o[6] = cmul(o[6], make_c(-h, sgn * h));
+    o[7] = cmul(o[7], make_c(-c1, sgn * s1));
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      v[q] = cadd(e[q], o[q]);
+      v[q + 8] = csub(e[q], o[q]);
+    }
   }
 };
 
@@ -272,6 +303,12 @@ template <> struct FixedPlan<192> { static constexpr int n = 3; static constexpr
 template <> struct FixedPlan<256> { static constexpr int n = 3; static constexpr int r[4] = {8, 8, 4, 1}; };
 template <> struct FixedPlan<512> { static constexpr int n = 3; static constexpr int r[4] = {8, 8, 8, 1}; };
 
+// Plans with a radix-16 first pass (two passes instead of three at 128 and
+// 256 points), for kernels whose tiles hold many lines.
+template <int N> struct WidePlan : FixedPlan<N> {};
+template <> struct WidePlan<128> { static constexpr int n = 2; static constexpr int r[4] = {16, 8, 1, 1}; };
+template <> struct WidePlan<256> { static constexpr int n = 2; static constexpr int r[4] = {16, 16, 1, 1}; };
+
 inline bool fixed_fft_size(int n) {
   return n == 32 || n == 64 || n == 96 || n == 128 || n == 192 || n == 256 || n == 512;
 }
@@ -334,12 +371,12 @@ __device__ inline void pass_inplace(C* buf, int nl, const C* tw2, S sgn) {
   __syncthreads();
 }
 
-template <int P, int NS, int N, int LINES, typename C, typename S>
+template <int P, int NS, int N, int LINES, typename PL = FixedPlan<N>, typename C, typename S>
 __device__ inline void passes_from(C* buf, int nl, const C* tw2, S sgn) {
-  if constexpr (P < FixedPlan<N>::n) {
-    constexpr int R = FixedPlan<N>::r[P];
+  if constexpr (P < PL::n) {
+    constexpr int R = PL::r[P];
     pass_inplace<R, NS, N, LINES>(buf, nl, tw2, sgn);
-    passes_from<P + 1, NS * R, N, LINES>(buf, nl, tw2, sgn);
+    passes_from<P + 1, NS * R, N, LINES, PL>(buf, nl, tw2, sgn);
   }
 }
 
@@ -350,6 +387,8 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_fixed(
     C* __restrict__ data, int nx, int ny, int nz, int npair, const C* __restrict__ tw2_g,
     int forward, const int* __restrict__ done, size_t bstride) {
   using S = typename ScalarOf<C>::type;
+  // y and z tiles hold LINES whole lines: the radix-16 plans
+  using Plan = typename std::conditional<AXIS != 0, WidePlan<N>, FixedPlan<N>>::type;
   constexpr int TILE = LINES * N;
   constexpr int EPT = (TILE + kFftThreads - 1) / kFftThreads;
   done = member_ptr(done, bstride);
@@ -415,7 +454,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_fixed(
         }
       }
       __syncthreads();
-      passes_from<0, 1, N, LINES>(buf, nl, tw2, forward ? S(-1) : S(1));
+      passes_from<0, 1, N, LINES, Plan>(buf, nl, tw2, forward ? S(-1) : S(1));
       for (int f = threadIdx.x; f < H * N; f += kFftThreads) {
         const int i = f / H, h = f - i * H;
         C a = buf[Lds<N>::at(2 * h, i)], b = buf[Lds<N>::at(2 * h + 1, i)];
@@ -453,7 +492,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_fixed(
     }
   }
   __syncthreads();
-  passes_from<0, 1, N, LINES>(buf, nl, tw2, forward ? S(-1) : S(1));
+  passes_from<0, 1, N, LINES, Plan>(buf, nl, tw2, forward ? S(-1) : S(1));
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
     const int f = threadIdx.x + e * kFftThreads;

@@ -105,7 +105,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fftx_residual(
   partials = member_ptr(partials, bstride);
   __shared__ C buf[LINES * Lds<N>::PITCH];
   __shared__ C tw2[2 * N];
-  __shared__ double red[kFftThreads / 64];
+  __shared__ double red[(MM + 1) * (kFftThreads / 64)];
   for (int i = threadIdx.x; i < 2 * N; i += kFftThreads) tw2[i] = tw2_g[i];
   const size_t plane = (size_t)nz * ny;
   const size_t rows = (size_t)npair * plane;
@@ -295,7 +295,7 @@ __global__ __launch_bounds__(kFftThreads) void k_zcz(
   }
   __syncthreads();
   // forward z passes over all 2 P B lines (unused tail lines carry stale data and are not stored)
-  passes_from<0, 1, NZ, LINES>(buf, LINES, tw2, S(-1));
+  passes_from<0, 1, NZ, LINES, WidePlan<NZ>>(buf, LINES, tw2, S(-1));
 
   // contraction: (b, jz) on side 0 with its mirror (b, NZ-1-jz) on side 1
   for (int t = threadIdx.x; t < nb * NZ; t += kFftThreads) {
@@ -332,7 +332,7 @@ __global__ __launch_bounds__(kFftThreads) void k_zcz(
     }
   }
   __syncthreads();
-  passes_from<0, 1, NZ, LINES>(buf, LINES, tw2, S(1));
+  passes_from<0, 1, NZ, LINES, WidePlan<NZ>>(buf, LINES, tw2, S(1));
   if constexpr (kVec) {
    if (vec) {
     for (int f = threadIdx.x; f < 2 * P * H * NZ; f += kFftThreads) {

@@ -175,17 +175,30 @@ __device__ inline void update_points(const UpdateCtl& u, float* __restrict__ tau
       ldv<V>(tau_hist + (size_t)u.newest * nv * N + gn, tb);
 #pragma unroll
       for (int v = 0; v < V; ++v) dt[v] = dr[v] = 0.0f;
+      // the stored pairs in chunks of K slots: every load of a chunk is in
+      // flight before the first is used (the sums keep the slot order)
+      constexpr int K = MM <= 5 ? MM : 4;
 #pragma unroll
-      for (int i = 0; i < MM; ++i) {
-        const float c = u.cf[i];   // zero beyond M and for unused slots
-        if (c != 0.0f) {
-          float ti[V], ri[V];
-          ldv<V>(tau_hist + (size_t)i * nv * N + gn, ti);
-          ldv<V>(res_hist + (size_t)i * nv * N + gn, ri);
+      for (int i0 = 0; i0 < MM; i0 += K) {
+        float ti[K][V], ri[K][V];
 #pragma unroll
-          for (int v = 0; v < V; ++v) {
-            dt[v] += c * (ti[v] - tb[v]);
-            dr[v] += c * ri[v];
+        for (int k = 0; k < K; ++k) {
+          const int i = i0 + k;
+          if (i < MM && u.cf[i] != 0.0f) {   // zero beyond M and for unused slots
+            ldv<V>(tau_hist + (size_t)i * nv * N + gn, ti[k]);
+            ldv<V>(res_hist + (size_t)i * nv * N + gn, ri[k]);
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const int i = i0 + k;
+          const float c = i < MM ? u.cf[i] : 0.0f;
+          if (c != 0.0f) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+              dt[v] += c * (ti[k][v] - tb[v]);
+              dr[v] += c * ri[k][v];
+            }
           }
         }
       }
@@ -468,16 +481,28 @@ __device__ inline void residual_points(const float* hre, const float* him, const
 #pragma unroll
     for (int v = 0; v < V; ++v) rr += (double)R[v] * (double)R[v];
     acc[MM] += rr;                 // unweighted: the RMS
+    // the other stored residuals in chunks of K slots, every load of a chunk
+    // in flight before the first is used
+    constexpr int K = MM <= 5 ? MM : 4;
 #pragma unroll
-    for (int i = 0; i < MM; ++i) {
-      if (i == dest) acc[i] += wg * rr;   // weighted Gram diagonal
-      if (mask & (1u << i)) {
-        float ri[V];
-        ldv<V>(res_hist + (size_t)i * nv * N + gn, ri);
-        double d = 0.0;
+    for (int i0 = 0; i0 < MM; i0 += K) {
+      float ri[K][V];
 #pragma unroll
-        for (int v = 0; v < V; ++v) d += (double)R[v] * (double)ri[v];
-        acc[i] += wg * d;
+      for (int k = 0; k < K; ++k) {
+        const int i = i0 + k;
+        if (i < MM && (mask & (1u << i))) ldv<V>(res_hist + (size_t)i * nv * N + gn, ri[k]);
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int i = i0 + k;
+        if (i >= MM) continue;
+        if (i == dest) acc[i] += wg * rr;   // weighted Gram diagonal
+        if (mask & (1u << i)) {
+          double d = 0.0;
+#pragma unroll
+          for (int v = 0; v < V; ++v) d += (double)R[v] * (double)ri[k][v];
+          acc[i] += wg * d;
+        }
       }
     }
   }
@@ -492,20 +517,32 @@ __device__ inline unsigned other_slots(const IterState* __restrict__ st, int M, 
 
 // Write this block's partial sums (fixed block order, reduced in fixed order).
 // Partials are column-major: quantity i of workgroup b at i * gridDim.x + b,
-// so the control kernel reads each quantity as one contiguous run.
+// so the control kernel reads each quantity as one contiguous run.  Each
+// wavefront reduces every quantity by shuffles (the tree of block_sum); one
+// barrier later thread q adds the wavefronts' sums of quantity q in wavefront
+// order, as block_sum does.  red holds (MM + 1) * (blockDim.x / 64) doubles.
 template <int MM = kMaxDepth>
 __device__ inline void write_partials(const double* acc, int M, double* __restrict__ partials,
                                       double* red) {
   const size_t nb = gridDim.x;
+  const int nw = (int)(blockDim.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int i = 0; i < MM; ++i) {
-    if (i < M) {   // M is uniform: every thread takes the same branches
-      const double s = block_sum(acc[i], red);
-      if (threadIdx.x == 0) partials[i * nb + blockIdx.x] = s;
+  for (int i = 0; i <= MM; ++i) {
+    if (i < M || i == MM) {   // M is uniform: every thread takes the same branches
+      double v = acc[i];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+      if (lane == 0) red[(i < M ? i : M) * nw + wv] = v;
     }
   }
-  const double s = block_sum(acc[MM], red);
-  if (threadIdx.x == 0) partials[(size_t)M * nb + blockIdx.x] = s;
+  __syncthreads();
+  const int q = (int)threadIdx.x;
+  if (q <= M) {
+    double s = 0.0;
+    for (int i = 0; i < nw; ++i) s += red[q * nw + i];
+    partials[(size_t)q * nb + blockIdx.x] = s;
+  }
 }
 
 template <bool ANCHOR, int V>
@@ -516,7 +553,7 @@ __global__ __launch_bounds__(kRedThreads) void k_residual(
     const float* __restrict__ dg, size_t N, int nv, int npair, int M, int kind, int order,
     double* __restrict__ partials, GramW gw) {
   if (skip_iteration<ANCHOR>(st->done)) return;
-  __shared__ double red[kRedThreads / 64];
+  __shared__ double red[(kMaxDepth + 1) * (kRedThreads / 64)];
   const int dest = st->dest;
   const unsigned mask = other_slots(st, M, dest);
   double acc[kMaxDepth + 1];
