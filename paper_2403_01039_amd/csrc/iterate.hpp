@@ -619,26 +619,29 @@ __device__ inline bool anderson_theta(const IterState& st, int s0, int s1, int s
 // The control workgroup: 1024 threads, so the thousands of per-workgroup
 // partial rows of the residual kernels are summed in a few rounds.
 constexpr int kCtlThreads = 1024;
-constexpr int kCtlN = kMaxDepth + 1;   // largest bordered system
 
 struct ControlScratch {
   IterState st;
   double wsum[kCtlThreads / 64][kMaxDepth + 1];
   double sums[kMaxDepth + 1];
-  double A[kCtlN][kCtlN + 1];   // bordered MDIIS system, right-hand side in column n
-  double f[kCtlN];              // elimination factors of one column
   double c[kMaxDepth];
   double rms;
-  double min_piv;
   int slot[kMaxDepth];
   int m;                        // stored pairs
   int mode;                     // what the rest of the step does (kCtl*)
-  int piv;
 };
 
 constexpr int kCtlDone = 0;      // the step ended (finished, verify, or max_iter)
 constexpr int kCtlSolve = 1;     // MDIIS with m > 1: bordered solve, then coefficients
 constexpr int kCtlDirect = 2;    // Anderson, or MDIIS with one pair: coefficients directly
+
+// Lane `lane` (uniform) of a double held by every lane of the wavefront.
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 
 // Orders the shared-memory accesses of the lanes of one wavefront (the lanes
 // run in lockstep; the fences keep the compiler from moving accesses across).
@@ -665,6 +668,7 @@ __device__ __forceinline__ void wave_sync() {
 // pivoting (first row of largest magnitude) in FP64.  A pivot below 1e-12
 // restarts from the stored pair of smallest RMS, and so does a new RMS above
 // 10x the smallest stored one (the new pair is then dropped).
+template <int MM>
 __device__ void control_step(ControlScratch& cs, const double* sums, int M, double inv_count,
                              double tol, int max_iter, float eta_static, int eta_dynamic,
                              int accel, double as1, double as2, int anchor) {
@@ -747,67 +751,86 @@ __device__ void control_step(ControlScratch& cs, const double* sums, int M, doub
   wave_sync();
   bool solved = true;
   if (cs.mode == kCtlSolve) {
+    // The bordered system in registers: lane j holds column j (lane n the
+    // right-hand side); pivots, the pivot column and the solution reach the
+    // other lanes by readlane.  The operations and their order are those of
+    // Gaussian elimination with partial pivoting on the whole array.
+    constexpr int NM = MM + 1;
     const int n = m + 1;
-    {
-      double scale = 0.0;
-      for (int i = 0; i < m; ++i) scale = fmax(scale, st.gram[cs.slot[i]][cs.slot[i]]);
-      for (int e = t; e < n * (n + 1); e += 64) {
-        const int i = e / (n + 1), j = e - i * (n + 1);
-        double a;
-        if (j == n) a = i == m ? -1.0 : 0.0;               // right-hand side
-        else if (i < m && j < m) a = st.gram[cs.slot[i]][cs.slot[j]] / scale;
-        else if (i == m && j == m) a = 0.0;
-        else a = -1.0;                                    // the border
-        cs.A[i][j] = a;
+    double scale = 0.0;
+    for (int i = 0; i < m; ++i) scale = fmax(scale, st.gram[cs.slot[i]][cs.slot[i]]);
+    double a[NM];
+#pragma unroll
+    for (int i = 0; i < NM; ++i) {
+      double v = 0.0;
+      if (i < n && t <= n) {
+        if (t == n) v = i == m ? -1.0 : 0.0;                 // right-hand side
+        else if (i < m && t < m) v = st.gram[cs.slot[i]][cs.slot[t]] / scale;
+        else if (i == m && t == m) v = 0.0;
+        else v = -1.0;                                      // the border
       }
+      a[i] = v;
     }
-    if (t == 0) cs.min_piv = 1.0e300;
-    wave_sync();
-    for (int col = 0; col < n; ++col) {
-      if (t == 0) {   // partial pivoting: the first row of largest magnitude
-        int piv = col;
-        double best = fabs(cs.A[col][col]);
-        for (int r = col + 1; r < n; ++r)
-          if (fabs(cs.A[r][col]) > best) {
-            best = fabs(cs.A[r][col]);
-            piv = r;
+    double min_piv = 1.0e300;
+#pragma unroll
+    for (int col = 0; col < NM; ++col) {
+      if (col < n && solved) {
+        // partial pivoting: the first row of largest magnitude in column col
+        int pl = col;
+        double bl = fabs(a[col]);
+#pragma unroll
+        for (int r = col + 1; r < NM; ++r)
+          if (r < n && fabs(a[r]) > bl) {
+            bl = fabs(a[r]);
+            pl = r;
           }
-        cs.piv = piv;
-        cs.min_piv = fmin(cs.min_piv, best);
+        const int piv = __builtin_amdgcn_readlane(pl, col);
+        min_piv = fmin(min_piv, readlane_d(bl, col));
+        if (piv != col) {
+          double ap = a[col];
+#pragma unroll
+          for (int r = col + 1; r < NM; ++r)
+            if (r == piv) ap = a[r];
+#pragma unroll
+          for (int r = col + 1; r < NM; ++r)
+            if (r == piv) a[r] = a[col];
+          a[col] = ap;
+        }
+        const double pv = readlane_d(a[col], col);
+        if (!(fabs(pv) >= 1.0e-300)) {
+          solved = false;   // uniform: every lane reads the same pivot
+        } else {
+          double f[NM];
+#pragma unroll
+          for (int r = col + 1; r < NM; ++r) f[r] = readlane_d(a[r], col) / pv;
+          const bool upd = t >= col && t <= n;
+#pragma unroll
+          for (int r = col + 1; r < NM; ++r)
+            if (r < n && upd) a[r] -= f[r] * a[col];
+        }
       }
-      wave_sync();
-      const int piv = cs.piv;
-      if (piv != col && t <= n) {
-        const double tmp = cs.A[col][t];
-        cs.A[col][t] = cs.A[piv][t];
-        cs.A[piv][t] = tmp;
-      }
-      wave_sync();
-      const double pv = cs.A[col][col];
-      if (!(fabs(pv) >= 1.0e-300)) {
-        solved = false;
-        break;   // uniform: every thread reads the same pivot
-      }
-      if (t > col && t < n) cs.f[t] = cs.A[t][col] / pv;
-      wave_sync();
-      const int w = n + 1 - col;
-      for (int e = t; e < (n - 1 - col) * w; e += 64) {
-        const int r = col + 1 + e / w, j = col + e % w;
-        cs.A[r][j] -= cs.f[r] * cs.A[col][j];
-      }
-      wave_sync();
     }
-    if (solved && cs.min_piv < 1.0e-12) solved = false;
+    if (solved && min_piv < 1.0e-12) solved = false;
     if (solved) {
       // back substitution, column by column: x_r = b_r / A_rr, then every
       // row above drops its A_ir x_r
-      for (int r = n - 1; r >= 0; --r) {
-        if (t == 0) cs.A[r][n] = cs.A[r][n] / cs.A[r][r];
-        wave_sync();
-        if (t < r) cs.A[t][n] -= cs.A[t][r] * cs.A[r][n];
-        wave_sync();
+#pragma unroll
+      for (int r = NM - 1; r >= 0; --r) {
+        if (r < n) {
+          const double xr = readlane_d(a[r], n) / readlane_d(a[r], r);
+          if (t == n) a[r] = xr;
+#pragma unroll
+          for (int i = 0; i < r; ++i) {
+            const double air = readlane_d(a[i], r);
+            if (t == n) a[i] -= air * xr;
+          }
+        }
       }
-      if (t < m) cs.c[t] = cs.A[t][n];
+      if (t == n) {
+#pragma unroll
+        for (int i = 0; i < NM - 1; ++i)
+          if (i < m) cs.c[i] = a[i];
+      }
     }
     wave_sync();
   }
@@ -923,7 +946,7 @@ __device__ __forceinline__ void control_block(IterState* __restrict__ st_g,
   }
   __syncthreads();
   if (threadIdx.x < 64)
-    control_step(cs, cs.sums, M, inv_count, tol, max_iter, eta_static, eta_dynamic, accel, as1,
+    control_step<MM>(cs, cs.sums, M, inv_count, tol, max_iter, eta_static, eta_dynamic, accel, as1,
                  as2, anchor);
   __syncthreads();
   if (threadIdx.x == 0) {
