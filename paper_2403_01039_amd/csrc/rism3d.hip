@@ -254,7 +254,7 @@ rism3d_status check_prepared(const IterState& host, const Layout& L) {
 // thermodynamic results left in the workspace by launch_sfe: per-site free
 // energies, their total, per-site rho_g \int c_g
 constexpr int kOutDoubles = 2 * kMaxSites + 1;
-constexpr int kDefaultAnchorEvery = 16;
+constexpr int kDefaultAnchorEvery = 32;
 
 rism3d_status make_layout(const rism3d_problem* pr, const rism3d_opts* op, Layout* L) {
   if (!pr || !op) return fail(RISM3D_E_ARG, "null problem or options");

@@ -218,3 +218,28 @@ def test_autotune_keeps_the_prepared_potential(R):
         assert (g - g0).abs().max().item() <= 1e-3 and abs(sfe - s0) <= 1e-4 * abs(s0)
     finally:
         R.tune_reset()
+
+
+def test_reused_workspace_with_another_spacing(R):
+    """The HIP graphs cached for a workspace are keyed on everything their
+    launches hold, the grid spacing (the k-vectors of the contraction)
+    included: a workspace that solved one problem and is then prepared for
+    the same solute on a grid of another spacing (same dimensions, atoms and
+    solvent) solves it exactly as a fresh workspace does."""
+    pa = inputs.small_problem(61, n_atoms=6, shape=(64, 32, 64), radius=3.0)
+    pb = inputs.small_problem(61, n_atoms=6, shape=(64, 32, 64), radius=3.0, spacing=0.55)
+    opts = R.make_opts(pa.options)
+    dpa = R.DeviceProblem(pa, *inputs.solvent_table_for(pa.solvent))
+    dpb = R.DeviceProblem(pb, *inputs.solvent_table_for(pb.solvent))
+    ws = R.alloc_workspace(max(R.rism3d_workspace_bytes(dpa, opts),
+                               R.rism3d_workspace_bytes(dpb, opts)))
+    R.rism3d_potential(dpa, opts, ws)
+    ia = R.rism3d_solve(dpa, opts, ws)
+    R.rism3d_potential(dpb, opts, ws)
+    g1 = torch.empty(dpb.shape, dtype=torch.float32, device="cuda")
+    i1 = R.rism3d_solve(dpb, opts, ws, None, g1)
+    g2, i2, _, _ = _single(R, pb, opts)
+    print(f"  spacing 0.5: it {ia.iterations}; spacing 0.55 reused workspace: it {i1.iterations}, "
+          f"fresh: it {i2.iterations}", flush=True)
+    assert i1.iterations == i2.iterations and i1.rms == i2.rms
+    assert torch.equal(g1, g2)
