@@ -94,91 +94,101 @@ struct ConvArgs {
   float slope;
 };
 
-// One wave computes MT x VT tiles of 16 output channels x 16 voxels (voxels
-// in linear order, so a tile may span rows).  grid.x covers the voxels in
-// steps of 4 * 16 * VT, grid.y the output channels in steps of 16 * MT.
-template <int MT, int VT, int EPI>
+// Epilogue of one accumulator tile: output channels c0 .. c0 + 3 of voxel v.
+template <int EPI>
+__device__ __forceinline__ void conv_store(const ConvArgs& p, int N, size_t v, int c0,
+                                           const f32x4& r) {
+  if (EPI == EPI_BF16_LEAKY) {
+    uint16_t h[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      float val = r[e] + (c0 + e < p.cout ? p.bias[c0 + e] : 0.0f);
+      val = val > 0.0f ? val : p.slope * val;
+      h[e] = f2bf(val);
+    }
+    const u32x2 pk = {(uint32_t)h[0] | ((uint32_t)h[1] << 16),
+                      (uint32_t)h[2] | ((uint32_t)h[3] << 16)};
+    *reinterpret_cast<u32x2*>(p.yb + v * p.cout_pad + c0) = pk;
+  } else if (EPI == EPI_F32_SITE) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (c0 + e < p.cout) p.yf[(size_t)(c0 + e) * N + v] = r[e] + p.bias[c0 + e];
+  } else {
+    *reinterpret_cast<f32x4*>(p.yf + v * p.cout_pad + c0) = r;
+  }
+}
+
+// Convolutions with 8 * CG input channels on a halo-tiled grid: a workgroup
+// computes 16 output channels (tile blockIdx.y) of a 16 x 8 x 4 voxel tile.  It stages the tile's input
+// with a one-voxel halo (18 x 10 x 6 voxels) in LDS, CGC channel groups at a
+// time (CG / CGC chunks), and every tap's operand is read from there instead
+// of from the cache hierarchy.  LDS layout [hz][hy][cg][hx] (16-byte units):
+// the 16 voxels of one operand are consecutive units, conflict-free.  Wave w
+// owns the z-slice z0 + w: its 8 rows y0 .. y0 + 7 of 16 voxels are its 8
+// accumulator tiles.  Within a chunk the K steps take (tap, channel group)
+// pairs in tap-major order, four per matrix instruction: lane group g
+// supplies pair q0 + g (its 8 channels), the weights are the A operand (rows
+// = output channels), the voxels the B operand (columns).
+constexpr int kTileX = 16, kTileY = 8, kTileZ = 4;
+constexpr int kHaloX = kTileX + 2, kHaloY = kTileY + 2, kHaloZ = kTileZ + 2;
+
+template <int EPI, int CGC>
 __global__ __launch_bounds__(kConvThreads) void k_conv3(ConvArgs p) {
+  __shared__ __align__(16) u32x4 halo[kHaloZ * kHaloY * CGC * kHaloX];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j = lane & 15, g = lane >> 4;
   const int N = p.nz * p.ny * p.nx;
-  const int vbase = ((int)blockIdx.x * 4 + wave) * 16 * VT;
-  if (vbase >= N) return;   // no barriers below
-  const int cbase = (int)blockIdx.y * MT * 16;
-  const int cin = p.in.ca + p.in.cb;
-  const int CG = cin >> 3;
-  const int nq = 27 * CG;
-  const float inv_cg = 1.0f / (float)CG;
-  int vz[VT], vy[VT], vx[VT];
-  bool vok[VT];
+  const int CG = (p.in.ca + p.in.cb) >> 3;   // a multiple of CGC
+  const int tiles_x = (p.nx + kTileX - 1) / kTileX, tiles_y = (p.ny + kTileY - 1) / kTileY;
+  int b = (int)blockIdx.x;
+  const int x0 = (b % tiles_x) * kTileX;
+  b /= tiles_x;
+  const int y0 = (b % tiles_y) * kTileY;
+  const int z0 = (b / tiles_y) * kTileZ;
+  const int cbase = (int)blockIdx.y * 16;
+  f32x4 acc[kTileY];
 #pragma unroll
-  for (int t = 0; t < VT; ++t) {
-    const int v = vbase + t * 16 + j;
-    vok[t] = v < N;
-    const int vv = vok[t] ? v : 0;
-    vx[t] = vv % p.nx;
-    vy[t] = (vv / p.nx) % p.ny;
-    vz[t] = vv / (p.nx * p.ny);
-  }
-  f32x4 acc[MT][VT];
-#pragma unroll
-  for (int m = 0; m < MT; ++m)
-#pragma unroll
-    for (int t = 0; t < VT; ++t) acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const size_t wrow = (size_t)27 * cin;
-  for (int q0 = 0; q0 < nq; q0 += 4) {
-    const int q = q0 + g;
-    bf16x8 bx[VT], aw[MT];
-    if (q < nq) {
-      const int tap = (int)(((float)q + 0.5f) * inv_cg);
-      const int cg = q - tap * CG;
-      int dz, dy, dx;
-      tap_offset(tap, dz, dy, dx);
-#pragma unroll
-      for (int t = 0; t < VT; ++t)
-        bx[t] = vok[t] ? load_in(p.in, cg, vz[t] + dz, vy[t] + dy, vx[t] + dx, p.nz, p.ny, p.nx)
-                       : zero8();
-#pragma unroll
-      for (int m = 0; m < MT; ++m) aw[m] = ld8(p.w + (size_t)(cbase + m * 16 + j) * wrow + q * 8);
-    } else {
-#pragma unroll
-      for (int t = 0; t < VT; ++t) bx[t] = zero8();
-#pragma unroll
-      for (int m = 0; m < MT; ++m) aw[m] = zero8();
+  for (int t = 0; t < kTileY; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  constexpr int nq = 27 * CGC;
+  const size_t wrow = (size_t)27 * CG * 8;
+  for (int c0 = 0; c0 < CG; c0 += CGC) {
+    if (c0 > 0) __syncthreads();   // the previous chunk's operands are read
+    // stage: item (h, cg), channel group fastest (consecutive 16-byte reads)
+    for (int it = threadIdx.x; it < kHaloZ * kHaloY * kHaloX * CGC; it += kConvThreads) {
+      const int h = it / CGC, cg = it - h * CGC;
+      const int hx = h % kHaloX, hy = (h / kHaloX) % kHaloY, hz = h / (kHaloX * kHaloY);
+      const bf16x8 v =
+          load_in(p.in, c0 + cg, z0 + hz - 1, y0 + hy - 1, x0 + hx - 1, p.nz, p.ny, p.nx);
+      halo[((hz * kHaloY + hy) * CGC + cg) * kHaloX + hx] = __builtin_bit_cast(u32x4, v);
     }
+    __syncthreads();
+    for (int q0 = 0; q0 < nq; q0 += 4) {
+      const int q = q0 + g;
+      bf16x8 aw = zero8(), bx[kTileY];
+      if (q < nq) {
+        const int tap = q / CGC, cg = q - tap * CGC;
+        int dz, dy, dx;
+        tap_offset(tap, dz, dy, dx);
+        aw = ld8(p.w + (size_t)(cbase + j) * wrow + (size_t)(tap * CG + c0 + cg) * 8);
+        const int base = ((wave + dz + 1) * kHaloY + dy + 1) * CGC + cg;
 #pragma unroll
-    for (int m = 0; m < MT; ++m)
-#pragma unroll
-      for (int t = 0; t < VT; ++t)
-        acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw[m], bx[t], acc[m][t], 0, 0, 0);
-  }
-#pragma unroll
-  for (int m = 0; m < MT; ++m) {
-    const int c0 = cbase + m * 16 + 4 * g;
-#pragma unroll
-    for (int t = 0; t < VT; ++t) {
-      if (!vok[t]) continue;
-      const size_t v = (size_t)vbase + t * 16 + j;
-      const f32x4 r = acc[m][t];
-      if (EPI == EPI_BF16_LEAKY) {
-        uint16_t h[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          float val = r[e] + (c0 + e < p.cout ? p.bias[c0 + e] : 0.0f);
-          val = val > 0.0f ? val : p.slope * val;
-          h[e] = f2bf(val);
-        }
-        const u32x2 pk = {(uint32_t)h[0] | ((uint32_t)h[1] << 16),
-                          (uint32_t)h[2] | ((uint32_t)h[3] << 16)};
-        *reinterpret_cast<u32x2*>(p.yb + v * p.cout_pad + c0) = pk;
-      } else if (EPI == EPI_F32_SITE) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (c0 + e < p.cout) p.yf[(size_t)(c0 + e) * N + v] = r[e] + p.bias[c0 + e];
+        for (int t = 0; t < kTileY; ++t)
+          bx[t] = __builtin_bit_cast(bf16x8, halo[(base + t * CGC) * kHaloX + j + dx + 1]);
       } else {
-        *reinterpret_cast<f32x4*>(p.yf + v * p.cout_pad + c0) = r;
+#pragma unroll
+        for (int t = 0; t < kTileY; ++t) bx[t] = zero8();
       }
+#pragma unroll
+      for (int t = 0; t < kTileY; ++t)
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw, bx[t], acc[t], 0, 0, 0);
     }
+  }
+  const int x = x0 + j, z = z0 + wave;
+#pragma unroll
+  for (int t = 0; t < kTileY; ++t) {
+    const int y = y0 + t;
+    if (x < p.nx && y < p.ny && z < p.nz)
+      conv_store<EPI>(p, N, ((size_t)z * p.ny + y) * p.nx + x, cbase + 4 * g, acc[t]);
   }
 }
 

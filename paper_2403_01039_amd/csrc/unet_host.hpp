@@ -176,22 +176,25 @@ void net_pack(const NetPlan& P, const float* params, void* ws, bool flipped, hip
   }
 }
 
-// One convolution: picks the channel-tile width MT (output channels per wave
-// = 16 MT) that divides cout_pad, and VT = 8 / MT voxel tiles per wave, so
-// every wave holds 8 accumulator tiles (16 measured slower: occupancy 2-3).
-template <int MT, int VT, int EPI>
-void net_conv_mv(const net::ConvArgs& a, size_t N, int tiles, hipStream_t s) {
-  const dim3 grid(net_blocks(N, 4 * 16 * VT), tiles / MT), block(net::kConvThreads);
-  hipLaunchKernelGGL((net::k_conv3<MT, VT, EPI>), grid, block, 0, s, a);
+// One convolution (channel counts are multiples of 8): the halo-tiled
+// kernel, staging CGC <= 4 channel groups (at most 64 KB of LDS) at a time,
+// CGC the largest of 4, 3, 2, 1 that divides the group count.
+template <int EPI, int CGC>
+void net_conv_chunks(const net::ConvArgs& a, hipStream_t s) {
+  const unsigned tiles = (unsigned)((a.nx + net::kTileX - 1) / net::kTileX) *
+                         (unsigned)((a.ny + net::kTileY - 1) / net::kTileY) *
+                         (unsigned)((a.nz + net::kTileZ - 1) / net::kTileZ);
+  hipLaunchKernelGGL((net::k_conv3<EPI, CGC>), dim3(tiles, a.cout_pad / 16),
+                     dim3(net::kConvThreads), 0, s, a);
 }
 
 template <int EPI>
 void net_conv(const net::ConvArgs& a, hipStream_t s) {
-  const size_t N = (size_t)a.nz * a.ny * a.nx;
-  const int tiles = a.cout_pad / 16;
-  if (tiles % 4 == 0) net_conv_mv<4, 2, EPI>(a, N, tiles, s);
-  else if (tiles % 2 == 0) net_conv_mv<2, 4, EPI>(a, N, tiles, s);
-  else net_conv_mv<1, 8, EPI>(a, N, tiles, s);
+  const int cg = (a.in.ca + a.in.cb) / 8;
+  if (cg % 4 == 0) net_conv_chunks<EPI, 4>(a, s);
+  else if (cg % 3 == 0) net_conv_chunks<EPI, 3>(a, s);
+  else if (cg % 2 == 0) net_conv_chunks<EPI, 2>(a, s);
+  else net_conv_chunks<EPI, 1>(a, s);
 }
 
 net::ConvArgs conv_args(const NetPlan& P, const NetLayer& ly, void* ws, net::ConvIn in,
