@@ -27,7 +27,6 @@ typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 constexpr int kConvThreads = 256;   // 4 waves
 constexpr int kWgradChunk = 64;     // voxels per LDS tile of the weight gradient
-constexpr int kWgradPitch = 72;     // LDS row pitch (elements): 144 B, 16-byte aligned rows
 constexpr int kWgradMaxTiles = 16;  // 16x16 output tiles per wave
 
 // FP32 -> BF16 with round-to-nearest-even (NaN stays NaN); BF16 -> FP32 exact.
@@ -195,8 +194,12 @@ __global__ __launch_bounds__(kConvThreads) void k_conv3(ConvArgs p) {
 // Weight gradient of one tap (blockIdx.y): dW[o][tap][i] += sum_v dy[v][o] x[v + off][i]
 // over the voxel chunks of this workgroup; the tiles go through LDS
 // transposed ([channel][voxel]) so each lane reads 8 consecutive voxels of
-// one channel as one 16-byte operand.  Waves share the 16x16 (o, i) tiles
-// round-robin; each workgroup stores its sums in its own slab of the FP32
+// one channel as one 16-byte operand.  With 4 or more 16x16 (o, i) tiles the
+// waves share the tiles round-robin over one chunk at a time (R = 1).  With
+// fewer tiles (R = 4 / tiles: the 16-channel full-resolution layers) R
+// chunks are staged together and wave w multiplies tile w % tiles over chunk
+// w / tiles of them; the R partial sums of a tile are added in chunk order
+// at the end.  Each workgroup stores its sums in its own slab of the FP32
 // partial buffer (every element of the slab, zeros where it saw no voxel),
 // which k_sum_slabs adds up in workgroup order (deterministic).
 struct WgradArgs {
@@ -209,14 +212,24 @@ struct WgradArgs {
   int chunks;           // chunks of kWgradChunk voxels per workgroup
 };
 
+// chunks staged together for a layer with `tiles` 16x16 (o, i) tiles
+__host__ __device__ constexpr int wgrad_group(int tiles) {
+  return tiles == 1 ? 4 : (tiles == 2 ? 2 : 1);
+}
+// LDS row pitch (elements) of R chunks: 16-byte aligned rows
+__host__ __device__ constexpr int wgrad_pitch(int R) { return kWgradChunk * R + 8; }
+
+template <int R>
 __global__ __launch_bounds__(kConvThreads) void k_conv3_wgrad(WgradArgs p) {
   extern __shared__ __align__(16) uint16_t smem[];
+  constexpr int PITCH = wgrad_pitch(R);
+  constexpr int CH = kWgradChunk * R;   // voxels staged at once
   const int cin = p.in.ca + p.in.cb;
   const int cit = (cin + 15) >> 4;          // input-channel tiles (x tile rows padded to 16)
   const int cot = p.cout_pad >> 4;
   const int ntiles = cot * cit;
-  uint16_t* dyT = smem;                                   // [cout_pad][pitch]
-  uint16_t* xT = smem + (size_t)p.cout_pad * kWgradPitch;  // [cit * 16][pitch]
+  uint16_t* dyT = smem;                             // [cout_pad][PITCH]
+  uint16_t* xT = smem + (size_t)p.cout_pad * PITCH;  // [cit * 16][PITCH]
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j = lane & 15, g = lane >> 4;
   const int tap = blockIdx.y;
@@ -228,67 +241,95 @@ __global__ __launch_bounds__(kConvThreads) void k_conv3_wgrad(WgradArgs p) {
   for (int k = 0; k < kWgradMaxTiles; ++k) acc[k] = f32x4{0.f, 0.f, 0.f, 0.f};
   // zero the padding rows of the x tile once (channels cin .. cit*16)
   for (int r = cin + (threadIdx.x >> 6); r < cit * 16; r += 4)
-    for (int c = lane; c < kWgradPitch; c += 64) xT[(size_t)r * kWgradPitch + c] = 0;
+    for (int c = lane; c < PITCH; c += 64) xT[(size_t)r * PITCH + c] = 0;
   const int cgo = p.cout_pad >> 3, cgi = cin >> 3;
-  for (int ch = 0; ch < p.chunks; ++ch) {
+  const int vend = ((int)blockIdx.x + 1) * p.chunks * kWgradChunk;   // this workgroup's range
+  for (int ch = 0; ch < p.chunks; ch += R) {
     const int v0 = ((int)blockIdx.x * p.chunks + ch) * kWgradChunk;
     if (v0 >= N) break;
     __syncthreads();
-    for (int it = threadIdx.x; it < kWgradChunk * cgo; it += kConvThreads) {
+    for (int it = threadIdx.x; it < CH * cgo; it += kConvThreads) {
       const int vv = it / cgo, cg = it - vv * cgo;
       const int v = v0 + vv;
       bf16x8 val = zero8();
-      if (v < N) val = ld8(p.dy + (size_t)v * p.cout_pad + cg * 8);
+      if (v < N && v < vend) val = ld8(p.dy + (size_t)v * p.cout_pad + cg * 8);
       const u32x4 w4 = __builtin_bit_cast(u32x4, val);
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        dyT[(size_t)(cg * 8 + 2 * e) * kWgradPitch + vv] = (uint16_t)(w4[e] & 0xffffu);
-        dyT[(size_t)(cg * 8 + 2 * e + 1) * kWgradPitch + vv] = (uint16_t)(w4[e] >> 16);
+        dyT[(size_t)(cg * 8 + 2 * e) * PITCH + vv] = (uint16_t)(w4[e] & 0xffffu);
+        dyT[(size_t)(cg * 8 + 2 * e + 1) * PITCH + vv] = (uint16_t)(w4[e] >> 16);
       }
     }
-    for (int it = threadIdx.x; it < kWgradChunk * cgi; it += kConvThreads) {
+    for (int it = threadIdx.x; it < CH * cgi; it += kConvThreads) {
       const int vv = it / cgi, cg = it - vv * cgi;
       const int v = v0 + vv;
       bf16x8 val = zero8();
-      if (v < N) {
+      if (v < N && v < vend) {
         const int x = v % p.nx, y = (v / p.nx) % p.ny, z = v / (p.nx * p.ny);
         val = load_in(p.in, cg, z + dz, y + dy, x + dx, p.nz, p.ny, p.nx);
       }
       const u32x4 w4 = __builtin_bit_cast(u32x4, val);
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        xT[(size_t)(cg * 8 + 2 * e) * kWgradPitch + vv] = (uint16_t)(w4[e] & 0xffffu);
-        xT[(size_t)(cg * 8 + 2 * e + 1) * kWgradPitch + vv] = (uint16_t)(w4[e] >> 16);
+        xT[(size_t)(cg * 8 + 2 * e) * PITCH + vv] = (uint16_t)(w4[e] & 0xffffu);
+        xT[(size_t)(cg * 8 + 2 * e + 1) * PITCH + vv] = (uint16_t)(w4[e] >> 16);
       }
     }
     __syncthreads();
+    if constexpr (R == 1) {
 #pragma unroll
-    for (int k = 0; k < kWgradMaxTiles; ++k) {
-      const int t = wave + 4 * k;
-      if (t < ntiles) {
-        const int to = t / cit, ti = t - to * cit;
+      for (int k = 0; k < kWgradMaxTiles; ++k) {
+        const int t = wave + 4 * k;
+        if (t < ntiles) {
+          const int to = t / cit, ti = t - to * cit;
 #pragma unroll
-        for (int kk = 0; kk < kWgradChunk; kk += 32) {
-          const bf16x8 a = ld8(dyT + (size_t)(to * 16 + j) * kWgradPitch + kk + 8 * g);
-          const bf16x8 b = ld8(xT + (size_t)(ti * 16 + j) * kWgradPitch + kk + 8 * g);
-          acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[k], 0, 0, 0);
+          for (int kk = 0; kk < kWgradChunk; kk += 32) {
+            const bf16x8 a = ld8(dyT + (size_t)(to * 16 + j) * PITCH + kk + 8 * g);
+            const bf16x8 b = ld8(xT + (size_t)(ti * 16 + j) * PITCH + kk + 8 * g);
+            acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[k], 0, 0, 0);
+          }
         }
+      }
+    } else {
+      // ntiles * R == 4: wave w takes tile w % ntiles over chunk w / ntiles
+      const int t = wave % ntiles, sub = wave / ntiles;
+      const int to = t / cit, ti = t - to * cit;
+#pragma unroll
+      for (int kk = 0; kk < kWgradChunk; kk += 32) {
+        const int k0 = sub * kWgradChunk + kk + 8 * g;
+        const bf16x8 a = ld8(dyT + (size_t)(to * 16 + j) * PITCH + k0);
+        const bf16x8 b = ld8(xT + (size_t)(ti * 16 + j) * PITCH + k0);
+        acc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[0], 0, 0, 0);
       }
     }
   }
+  float* slab = p.dw + (size_t)blockIdx.x * p.cout * 27 * p.cin_real;
+  auto store_tile = [&](int t, const f32x4& r) {
+    const int to = t / cit, ti = t - to * cit;
+    const int i = ti * 16 + j;
 #pragma unroll
-  for (int k = 0; k < kWgradMaxTiles; ++k) {
-    const int t = wave + 4 * k;
-    if (t < ntiles) {
-      const int to = t / cit, ti = t - to * cit;
-      const int i = ti * 16 + j;
-      float* slab = p.dw + (size_t)blockIdx.x * p.cout * 27 * p.cin_real;
+    for (int e = 0; e < 4; ++e) {
+      const int o = to * 16 + 4 * g + e;
+      if (o < p.cout && i < p.cin_real) slab[((size_t)o * 27 + tap) * p.cin_real + i] = r[e];
+    }
+  };
+  if constexpr (R == 1) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int o = to * 16 + 4 * g + e;
-        if (o < p.cout && i < p.cin_real)
-          slab[((size_t)o * 27 + tap) * p.cin_real + i] = acc[k][e];
-      }
+    for (int k = 0; k < kWgradMaxTiles; ++k) {
+      const int t = wave + 4 * k;
+      if (t < ntiles) store_tile(t, acc[k]);
+    }
+  } else {
+    // the R partial sums of each tile, added in chunk order
+    __syncthreads();   // the last chunk's tiles are read; smem is reused
+    f32x4* part = reinterpret_cast<f32x4*>(smem);   // [wave][lane]
+    part[wave * 64 + lane] = acc[0];
+    __syncthreads();
+    const int t = wave % ntiles, sub = wave / ntiles;
+    if (sub == 0) {
+      f32x4 r = acc[0];
+      for (int q = 1; q < R; ++q) r += part[(q * ntiles + t) * 64 + lane];
+      store_tile(t, r);
     }
   }
 }
