@@ -194,12 +194,11 @@ __global__ __launch_bounds__(kConvThreads) void k_conv3(ConvArgs p) {
 // Weight gradient of one tap (blockIdx.y): dW[o][tap][i] += sum_v dy[v][o] x[v + off][i]
 // over the voxel chunks of this workgroup; the tiles go through LDS
 // transposed ([channel][voxel]) so each lane reads 8 consecutive voxels of
-// one channel as one 16-byte operand.  With 4 or more 16x16 (o, i) tiles the
-// waves share the tiles round-robin over one chunk at a time (R = 1).  With
-// fewer tiles (R = 4 / tiles: the 16-channel full-resolution layers) R
-// chunks are staged together and wave w multiplies tile w % tiles over chunk
-// w / tiles of them; the R partial sums of a tile are added in chunk order
-// at the end.  Each workgroup stores its sums in its own slab of the FP32
+// one channel as one 16-byte operand.  With more than 4 16x16 (o, i) tiles
+// the waves share the tiles round-robin over one chunk at a time (R = 1).
+// With at most 4 tiles (the full-resolution layers) R = 4 chunks are staged
+// together and wave w multiplies every tile over chunk w of them; the four
+// partial sums of a tile are added in chunk order at the end.  Each workgroup stores its sums in its own slab of the FP32
 // partial buffer (every element of the slab, zeros where it saw no voxel),
 // which k_sum_slabs adds up in workgroup order (deterministic).
 struct WgradArgs {
@@ -213,9 +212,7 @@ struct WgradArgs {
 };
 
 // chunks staged together for a layer with `tiles` 16x16 (o, i) tiles
-__host__ __device__ constexpr int wgrad_group(int tiles) {
-  return tiles == 1 ? 4 : (tiles == 2 ? 2 : 1);
-}
+__host__ __device__ constexpr int wgrad_group(int tiles) { return tiles <= 4 ? 4 : 1; }
 // LDS row pitch (elements) of R chunks: 16-byte aligned rows
 __host__ __device__ constexpr int wgrad_pitch(int R) { return kWgradChunk * R + 8; }
 
@@ -291,15 +288,19 @@ __global__ __launch_bounds__(kConvThreads) void k_conv3_wgrad(WgradArgs p) {
         }
       }
     } else {
-      // ntiles * R == 4: wave w takes tile w % ntiles over chunk w / ntiles
-      const int t = wave % ntiles, sub = wave / ntiles;
-      const int to = t / cit, ti = t - to * cit;
+      // ntiles <= 4: wave w takes every tile over chunk w
 #pragma unroll
-      for (int kk = 0; kk < kWgradChunk; kk += 32) {
-        const int k0 = sub * kWgradChunk + kk + 8 * g;
-        const bf16x8 a = ld8(dyT + (size_t)(to * 16 + j) * PITCH + k0);
-        const bf16x8 b = ld8(xT + (size_t)(ti * 16 + j) * PITCH + k0);
-        acc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[0], 0, 0, 0);
+      for (int k = 0; k < 4; ++k) {
+        if (k < ntiles) {
+          const int to = k / cit, ti = k - to * cit;
+#pragma unroll
+          for (int kk = 0; kk < kWgradChunk; kk += 32) {
+            const int k0 = wave * kWgradChunk + kk + 8 * g;
+            const bf16x8 a = ld8(dyT + (size_t)(to * 16 + j) * PITCH + k0);
+            const bf16x8 b = ld8(xT + (size_t)(ti * 16 + j) * PITCH + k0);
+            acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[k], 0, 0, 0);
+          }
+        }
       }
     }
   }
@@ -320,16 +321,18 @@ __global__ __launch_bounds__(kConvThreads) void k_conv3_wgrad(WgradArgs p) {
       if (t < ntiles) store_tile(t, acc[k]);
     }
   } else {
-    // the R partial sums of each tile, added in chunk order
+    // the four partial sums of each tile, added in chunk order: wave t < ntiles
+    // stores tile t
     __syncthreads();   // the last chunk's tiles are read; smem is reused
-    f32x4* part = reinterpret_cast<f32x4*>(smem);   // [wave][lane]
-    part[wave * 64 + lane] = acc[0];
+    f32x4* part = reinterpret_cast<f32x4*>(smem);   // [wave][tile][lane]
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (k < ntiles) part[(wave * 4 + k) * 64 + lane] = acc[k];
     __syncthreads();
-    const int t = wave % ntiles, sub = wave / ntiles;
-    if (sub == 0) {
-      f32x4 r = acc[0];
-      for (int q = 1; q < R; ++q) r += part[(q * ntiles + t) * 64 + lane];
-      store_tile(t, r);
+    if (wave < ntiles) {
+      f32x4 r = part[wave * 64 + lane];
+      for (int q = 1; q < 4; ++q) r += part[(q * 4 + wave) * 64 + lane];
+      store_tile(wave, r);
     }
   }
 }
@@ -362,8 +365,17 @@ __global__ void k_sum_slabs(const float* __restrict__ part, int n_slab, size_t n
                             float* __restrict__ dst) {
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
+  // 16 slabs' loads in flight at a time; the additions keep slab order
   float t = 0.0f;
-  for (int b = 0; b < n_slab; ++b) t += part[(size_t)b * n + e];
+  int b = 0;
+  for (; b + 16 <= n_slab; b += 16) {
+    float v[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = part[(size_t)(b + k) * n + e];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) t += v[k];
+  }
+  for (; b < n_slab; ++b) t += part[(size_t)b * n + e];
   dst[e] += t;
 }
 

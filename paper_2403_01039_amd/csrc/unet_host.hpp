@@ -318,7 +318,6 @@ void net_conv_dw(const NetPlan& P, const NetLayer& ly, const net::ConvIn& in, vo
   const size_t lds = ((size_t)ly.cout_pad + (size_t)cit * 16) * net::wgrad_pitch(R) * 2;
   const dim3 grid((unsigned)nbx, 27), block(net::kConvThreads);
   if (R == 4) hipLaunchKernelGGL(net::k_conv3_wgrad<4>, grid, block, lds, s, w);
-  else if (R == 2) hipLaunchKernelGGL(net::k_conv3_wgrad<2>, grid, block, lds, s, w);
   else hipLaunchKernelGGL(net::k_conv3_wgrad<1>, grid, block, lds, s, w);
   const size_t nw = (size_t)ly.cout * 27 * ly.cin;
   hipLaunchKernelGGL(net::k_sum_slabs, dim3(net_blocks(nw, 256)), dim3(256), 0, s, slabs,
