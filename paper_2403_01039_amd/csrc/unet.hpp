@@ -216,6 +216,26 @@ __host__ __device__ constexpr int wgrad_group(int tiles) { return tiles <= 4 ? 4
 // LDS row pitch (elements) of R chunks: 16-byte aligned rows
 __host__ __device__ constexpr int wgrad_pitch(int R) { return kWgradChunk * R + 8; }
 
+// Stage CH voxels x (8 ngroups) channels, read channels last by load(voxel,
+// group), into dst[channel][voxel] (row pitch `pitch` elements, even): each
+// thread takes two neighbouring voxels of one channel group and stores, per
+// channel, their two 2-byte elements as one 4-byte word.
+template <typename Load>
+__device__ __forceinline__ void stage_pairs(uint16_t* dst, int pitch, int CH, int ngroups,
+                                            Load load) {
+  for (int it = threadIdx.x; it < (CH / 2) * ngroups; it += kConvThreads) {
+    const int vp = it / ngroups, cg = it - vp * ngroups;
+    const u32x4 a = __builtin_bit_cast(u32x4, load(2 * vp, cg));
+    const u32x4 b = __builtin_bit_cast(u32x4, load(2 * vp + 1, cg));
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      uint32_t* row = reinterpret_cast<uint32_t*>(dst + (size_t)(cg * 8 + 2 * e) * pitch + 2 * vp);
+      row[0] = (a[e] & 0xffffu) | (b[e] << 16);                              // channel 2e
+      row[pitch / 2] = (a[e] >> 16) | (b[e] & 0xffff0000u);                  // channel 2e + 1
+    }
+  }
+}
+
 template <int R>
 __global__ __launch_bounds__(kConvThreads) void k_conv3_wgrad(WgradArgs p) {
   extern __shared__ __align__(16) uint16_t smem[];
@@ -245,33 +265,19 @@ __global__ __launch_bounds__(kConvThreads) void k_conv3_wgrad(WgradArgs p) {
     const int v0 = ((int)blockIdx.x * p.chunks + ch) * kWgradChunk;
     if (v0 >= N) break;
     __syncthreads();
-    for (int it = threadIdx.x; it < CH * cgo; it += kConvThreads) {
-      const int vv = it / cgo, cg = it - vv * cgo;
+    stage_pairs(dyT, PITCH, CH, cgo, [&](int vv, int cg) {
       const int v = v0 + vv;
-      bf16x8 val = zero8();
-      if (v < N && v < vend) val = ld8(p.dy + (size_t)v * p.cout_pad + cg * 8);
-      const u32x4 w4 = __builtin_bit_cast(u32x4, val);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        dyT[(size_t)(cg * 8 + 2 * e) * PITCH + vv] = (uint16_t)(w4[e] & 0xffffu);
-        dyT[(size_t)(cg * 8 + 2 * e + 1) * PITCH + vv] = (uint16_t)(w4[e] >> 16);
-      }
-    }
-    for (int it = threadIdx.x; it < CH * cgi; it += kConvThreads) {
-      const int vv = it / cgi, cg = it - vv * cgi;
+      return v < N && v < vend ? ld8(p.dy + (size_t)v * p.cout_pad + cg * 8) : zero8();
+    });
+    stage_pairs(xT, PITCH, CH, cgi, [&](int vv, int cg) {
       const int v = v0 + vv;
       bf16x8 val = zero8();
       if (v < N && v < vend) {
         const int x = v % p.nx, y = (v / p.nx) % p.ny, z = v / (p.nx * p.ny);
         val = load_in(p.in, cg, z + dz, y + dy, x + dx, p.nz, p.ny, p.nx);
       }
-      const u32x4 w4 = __builtin_bit_cast(u32x4, val);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        xT[(size_t)(cg * 8 + 2 * e) * PITCH + vv] = (uint16_t)(w4[e] & 0xffffu);
-        xT[(size_t)(cg * 8 + 2 * e + 1) * PITCH + vv] = (uint16_t)(w4[e] >> 16);
-      }
-    }
+      return val;
+    });
     __syncthreads();
     if constexpr (R == 1) {
 #pragma unroll
