@@ -105,7 +105,7 @@ typedef struct {
  * check_every (host polls the device convergence flag every this many
  * iterations; 0 picks a default), anchor_every (every this many iterations the
  * residual is evaluated exactly in FP64 and the FP32 iterations in between
- * transform only the increment from that anchor; 0 picks a default),
+ * transform only the increment from that anchor; 0 picks the default, 32),
  * accelerator (RISM3D_MDIIS, or RISM3D_ANDERSON: the modified Anderson method
  * with two histories of section "Convergence acceleration", Eq 34-39: Picard
  * for the first two steps, then theta from Eq 36 in the inner product of
