@@ -118,21 +118,23 @@ __device__ __forceinline__ void conv_store(const ConvArgs& p, int N, size_t v, i
 }
 
 // Convolutions with 8 * CG input channels on a halo-tiled grid: a workgroup
-// computes 16 output channels (tile blockIdx.y) of a 16 x 8 x 4 voxel tile.  It stages the tile's input
-// with a one-voxel halo (18 x 10 x 6 voxels) in LDS, CGC channel groups at a
+// computes 16 output channels (tile blockIdx.y) of a 16 x TY x 4 voxel tile
+// (TY = 8; 2 on small grids, for more workgroups).  It stages the tile's input
+// with a one-voxel halo (18 x (TY + 2) x 6 voxels) in LDS, CGC channel groups at a
 // time (CG / CGC chunks), and every tap's operand is read from there instead
 // of from the cache hierarchy.  LDS layout [hz][hy][cg][hx] (16-byte units):
 // the 16 voxels of one operand are consecutive units, conflict-free.  Wave w
-// owns the z-slice z0 + w: its 8 rows y0 .. y0 + 7 of 16 voxels are its 8
-// accumulator tiles.  Within a chunk the K steps take (tap, channel group)
+// owns the z-slice z0 + w: its TY rows y0 .. y0 + TY - 1 of 16 voxels are its
+// TY accumulator tiles.  Within a chunk the K steps take (tap, channel group)
 // pairs in tap-major order, four per matrix instruction: lane group g
 // supplies pair q0 + g (its 8 channels), the weights are the A operand (rows
 // = output channels), the voxels the B operand (columns).
-constexpr int kTileX = 16, kTileY = 8, kTileZ = 4;
-constexpr int kHaloX = kTileX + 2, kHaloY = kTileY + 2, kHaloZ = kTileZ + 2;
+constexpr int kTileX = 16, kTileZ = 4;
+constexpr int kHaloX = kTileX + 2, kHaloZ = kTileZ + 2;
 
-template <int EPI, int CGC>
+template <int EPI, int CGC, int TY>
 __global__ __launch_bounds__(kConvThreads) void k_conv3(ConvArgs p) {
+  constexpr int kTileY = TY, kHaloY = TY + 2;
   __shared__ __align__(16) u32x4 halo[kHaloZ * kHaloY * CGC * kHaloX];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j = lane & 15, g = lane >> 4;

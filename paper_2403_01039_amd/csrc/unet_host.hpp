@@ -178,14 +178,23 @@ void net_pack(const NetPlan& P, const float* params, void* ws, bool flipped, hip
 
 // One convolution (channel counts are multiples of 8): the halo-tiled
 // kernel, staging CGC <= 4 channel groups (at most 64 KB of LDS) at a time,
-// CGC the largest of 4, 3, 2, 1 that divides the group count.
+// CGC the largest of 4, 3, 2, 1 that divides the group count.  Tiles of
+// 16 x 8 x 4 voxels, or 16 x 2 x 4 where those would give fewer than 512
+// workgroups (the coarse levels).
+template <int EPI, int CGC, int TY>
+void net_conv_tiles(const net::ConvArgs& a, unsigned tiles, hipStream_t s) {
+  hipLaunchKernelGGL((net::k_conv3<EPI, CGC, TY>), dim3(tiles, a.cout_pad / 16),
+                     dim3(net::kConvThreads), 0, s, a);
+}
+
 template <int EPI, int CGC>
 void net_conv_chunks(const net::ConvArgs& a, hipStream_t s) {
-  const unsigned tiles = (unsigned)((a.nx + net::kTileX - 1) / net::kTileX) *
-                         (unsigned)((a.ny + net::kTileY - 1) / net::kTileY) *
-                         (unsigned)((a.nz + net::kTileZ - 1) / net::kTileZ);
-  hipLaunchKernelGGL((net::k_conv3<EPI, CGC>), dim3(tiles, a.cout_pad / 16),
-                     dim3(net::kConvThreads), 0, s, a);
+  auto tiles = [&](int ty) {
+    return (unsigned)((a.nx + net::kTileX - 1) / net::kTileX) * (unsigned)((a.ny + ty - 1) / ty) *
+           (unsigned)((a.nz + net::kTileZ - 1) / net::kTileZ);
+  };
+  if (tiles(8) * (unsigned)(a.cout_pad / 16) >= 512) net_conv_tiles<EPI, CGC, 8>(a, tiles(8), s);
+  else net_conv_tiles<EPI, CGC, 2>(a, tiles(2), s);
 }
 
 template <int EPI>
